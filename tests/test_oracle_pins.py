@@ -1,0 +1,535 @@
+"""Pins for the CPU oracle: every check here is fixed by the paper or by
+mathematics, never by the oracle itself (brute-force enumeration, published
+generator outputs, closed forms, networkx, hand-derived fixtures, invariants
+of the method)."""
+import itertools
+
+import networkx as nx
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
+
+import graphgen as gg
+import oracle
+from helpers import (all_min_sides, brute_mincut, cut_value, edges_of, load_golden, random_graph,
+                     side_from_words)
+
+GOLDEN = ["strict_pr.txt", "cycle6_w3.txt", "k5_unit.txt", "barbell.txt", "weighted_path4.txt",
+          "two_triangles_disconnected.txt"]
+M64 = (1 << 64) - 1
+
+
+# --------------------------------------------------------------- mixers ----
+def py_splitmix64(seed, i):
+    """SplitMix64 as published (Steele, Lea, Flood 2014; Vigna's splitmix64.c)."""
+    state = seed & M64
+    z = 0
+    for _ in range(i):
+        state = (state + 0x9E3779B97F4A7C15) & M64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        z = z ^ (z >> 31)
+    return z
+
+
+def py_fmix32(h):
+    """MurmurHash3 fmix32 as published (Appleby)."""
+    h &= 0xFFFFFFFF
+    h ^= h >> 16
+    h = (h * 0x85EBCA6B) & 0xFFFFFFFF
+    h ^= h >> 13
+    h = (h * 0xC2B2AE35) & 0xFFFFFFFF
+    h ^= h >> 16
+    return h
+
+
+def py_fmix32_inverse(h):
+    def unxorshift(x, s):
+        y = x
+        for _ in range(32 // s + 1):
+            y = x ^ (y >> s)
+        return y & 0xFFFFFFFF
+    h = unxorshift(h, 16)
+    h = (h * pow(0xC2B2AE35, -1, 1 << 32)) & 0xFFFFFFFF
+    h = unxorshift(h, 13)
+    h = (h * pow(0x85EBCA6B, -1, 1 << 32)) & 0xFFFFFFFF
+    return unxorshift(h, 16)
+
+
+def test_splitmix64_published_first_output():
+    # the first output of SplitMix64 started at state 0 is 0xE220A8397B1DCDAF
+    assert oracle.splitmix64_output(0, 1) == 0xE220A8397B1DCDAF
+    assert py_splitmix64(0, 1) == 0xE220A8397B1DCDAF
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2**63 + 7, M64])
+def test_splitmix64_matches_definition(seed):
+    for i in [1, 2, 3, 4, 7, 64, 129]:
+        assert oracle.splitmix64_output(seed, i) == py_splitmix64(seed, i)
+
+
+def test_fmix32_definition_and_bijection():
+    rng = np.random.default_rng(0)
+    xs = [0, 1, 2, 0xFFFFFFFF, 0x80000000] + [int(v) for v in rng.integers(0, 2**32, 500)]
+    assert py_fmix32(0) == 0
+    for x in xs:
+        h = oracle.fmix32(x)
+        assert h == py_fmix32(x)
+        assert py_fmix32_inverse(h) == x  # a bijection: distinct labels never tie on prio
+
+
+def test_prio_is_fmix_of_label_xor_low_seed_word():
+    for s in [0, 0xDEADBEEFCAFEBABE, py_splitmix64(0, 3)]:
+        for x in [0, 1, 5, 1 << 20, 2**31 - 1]:
+            assert oracle.prio(s, x) == py_fmix32(x ^ (s & 0xFFFFFFFF))
+
+
+# --------------------------------------------------------- Stoer-Wagner ----
+@pytest.mark.parametrize("name", GOLDEN)
+def test_sw_golden(name):
+    g, facts = load_golden(name)
+    val, side = oracle.stoer_wagner(g.row_ptr, g.col, g.w)
+    assert val == facts["lambda"]
+    assert 0 < side.sum() < g.n
+    assert cut_value(g, side) == val
+    if "side" in facts:
+        want = np.zeros(g.n, bool)
+        want[facts["side"]] = True
+        assert np.array_equal(side, want) or np.array_equal(side, ~want)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_sw_vs_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 13))
+    g = random_graph(n, float(rng.uniform(0.2, 0.9)), int(rng.choice([1, 3, 20])), seed,
+                     connected=bool(seed % 5))
+    lam, _ = brute_mincut(g)
+    val, side = oracle.stoer_wagner(g.row_ptr, g.col, g.w)
+    assert val == lam
+    assert 0 < side.sum() < g.n
+    assert cut_value(g, side) == val
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sw_vs_networkx(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(20, 70))
+    g = random_graph(n, float(rng.uniform(0.05, 0.3)), 50, 100 + seed)
+    u, v, w = edges_of(g.row_ptr, g.col, g.w)
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_weighted_edges_from(zip(u.tolist(), v.tolist(), w.tolist()))
+    ref, _ = nx.stoer_wagner(G)
+    val, side = oracle.stoer_wagner(g.row_ptr, g.col, g.w)
+    assert val == ref
+    assert cut_value(g, side) == val
+
+
+@pytest.mark.parametrize("n,w", [(3, 1), (6, 3), (17, 5), (40, 2)])
+def test_sw_cycle_closed_form(n, w):
+    g = gg.from_edges(n, [(i, (i + 1) % n) for i in range(n)], [w] * n)
+    assert oracle.stoer_wagner(g.row_ptr, g.col, g.w)[0] == 2 * w
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 9, 16])
+def test_sw_clique_closed_form(n):
+    g = gg.from_edges(n, list(itertools.combinations(range(n), 2)))
+    assert oracle.stoer_wagner(g.row_ptr, g.col, g.w)[0] == n - 1
+
+
+# ------------------------------------------------------------ the method ----
+def check_result(g, r, lam=None):
+    """Properties every result must have: the side is non-trivial, excludes
+    vertex 0, and its recomputed capacity equals the returned value; the value
+    lies between lambda and the minimum degree (Section 2, Section 4)."""
+    side = side_from_words(r.side, g.n)
+    assert not side[0]
+    assert 0 < side.sum() < g.n
+    assert cut_value(g, side) == r.cut
+    assert r.cut <= int(g.degrees().min())
+    if lam is not None:
+        assert r.cut >= lam
+    # padding bits of the last word are zero
+    bits = np.unpackbits(r.side.view(np.uint8), bitorder="little")
+    assert not bits[g.n:].any()
+
+
+@pytest.mark.parametrize("name", GOLDEN)
+@pytest.mark.parametrize("lp", [0, 1, 2, 3])
+@pytest.mark.parametrize("n0", [1, 3, 100])
+def test_method_golden(name, lp, n0):
+    g, facts = load_golden(name)
+    r = oracle.mincut_graph(g, lp_iters=lp, n0=n0, seed=lp * 7 + n0)
+    check_result(g, r, facts["lambda"])
+    assert int(g.degrees().min()) == facts["delta"]
+    if lp == 0 or facts["lambda"] in (0, facts["delta"]):
+        assert r.cut == facts["lambda"]
+
+
+def test_strict_pr_keeps_the_minimum_cut():
+    """The fixture where non-strict PR condition 2 would contract every
+    minimum cut away: with the strict reading the method stays exact."""
+    g, facts = load_golden("strict_pr.txt")
+    r = oracle.mincut_graph(g, lp_iters=0, n0=1, trace=True)
+    assert r.cut == 2
+    pr = [e for e in r.events if e["kind"] == oracle.EV_PR][0]
+    # the two weight-2 edges at vertex 8 (4 = c(8) = 2 c(8,x) is not < ) stay unmarked
+    marks = {(u, int(g.col[i])) for u in range(g.n) for i in range(g.row_ptr[u], g.row_ptr[u + 1]) if pr["mark"][i]}
+    assert (8, 0) not in marks and (8, 4) not in marks
+    # every block edge has weight 5 >= lambda-hat = 4: condition 1 marks it
+    assert (0, 1) in marks and (6, 7) in marks
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_pr_only_is_exact(seed):
+    """With no label propagation every contraction is a Padberg-Rinaldi one,
+    which keeps a minimum cut (or lambda-hat already equals lambda): the
+    result must equal the brute-force minimum cut."""
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(3, 15))
+    g = random_graph(n, float(rng.uniform(0.15, 0.8)), int(rng.choice([1, 2, 5, 30])), 1000 + seed,
+                     connected=bool(seed % 7))
+    lam, _ = brute_mincut(g)
+    r = oracle.mincut_graph(g, lp_iters=0, n0=1)
+    assert r.cut == lam
+    check_result(g, r, lam)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_sandwich_bound(seed):
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(3, 15))
+    g = random_graph(n, float(rng.uniform(0.15, 0.8)), int(rng.choice([1, 3, 10])), 2000 + seed)
+    lam, _ = brute_mincut(g)
+    for lp in (1, 2, 4):
+        r = oracle.mincut_graph(g, lp_iters=lp, n0=int(rng.integers(1, 4)), seed=seed)
+        check_result(g, r, lam)
+
+
+@pytest.mark.parametrize("n,w", [(3, 2), (8, 1), (25, 3), (200, 7), (1001, 2)])
+@pytest.mark.parametrize("lp,seed", [(1, 0), (2, 0), (2, 5), (3, 11)])
+def test_cycle_exact_for_every_seed(n, w, lp, seed):
+    # lambda <= result <= delta and lambda = delta = 2w pin the cycle exactly
+    g = gg.from_edges(n, [(i, (i + 1) % n) for i in range(n)], [w] * n)
+    r = oracle.mincut_graph(g, lp_iters=lp, n0=1, seed=seed)
+    assert r.cut == 2 * w
+    check_result(g, r)
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 12, 40])
+def test_clique_exact(n):
+    g = gg.from_edges(n, list(itertools.combinations(range(n), 2)))
+    r = oracle.mincut_graph(g, lp_iters=2, n0=1)
+    assert r.cut == n - 1
+    check_result(g, r)
+
+
+def test_isolated_vertex_gives_zero():
+    g = gg.from_edges(5, [(0, 1), (1, 2), (2, 3)])  # vertex 4 isolated
+    r = oracle.mincut_graph(g, n0=1)
+    assert r.cut == 0 and r.status & oracle.ST_DISCONNECTED
+    side = side_from_words(r.side, 5)
+    assert side.tolist() == [False, False, False, False, True]
+
+
+@pytest.mark.parametrize("lp", [0, 2])
+def test_disconnected_gives_zero(lp):
+    g, _ = load_golden("two_triangles_disconnected.txt")
+    r = oracle.mincut_graph(g, lp_iters=lp, n0=1)
+    assert r.cut == 0
+    check_result(g, r, 0)
+
+
+def test_errors():
+    ok = gg.from_edges(3, [(0, 1), (1, 2)])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.mincut(np.array([0, 0]), np.zeros(0), np.zeros(0))
+    assert e.value.code == -1
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.mincut(ok.row_ptr, ok.col, np.where(np.arange(ok.nnz) == 1, 0, ok.w))
+    assert e.value.code == -2
+    w = ok.w.copy()
+    w[0] = 2  # w(0,1) != w(1,0)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.mincut(ok.row_ptr, ok.col, w)
+    assert e.value.code == -6
+    big = gg.from_edges(3, [(0, 1), (1, 2)], [2**31 - 1, 5])
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.mincut(big.row_ptr, big.col, big.w)
+    assert e.value.code == -3
+
+
+# -------------------------------------------------- trace-level invariants ----
+def _csr_of(ev):
+    return gg.Graph(ev["row_ptr"], ev["col"], ev["w"])
+
+
+def _check_coarse(prev, labels, ev):
+    """Cluster contraction (Section 4.1): one vertex per block, numbered by
+    ascending label; coarse weight = summed inter-block weight."""
+    uniq = np.unique(labels)
+    assert ev["n"] == uniq.size
+    assert np.array_equal(ev["cl"], np.searchsorted(uniq, labels))
+    h = _csr_of(ev)
+    rp, col, w = h.row_ptr, h.col, h.w
+    rows = np.repeat(np.arange(h.n), np.diff(rp))
+    assert not np.any(rows == col)  # no self loops
+    for v in range(h.n):  # strictly increasing rows
+        assert np.all(np.diff(col[rp[v]:rp[v + 1]]) > 0)
+    A = sp.csr_matrix((w.astype(np.int64), col, rp), shape=(h.n, h.n))
+    assert (A != A.T).nnz == 0  # symmetric
+    # recompute from the fine graph
+    cl = ev["cl"]
+    u, v, wt = edges_of(prev.row_ptr, prev.col, prev.w)
+    cu, cv = cl[u], cl[v]
+    x = cu != cv
+    B = sp.coo_matrix((np.concatenate([wt[x], wt[x]]), (np.concatenate([cu[x], cv[x]]),
+                                                        np.concatenate([cv[x], cu[x]]))),
+                      shape=(h.n, h.n)).tocsr()
+    assert (A != B).nnz == 0
+    assert np.array_equal(ev["deg"], np.asarray(A.sum(axis=1)).ravel())
+
+
+def _check_lp_step(g, prev_labels, labels, s=None):
+    """Each new label is a neighbour's previous label (or the vertex's own),
+    and it maximises the connection weight S (Section 4.1). With the
+    iteration's seed word ``s`` also check the stated tie rule: keep the own
+    label when it attains the maximum, else the smallest (prio, label)."""
+    for v in range(g.n):
+        nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+        wt = g.w[g.row_ptr[v]:g.row_ptr[v + 1]].astype(np.int64)
+        if nb.size == 0:
+            assert labels[v] == prev_labels[v]
+            continue
+        S = {}
+        for u, c in zip(nb, wt):
+            S[prev_labels[u]] = S.get(prev_labels[u], 0) + int(c)
+        best = max(S.values())
+        assert labels[v] in S or labels[v] == prev_labels[v]
+        assert S.get(labels[v], 0) == best
+        if s is not None:
+            if S.get(prev_labels[v], 0) == best:
+                assert labels[v] == prev_labels[v]
+            else:
+                want = min((py_fmix32(int(x) ^ (s & 0xFFFFFFFF)), int(x)) for x, val in S.items() if val == best)[1]
+                assert labels[v] == want
+
+
+def test_trace_invariants_random_graphs():
+    for seed in range(25):
+        rng = np.random.default_rng(3000 + seed)
+        n = int(rng.integers(20, 120))
+        g = random_graph(n, float(rng.uniform(0.03, 0.3)), int(rng.choice([1, 5, 40])), 3000 + seed)
+        lp = int(rng.integers(1, 4))
+        r = oracle.mincut_graph(g, lp_iters=lp, n0=int(rng.integers(1, 8)), seed=seed, trace=True)
+        check_result(g, r)
+        cur = g
+        labels = np.arange(g.n)
+        lam_prev = None
+        pending_rep = None
+        for ev in r.events:
+            k = ev["kind"]
+            if k == oracle.EV_LP:
+                if ev["iter"] == 1:
+                    labels = np.arange(cur.n)
+                _check_lp_step(cur, labels, ev["labels"], py_splitmix64(seed, ev["round"] * lp + ev["iter"]))
+                if ev["iter"] == 1:
+                    # the own label scores 0 in the first iteration: every vertex with a neighbour moves
+                    deg_arcs = np.diff(cur.row_ptr)
+                    assert np.all(ev["labels"][deg_arcs > 0] != np.arange(cur.n)[deg_arcs > 0])
+                labels = ev["labels"]
+            elif k == oracle.EV_UF:
+                pending_rep = ev["rep"]
+            elif k == oracle.EV_PR:
+                # condition 1 alone already forces a mark on every edge with c >= lambda-hat
+                assert np.all(ev["mark"][cur.w >= ev["lam_hat"]] == 1)
+                # marks are symmetric
+                A = sp.csr_matrix((ev["mark"], cur.col, cur.row_ptr), shape=(cur.n, cur.n))
+                assert (A != A.T).nnz == 0
+                mk = ev["mark"]
+            elif k == oracle.EV_CONTRACT:
+                part = pending_rep if pending_rep is not None else labels
+                if pending_rep is not None:
+                    # representatives = smallest id of each marked-edge component
+                    A = sp.csr_matrix((mk, cur.col, cur.row_ptr), shape=(cur.n, cur.n), copy=True)
+                    A.eliminate_zeros()
+                    nc, comp = connected_components(A, directed=False)
+                    mins = np.full(nc, cur.n)
+                    np.minimum.at(mins, comp, np.arange(cur.n))
+                    assert np.array_equal(pending_rep, mins[comp])
+                _check_coarse(cur, part, ev)
+                cur = _csr_of(ev)
+                pending_rep = None
+            elif k == oracle.EV_BOUND:
+                if lam_prev is not None:
+                    assert ev["lam_hat"] <= lam_prev
+                lam_prev = ev["lam_hat"]
+
+
+def test_bound_witness_is_a_cut_of_that_value():
+    g = gg.planted(300, 10.0, 3, 1, 9, seed=5)
+    r = oracle.mincut_graph(g, lp_iters=2, n0=1, trace=True)
+    bounds = [e for e in r.events if e["kind"] == oracle.EV_BOUND]
+    assert bounds[0]["lam_hat"] == int(g.degrees().min())
+    assert bounds[0]["witness_vertex"] == int(np.argmin(g.degrees()))
+    check_result(g, r)
+
+
+@pytest.mark.parametrize("a", [3, 4, 5, 8, 11])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 17])
+def test_lp_clique_single_cluster(a, seed):
+    g = gg.from_edges(a, list(itertools.combinations(range(a), 2)))
+    r = oracle.mincut_graph(g, lp_iters=2, n0=1, seed=seed, trace=True)
+    lp2 = [e for e in r.events if e["kind"] == oracle.EV_LP and e["iter"] == 2][0]
+    assert np.unique(lp2["labels"]).size == 1
+
+
+@pytest.mark.parametrize("a", [6, 8, 12])
+@pytest.mark.parametrize("bw", [1, 2])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_lp_two_cliques_with_bridge(a, bw, seed):
+    e = list(itertools.combinations(range(a), 2)) + [(a + i, a + j) for i, j in itertools.combinations(range(a), 2)]
+    e.append((a - 1, a))
+    g = gg.from_edges(2 * a, e, [1] * (len(e) - 1) + [bw])
+    r = oracle.mincut_graph(g, lp_iters=2, n0=1, seed=seed, trace=True)
+    lp2 = [ev for ev in r.events if ev["kind"] == oracle.EV_LP and ev["iter"] == 2][0]["labels"]
+    assert np.unique(lp2[:a]).size == 1 and np.unique(lp2[a:]).size == 1 and lp2[0] != lp2[-1]
+    assert r.cut == bw
+
+
+def test_lemma1_cluster_contraction_respecting_a_min_cut():
+    """Lemma 1: if every cluster lies on one side of some minimum cut and more
+    than one cluster remains, the contracted graph has the same lambda."""
+    hits = 0
+    for seed in range(40):
+        rng = np.random.default_rng(4000 + seed)
+        n = int(rng.integers(6, 13))
+        g = random_graph(n, float(rng.uniform(0.2, 0.7)), 6, 4000 + seed)
+        lam, sides = all_min_sides(g)
+        r = oracle.mincut_graph(g, lp_iters=2, n0=1, seed=seed, trace=True)
+        contracts = [e for e in r.events if e["kind"] == oracle.EV_CONTRACT]
+        if not contracts or contracts[0]["n"] < 2:
+            continue
+        cl = contracts[0]["cl"]
+        respects = False
+        for m in sides:
+            s = np.array([(m >> i) & 1 for i in range(n)])
+            if all(np.unique(s[cl == c]).size == 1 for c in range(contracts[0]["n"])):
+                respects = True
+        h = _csr_of(contracts[0])
+        lam_c, _ = brute_mincut(h)
+        assert lam_c >= lam  # contraction never creates cuts
+        if respects:
+            hits += 1
+            assert lam_c == lam
+    assert hits >= 5
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_planted_c1_small_seeds(seed):
+    g = gg.c1_planted(seed)
+    r = oracle.mincut_graph(g, lp_iters=2, n0=64, seed=0)
+    check_result(g, r)
+    lam, _ = oracle.stoer_wagner(g.row_ptr, g.col, g.w)
+    assert lam == min(5, int(g.degrees().min()))
+    assert r.cut >= lam
+
+
+def test_pr_condition3_and_4_hand_cases():
+    """Hand-built edges that only condition 3 (resp. 4) of the
+    Padberg-Rinaldi lemma marks, with lambda-hat = delta."""
+    # Condition 3: v=0, w=1, c(0,1)=2, common neighbour u=2 with c(0,2)=c(1,2)=2,
+    # plus pendant weight to raise degrees: c(0)=2+2+3=7 < 2(2+2)=8 and likewise c(1);
+    # condition 2 fails (7 >= 4), condition 1 fails (2 < delta), condition 4: 2+2=4 < delta.
+    e = [(0, 1, 2), (0, 2, 2), (1, 2, 2), (0, 3, 3), (1, 4, 3), (3, 4, 9), (2, 3, 9), (2, 4, 9)]
+    g = gg.from_edges(5, [(a, b) for a, b, _ in e], [c for _, _, c in e])
+    deg = g.degrees()
+    assert deg.min() == 7
+    r = oracle.mincut_graph(g, lp_iters=0, n0=1, trace=True)
+    pr = [x for x in r.events if x["kind"] == oracle.EV_PR][0]
+    i01 = [i for i in range(g.row_ptr[0], g.row_ptr[1]) if g.col[i] == 1][0]
+    assert pr["mark"][i01] == 1
+    # Condition 4: c(v,w) + sum of min over common neighbours >= lambda-hat.
+    # K4 on {0,1,2,3} with unit weights plus heavy pendants so delta stays 3 at vertex 4.
+    e = list(itertools.combinations(range(4), 2))
+    e = [(a, b, 1) for a, b in e] + [(0, 4, 1), (1, 4, 1), (2, 4, 1), (3, 5, 50), (4, 5, 50)]
+    g = gg.from_edges(6, [(a, b) for a, b, _ in e], [c for _, _, c in e])
+    r = oracle.mincut_graph(g, lp_iters=0, n0=1, trace=True)
+    pr = [x for x in r.events if x["kind"] == oracle.EV_PR][0]
+    lam_hat = pr["lam_hat"]
+    # edge (0,1): c = 1, common neighbours 2, 3(?), 4 -> 1 + min(1,1)*3 = 4 >= lambda-hat
+    i01 = [i for i in range(g.row_ptr[0], g.row_ptr[1]) if g.col[i] == 1][0]
+    assert lam_hat <= 4
+    assert pr["mark"][i01] == 1
+
+
+def test_repeat_runs_identical():
+    g = gg.planted(2000, 12.0, 7, 1, 50, seed=9)
+    a = oracle.mincut_graph(g, n0=16, seed=3, trace=True)
+    b = oracle.mincut_graph(g, n0=16, seed=3, trace=True)
+    assert a.cut == b.cut and np.array_equal(a.side, b.side)
+    la = [e["labels"] for e in a.events if e["kind"] == oracle.EV_LP]
+    lb = [e["labels"] for e in b.events if e["kind"] == oracle.EV_LP]
+    assert all(np.array_equal(x, y) for x, y in zip(la, lb))
+
+
+@pytest.mark.parametrize("a", [3, 6, 10])
+@pytest.mark.parametrize("seed", [0, 7])
+def test_lp_first_iteration_on_a_clique_by_hand(a, seed):
+    """Unit clique, iteration 1: all S values tie at 1, so every vertex takes
+    the neighbour of smallest prio; with m1 < m2 the two smallest prio
+    vertices, every vertex but m1 takes m1 and m1 takes m2."""
+    g = gg.from_edges(a, list(itertools.combinations(range(a), 2)))
+    r = oracle.mincut_graph(g, lp_iters=2, n0=1, seed=seed, trace=True)
+    s = py_splitmix64(seed, 1)
+    order = sorted(range(a), key=lambda x: (py_fmix32(x ^ (s & 0xFFFFFFFF)), x))
+    m1, m2 = order[0], order[1]
+    lp1 = [e for e in r.events if e["kind"] == oracle.EV_LP and e["iter"] == 1][0]["labels"]
+    want = np.full(a, m1)
+    want[m1] = m2
+    assert np.array_equal(lp1, want)
+
+
+def test_pr_condition3_asymmetric_hand_case():
+    """Condition 3 pairs c(v) with c(v,w)+c(v,u) and c(w) with c(v,w)+c(w,u).
+    Two hand-built graphs around the edge v=0, w=1 with common neighbour u=2."""
+    def pr_mark_01(e):
+        g = gg.from_edges(6, [(a, b) for a, b, _ in e], [c for _, _, c in e])
+        r = oracle.mincut_graph(g, lp_iters=0, n0=1, trace=True)
+        pr = [x for x in r.events if x["kind"] == oracle.EV_PR][0]
+        i01 = [i for i in range(g.row_ptr[0], g.row_ptr[1]) if g.col[i] == 1][0]
+        return g.degrees(), pr["lam_hat"], int(pr["mark"][i01])
+    rest = [(3, 4, 9), (2, 3, 9), (2, 4, 9), (3, 5, 9), (4, 5, 9), (2, 5, 9)]
+    # c(0,1)=2, c(0,2)=4, c(1,2)=1, c(0)=11 < 2(2+4)=12, c(1)=5 < 2(2+1)=6: marked.
+    # (condition 2: 11, 5 >= 4; condition 4: 2+min(4,1) = 3 < lambda-hat = 5)
+    deg, lam, mark = pr_mark_01([(0, 1, 2), (0, 2, 4), (1, 2, 1), (0, 3, 5), (1, 4, 2)] + rest)
+    assert (deg[0], deg[1], lam, mark) == (11, 5, 5, 1)
+    # same, but c(1) = 7: 7 < 6 fails (pairing c(1) with c(0,2) would give 7 < 12).
+    # condition 2: 11, 7 >= 4; condition 4: 3 < lambda-hat = 7: not marked.
+    deg, lam, mark = pr_mark_01([(0, 1, 2), (0, 2, 4), (1, 2, 1), (0, 3, 5), (1, 4, 4)] + rest)
+    assert (deg[0], deg[1], lam, mark) == (11, 7, 7, 0)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_lp_tie_rule_over_several_rounds(seed):
+    """Sparse graphs that need several rounds: every LP iteration of every
+    round follows the stated rule with seed word number r*l + t."""
+    rng = np.random.default_rng(seed)
+    n = 300
+    e = [(i, (i + 1) % n) for i in range(n)] + [(int(a), int(b)) for a, b in rng.integers(0, n, (40, 2)) if a != b]
+    g = gg.from_edges(n, e, rng.integers(1, 4, len(e)))
+    for lp in (1, 2, 3):
+        r = oracle.mincut_graph(g, lp_iters=lp, n0=1, seed=seed, trace=True)
+        assert r.rounds >= 2
+        cur, prev = g, None
+        for ev in r.events:
+            if ev["kind"] == oracle.EV_LP:
+                prev = np.arange(cur.n) if ev["iter"] == 1 else prev
+                _check_lp_step(cur, prev, ev["labels"], py_splitmix64(seed, ev["round"] * lp + ev["iter"]))
+                prev = ev["labels"]
+            elif ev["kind"] == oracle.EV_CONTRACT:
+                cur = _csr_of(ev)
+        check_result(g, r)

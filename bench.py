@@ -1,0 +1,117 @@
+"""Benchmark: input edges/s of the whole min-cut path on one MI355X.
+
+A step is one full solve (validation, label propagation, cluster
+contraction, Padberg-Rinaldi contraction, bound tracking, exact solve on the
+remaining graph, transfer of the side) of one graph already resident in HBM,
+with a preallocated workspace. Default workload: the random hyperbolic graph
+with n = 2^20, average degree 32, power-law exponent 5, unit weights
+(seed 1), n0 = 10,000, two LP iterations, tie-break seed 0.
+
+Prints one JSON line. The CPU baseline times the oracle (the plain C++
+implementation used by the tests) on the same graph on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "rhg2p20": dict(desc="random hyperbolic graph n=2^20 avg deg 32 gamma 5 unit weights seed 1", n0=10000),
+    "rmat22core": dict(desc="R-MAT scale 22 ef 16 (0.57/0.19/0.19) 10-core LCC seed 2", n0=10000),
+    "planted2000": dict(desc="planted cut n=2000 d=32 5 cross edges unit weights seed 0", n0=64),
+}
+
+
+def make_graph(name):
+    import graphgen as gg
+    if name == "rhg2p20":
+        return gg.c2_rhg()
+    if name == "rmat22core":
+        return gg.c3_rmat()
+    if name == "planted2000":
+        return gg.c1_planted(0)
+    raise SystemExit("unknown workload " + name)
+
+
+def cpu_baseline(g, n0, budget_s=20.0):
+    """Time the oracle on the same graph (the whole method, generation and
+    I/O excluded), repeating while within the time budget."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        oracle.mincut_graph(g, lp_iters=2, n0=n0, seed=0)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start + times[-1] > budget_s or len(times) >= 5:
+            break
+    med = sorted(times)[len(times) // 2]
+    return {"value": g.m / med, "unit": "input edges/s", "cores": threads, "kind": "oracle",
+            "sample": "%d full solve(s) of the same graph, median %.3f s" % (len(times), med)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rhg2p20", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on one GPU only: the graphs are solved on a single device "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1708_06127_amd as vc
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = make_graph(args.workload)
+    print("# generated %s: n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    dev = [torch.from_numpy(np.ascontiguousarray(a, np.int32)).cuda() for a in (g.row_ptr, g.col, g.w)]
+    ws = vc.workspace(g.n, g.nnz)
+    side = torch.empty((g.n + 63) // 64, dtype=torch.int64, device="cuda")
+    kw = dict(lp_iters=2, n0=wl["n0"], seed=0, ws=ws, side=side)
+    for _ in range(args.warmup):
+        cut, _, info = vc.mincut(*dev, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cut, _, info = vc.mincut(*dev, **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {
+        "metric": "input edges/s to min cut (single graph, device-resident)",
+        "value": g.m / dt,
+        "unit": "input edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": g.n, "m": g.m, "n0": wl["n0"], "lp_iters": 2,
+                   "cut": cut, "rounds": info["rounds"], "kernel_n": info["kernel_n"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, wl["n0"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

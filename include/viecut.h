@@ -1,0 +1,208 @@
+/*
+ * viecut.h - C ABI of the MI355X (gfx950) inexact minimum-cut library.
+ *
+ * The library computes a cut of an undirected graph with positive integer
+ * edge weights, G = (V, E, c), following the method of Henzinger, Noe,
+ * Schulz and Strash, "Practical Minimum Cut Algorithms" (arXiv 1708.06127):
+ * rounds of label-propagation clustering and cluster contraction
+ * (Section 4.1), Padberg-Rinaldi contraction tests applied through a
+ * union-find (Lemma "Padberg-Rinaldi", Section 4.1), a running upper bound
+ * equal to the minimum weighted degree (Section 4, introduction), an exact
+ * solve on the small remaining graph and a transfer of its cut back to the
+ * input (Algorithm 1, appendix A).
+ *
+ * What is returned follows the problem statement (Section 2): a cut
+ * (A, V \ A) with both sides non-empty and its capacity c(A) = the summed
+ * weight of the edges between A and V \ A. The value is never below the
+ * minimum cut lambda(G) (contraction only removes cuts) and never above the
+ * minimum weighted degree delta(G); it is not guaranteed to equal lambda(G)
+ * (the method is a heuristic).
+ *
+ * Determinism: label propagation is synchronous (every vertex reads the
+ * previous iteration's labels) with a seeded, hash-based tie-break, so the
+ * result (value and side) is a pure function of (graph, params). It does not
+ * depend on thread timing, launch configuration or batch composition.
+ *
+ * Arithmetic: int32 weights, sums in int64 (or in uint32 where the sum is
+ * bounded by the total weight, which is checked to be <= INT32_MAX).
+ *
+ * All graph pointers are DEVICE pointers unless stated otherwise. A stream
+ * argument is a hipStream_t passed as void* (NULL = the default stream).
+ * No function throws; every function that can fail returns a status code
+ * (VIECUT_OK = 0 or a negative VIECUT_E* value). On error no output is
+ * written and the library stays usable.
+ */
+#ifndef VIECUT_H
+#define VIECUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+  VIECUT_OK = 0,
+  VIECUT_EINVAL = -1,    /* bad argument: n < 2, bad row_ptr, column out of range or a self loop, bad params */
+  VIECUT_EWEIGHT = -2,   /* an edge weight < 1 */
+  VIECUT_EOVERFLOW = -3, /* total weight (sum over edges) > INT32_MAX, or nnz >= 2^31 */
+  VIECUT_ENOMEM = -4,    /* workspace too small, or device allocation failed */
+  VIECUT_EDEVICE = -5,   /* a HIP runtime call failed */
+  VIECUT_ENOTSYM = -6,   /* (with VIECUT_F_VALIDATE) not symmetric, or a row not strictly increasing */
+  VIECUT_EBUDGET = -7    /* (sessions) a request larger than the whole memory budget */
+};
+
+/* status_bits of a result */
+enum {
+  VIECUT_ST_COLLAPSED = 1,    /* a contraction left one vertex: the result is the upper bound */
+  VIECUT_ST_DISCONNECTED = 2, /* a vertex of degree 0 was found: the minimum cut is 0 */
+  VIECUT_ST_NO_PROGRESS = 4,  /* a round did not shrink the graph; the exact solve ran on what remained */
+  VIECUT_ST_MAX_ROUNDS = 8    /* max_rounds reached before the graph got to n0 vertices */
+};
+
+/* params.flags */
+enum {
+  VIECUT_F_VALIDATE = 1 /* check symmetry (w(u,v) == w(v,u)) and strictly increasing rows (O(nnz log d)) */
+};
+
+/* Input graph: a symmetric CSR. Row v lists the neighbours of v.
+ * Layout: row_ptr[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
+ * col[nnz] (0 <= col < n, no self loops, strictly increasing within a row),
+ * w[nnz] (w >= 1, w(u,v) == w(v,u), total weight sum(w)/2 <= INT32_MAX).
+ * nnz = 2|E| arcs. The arrays are owned by the caller, read-only, and must
+ * stay valid until the call returns (or, for sessions, until the request is
+ * reported done). */
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const int32_t *w;
+} viecut_csr;
+
+/* Method parameters (Section 4.1 / Algorithm 1):
+ *   lp_iters   - label-propagation iterations per round (the paper's l; 2). 0 disables clustering.
+ *   n0         - bound for the exact solve: rounds run while more than n0 vertices remain (10000).
+ *   max_rounds - safety cap on rounds (64).
+ *   flags      - VIECUT_F_* bits.
+ *   seed       - seed of the tie-break priorities (0). */
+typedef struct {
+  int32_t lp_iters;
+  int32_t n0;
+  int32_t max_rounds;
+  uint32_t flags;
+  uint64_t seed;
+} viecut_params;
+
+/* Result of one solve.
+ *   cut           - capacity of the returned cut
+ *   rounds        - rounds started
+ *   kernel_n      - vertices of the graph the loop stopped at
+ *   witness_level - contraction level whose minimum-degree vertex gave the cut, or -1 when the
+ *                   exact solve on the remaining graph gave it
+ *   status_bits   - VIECUT_ST_* bits
+ *   levels        - contractions performed
+ *   t_ms          - host-measured phase times: [0] validate+first LP iteration, [1] remaining LP
+ *                   iterations, [2] cluster contraction, [3] PR marking+union-find+contraction,
+ *                   [4] exact solve + transfer, [5] total; [6],[7] unused. */
+typedef struct {
+  int64_t cut;
+  int32_t rounds;
+  int32_t kernel_n;
+  int32_t witness_level;
+  uint32_t status_bits;
+  int32_t levels;
+  int32_t reserved;
+  float t_ms[8];
+} viecut_result;
+
+/* Fills *p with the defaults above (lp_iters 2, n0 10000, max_rounds 64, flags 0, seed 0). */
+void viecut_default_params(viecut_params *p);
+
+/* Device workspace (bytes) that viecut_mincut needs for a graph of n vertices
+ * and nnz arcs. Returns 0 for invalid sizes. */
+size_t viecut_workspace_bytes(int32_t n, int32_t nnz, const viecut_params *p);
+
+/* Solves one graph. ws: device workspace of at least viecut_workspace_bytes()
+ * bytes (NULL: the library allocates and frees it inside the call). side:
+ * device array of ceil(n/64) uint64 words; on success bit (u & 63) of word
+ * (u >> 6) is 1 iff vertex u is on the side NOT containing vertex 0 (padding
+ * bits 0). out: host struct. The call returns when the result is final
+ * (the exact solve runs on the host). One call at a time per workspace. */
+int viecut_mincut(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
+                  viecut_result *out, uint64_t *side);
+
+/* Trace record for viecut_mincut_trace. Array pointers are HOST copies valid
+ * only during the callback.
+ *   kind 1 (LP):       a = labels[n] after iteration `iter` of round `round`
+ *   kind 2 (CONTRACT): a = row_ptr[n+1], b = col[nnz], c = w[nnz], d = deg[n] of the new graph at
+ *                      `level`, e = cl[n_prev] (old vertex -> new vertex). Rows are sorted.
+ *   kind 3 (BOUND):    lam_hat, witness_vertex, witness_level after the update at `level`
+ *   kind 4 (PR):       a = mark[nnz] on the graph at `level`: 1 on the arc (v, x), v < x, of
+ *                      every marked edge, 0 elsewhere
+ *   kind 5 (UF):       a = rep[n], the smallest vertex id of each marked-edge component */
+typedef struct {
+  int32_t kind, round, iter, level;
+  int32_t n, n_prev;
+  int64_t nnz;
+  int64_t lam_hat;
+  int32_t witness_vertex, witness_level;
+  const int32_t *a, *b, *c;
+  const int64_t *d;
+  const int32_t *e;
+} viecut_event;
+typedef void (*viecut_trace_fn)(void *user, const viecut_event *ev);
+
+/* viecut_mincut with a host callback receiving every intermediate state
+ * (for parity checking and debugging; it synchronises and copies at every
+ * step, so it is slow). */
+int viecut_mincut_trace(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
+                        viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user);
+
+/* Checks g on the device (row_ptr, column range, self loops, weights, total
+ * weight; with VIECUT_F_VALIDATE in flags also symmetry and sorted rows)
+ * without solving. Returns VIECUT_OK or the error code viecut_mincut would. */
+int viecut_validate(const viecut_csr *g, uint32_t flags, void *stream);
+
+/* ------------------------------------------------------------ batching */
+/* Workspace for solving `count` graphs together. */
+size_t viecut_batch_workspace_bytes(const viecut_csr *gs, int32_t count, const viecut_params *p);
+
+/* Solves `count` independent graphs in one batched execution (all graphs
+ * advance round by round together; each graph's arithmetic and result are
+ * identical to viecut_mincut on it alone). gs: host array of descriptors
+ * (device pointers inside). outs: host array of count results. sides: host
+ * array of count device pointers (ceil(n_i/64) words each). Returns
+ * VIECUT_OK, or the first error; per-graph input errors are reported in
+ * outs[i].status_bits as 0x80000000 | (-code) and do not stop the others. */
+int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params *p, void *ws, size_t ws_bytes,
+                        void *stream, viecut_result *outs, uint64_t *const *sides);
+
+/* ------------------------------------------------------------ serving */
+/* A session keeps admitted graphs resident and advances all of them by one
+ * batched round per step (continuous batching): requests submitted while
+ * others are in flight join at the next step once their workspace fits in
+ * the budget; finished requests release their workspace. */
+typedef struct viecut_session viecut_session;
+
+/* hbm_budget: bytes of device memory the session may hold for workspaces. */
+int viecut_session_create(size_t hbm_budget, const viecut_params *p, void *stream, viecut_session **out);
+/* Queues a request. g's arrays and side (ceil(n/64) device words) must stay
+ * valid until the request is polled. Returns VIECUT_EBUDGET if it can never fit. */
+int viecut_session_submit(viecut_session *s, const viecut_csr *g, uint64_t *side, int64_t request_id);
+/* Admits what fits, runs one round for every active request, finishes those
+ * that are done. *n_active receives the number of requests still in flight or queued. */
+int viecut_session_step(viecut_session *s, int32_t *n_active);
+/* Retrieves up to max finished requests (ids and results); returns how many. */
+int viecut_session_poll(viecut_session *s, int64_t *ids, viecut_result *outs, int32_t max);
+void viecut_session_destroy(viecut_session *s);
+
+/* Static message for a status code. */
+const char *viecut_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VIECUT_H */

@@ -1,0 +1,483 @@
+// Host driver of the inexact minimum-cut method (Algorithm 1 of the paper
+// with synchronous label propagation): workspace carving, the round loop
+// (label propagation -> cluster contraction -> bound -> Padberg-Rinaldi
+// marking -> union-find contraction -> bound), the exact solve on the
+// remaining graph and the transfer of its side to the input vertices.
+// Device work is enqueued on the caller's stream; the host reads the small
+// status block back at the points where sizes or stop decisions are needed.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/viecut.h"
+#include "vc_internal.h"
+
+namespace vc {
+
+// SplitMix64 (Steele, Lea, Flood 2014): output number `index` (1-based) of the
+// generator whose state starts at `seed` is mix(seed + index * golden gamma).
+uint64_t splitmix64_at(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + index * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+namespace {
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t off[40];
+  int cnt = 0;
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    off[cnt++] = total;
+    total += align256(bytes);
+    return off[cnt - 1];
+  }
+};
+
+int64_t scan_tmp_need(int64_t count) {
+  int64_t need = 0;
+  int64_t c = count;
+  while (c > 2048) {
+    c = (c + 2047) / 2048;
+    need += c;
+  }
+  return need + 64;
+}
+
+Layout make_layout(int32_t n, int64_t nnz) {
+  Layout L;
+  const int64_t tiles = (nnz + 4095) / 4096 + 1;
+  const int64_t huge_rows = nnz / (kHugeChunk + 1) + 1;
+  int64_t maxscan = std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles});
+  L.add(sizeof(Status));                       // 0 st
+  for (int b = 0; b < 2; b++) {
+    L.add(4 * ((size_t)n + 1));                // rp
+    L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // col
+    L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // w
+  }                                            // 1..6
+  L.add(8 * (size_t)n + 8);                    // 7 deg
+  L.add(4 * (size_t)n + 4);                    // 8 La
+  L.add(4 * (size_t)n + 4);                    // 9 Lb
+  L.add(4 * ((size_t)n + 1));                  // 10 ids
+  L.add(4 * (size_t)n + 4);                    // 11 cl
+  L.add(4 * (size_t)n + 4);                    // 12 map
+  L.add(8 * (((size_t)n + 63) / 64) + 8);      // 13 witness
+  L.add(4 * (size_t)kBins * n + 4);            // 14 bins
+  L.add(4 * ((size_t)n + 1));                  // 15 cnt
+  L.add(8 * (size_t)std::max<int64_t>(nnz, 1));  // 16 keys0
+  L.add(8 * (size_t)std::max<int64_t>(nnz, 1));  // 17 keys1
+  L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // 18 vals0
+  L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // 19 vals1
+  L.add(4 * 256 * (size_t)tiles);              // 20 hist
+  L.add(4 * (size_t)scan_tmp_need(maxscan));   // 21 scan_tmp
+  L.add((size_t)std::max<int64_t>(nnz, 1));    // 22 mark
+  L.add(4 * (size_t)n + 4);                    // 23 parent
+  L.add(4 * 4 * (size_t)std::max<int64_t>(nnz, 1));  // 24 huge keys (4 slots per arc)
+  L.add(4 * 4 * (size_t)std::max<int64_t>(nnz, 1));  // 25 huge vals
+  L.add(8 * (size_t)huge_rows);                // 26 huge best
+  L.add(12 * (size_t)huge_rows);               // 27 huge meta
+  L.add((size_t)n + 1);                        // 28 flags8
+  return L;
+}
+
+}  // namespace
+
+size_t work_bytes(int32_t n, int64_t nnz) { return make_layout(n, nnz).total + 256; }
+
+bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w) {
+  Layout L = make_layout(n, nnz);
+  uintptr_t base = ((uintptr_t)ws + 255) & ~uintptr_t(255);
+  if (base + L.total > (uintptr_t)ws + bytes) return false;
+  auto at = [&](int i) { return (void *)(base + L.off[i]); };
+  w.n_in = n;
+  w.nnz_in = nnz;
+  w.st = (Status *)at(0);
+  for (int b = 0; b < 2; b++) {
+    w.rp[b] = (int32_t *)at(1 + 3 * b);
+    w.col[b] = (int32_t *)at(2 + 3 * b);
+    w.w[b] = (int32_t *)at(3 + 3 * b);
+  }
+  w.deg = (long long *)at(7);
+  w.La = (int32_t *)at(8);
+  w.Lb = (int32_t *)at(9);
+  w.ids = (int32_t *)at(10);
+  w.cl = (int32_t *)at(11);
+  w.map = (int32_t *)at(12);
+  w.witness = (unsigned long long *)at(13);
+  w.bins = (int32_t *)at(14);
+  w.cnt = (int32_t *)at(15);
+  w.keys[0] = (unsigned long long *)at(16);
+  w.keys[1] = (unsigned long long *)at(17);
+  w.vals[0] = (int32_t *)at(18);
+  w.vals[1] = (int32_t *)at(19);
+  w.hist = (int32_t *)at(20);
+  w.scan_tmp = (int32_t *)at(21);
+  const int64_t tiles = (nnz + 4095) / 4096 + 1;
+  w.scan_tmp_elems = (size_t)scan_tmp_need(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles}));
+  w.mark = (uint8_t *)at(22);
+  w.parent = (int32_t *)at(23);
+  w.huge_tab_key = (int32_t *)at(24);
+  w.huge_tab_val = (uint32_t *)at(25);
+  w.huge_best = (unsigned long long *)at(26);
+  w.huge_meta = (int32_t *)at(27);
+  w.huge_cap = 4 * std::max<int64_t>(nnz, 1);
+  w.flags8 = (uint8_t *)at(28);
+  return true;
+}
+
+namespace {
+
+inline int bits_for_host(int32_t k) {
+  int b = 0;
+  while (b < 31 && (1 << b) < k) b++;
+  return b;
+}
+
+struct Tracer {
+  viecut_trace_fn fn = nullptr;
+  void *user = nullptr;
+};
+
+#define VC_TRY(x)                              \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return VIECUT_EDEVICE; \
+  } while (0)
+
+struct Solver {
+  Work &w;
+  hipStream_t s;
+  const viecut_params &p;
+  Tracer tr;
+  Status st{};  // host copy
+
+  Solver(Work &w_, hipStream_t s_, const viecut_params &p_) : w(w_), s(s_), p(p_) {}
+
+  int sync_status() {
+    VC_TRY(hipMemcpyAsync(&st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
+    VC_TRY(hipStreamSynchronize(s));
+    return VIECUT_OK;
+  }
+
+  uint32_t salt(int32_t round, int32_t iter) const {
+    return (uint32_t)(splitmix64_at(p.seed, (uint64_t)round * (uint64_t)p.lp_iters + (uint64_t)iter) & 0xFFFFFFFFull);
+  }
+
+  // ---- tracing helpers (host copies)
+  template <class T>
+  std::vector<T> d2h(const T *d, int64_t count) {
+    std::vector<T> h((size_t)std::max<int64_t>(count, 0));
+    if (count > 0) {
+      (void)hipMemcpyAsync(h.data(), d, sizeof(T) * count, hipMemcpyDeviceToHost, s);
+      (void)hipStreamSynchronize(s);
+    }
+    return h;
+  }
+  void trace_labels(int32_t round, int32_t iter, const int32_t *L, int32_t n) {
+    if (!tr.fn) return;
+    std::vector<int32_t> h = d2h(L, n);
+    viecut_event ev{};
+    ev.kind = 1; ev.round = round; ev.iter = iter; ev.n = n; ev.a = h.data();
+    tr.fn(tr.user, &ev);
+  }
+  void trace_graph(int32_t level, const DGraph &G, int32_t n_prev) {
+    if (!tr.fn) return;
+    std::vector<int32_t> rp = d2h(G.row_ptr, (int64_t)G.n + 1), col = d2h(G.col, G.nnz), ww = d2h(G.w, G.nnz),
+                         cl = d2h(w.cl, n_prev);
+    std::vector<long long> deg = d2h(w.deg, G.n);
+    std::vector<int64_t> d64(deg.begin(), deg.end());
+    viecut_event ev{};
+    ev.kind = 2; ev.level = level; ev.n = G.n; ev.n_prev = n_prev; ev.nnz = G.nnz;
+    ev.a = rp.data(); ev.b = col.data(); ev.c = ww.data(); ev.d = d64.data(); ev.e = cl.data();
+    tr.fn(tr.user, &ev);
+  }
+  void trace_bound(int32_t level, int32_t n) {
+    if (!tr.fn) return;
+    viecut_event ev{};
+    ev.kind = 3; ev.level = level; ev.n = n; ev.lam_hat = st.lam_hat;
+    ev.witness_vertex = st.wit_v; ev.witness_level = st.wit_level;
+    tr.fn(tr.user, &ev);
+  }
+  void trace_pr(int32_t round, int32_t level, const DGraph &G) {
+    if (!tr.fn) return;
+    std::vector<uint8_t> m8 = d2h(w.mark, G.nnz);
+    std::vector<int32_t> m(m8.begin(), m8.end());
+    viecut_event ev{};
+    ev.kind = 4; ev.round = round; ev.level = level; ev.n = G.n; ev.nnz = G.nnz; ev.lam_hat = st.lam_hat;
+    ev.a = m.data();
+    tr.fn(tr.user, &ev);
+  }
+  void trace_rep(int32_t round, int32_t level, const int32_t *rep, int32_t n) {
+    if (!tr.fn) return;
+    std::vector<int32_t> h = d2h(rep, n);
+    viecut_event ev{};
+    ev.kind = 5; ev.round = round; ev.level = level; ev.n = n; ev.a = h.data();
+    tr.fn(tr.user, &ev);
+  }
+
+  // Contract the partition `L` of G into the other CSR buffer. Returns the
+  // new graph in G/cur; reads the status (k, ax, then nnz / stop / bins).
+  int contract(const int32_t *L, DGraph &G, int &cur, int32_t &level) {
+    VC_TRY(relabel(L, G.n, w, s));
+    VC_TRY(compose_map(w, s));
+    VC_TRY(contract_emit(G, w, s));
+    int rc = sync_status();
+    if (rc) return rc;
+    const int32_t k = st.k;
+    const int64_t ax = st.ax;
+    const int kb = bits_for_host(k);
+    int which = 0;
+    VC_TRY(radix_sort(w, ax, 2 * kb, which, s));
+    const int dst = cur == 0 ? 1 : 0;
+    level++;
+    VC_TRY(contract_build(w, which, ax, kb, k, dst, level, s));
+    DGraph H;
+    H.n = k;
+    H.row_ptr = w.rp[dst];
+    H.col = w.col[dst];
+    H.w = w.w[dst];
+    VC_TRY(reset_bins(w, s));
+    VC_TRY(build_bins(H, w, s));
+    rc = sync_status();
+    if (rc) return rc;
+    H.nnz = st.nnz;
+    const int32_t n_prev = G.n;
+    G = H;
+    cur = dst;
+    trace_graph(level, G, n_prev);
+    if (!(st.stop & ST_COLLAPSED)) trace_bound(level, G.n);
+    return VIECUT_OK;
+  }
+
+  int run(const viecut_csr &g, viecut_result *out, uint64_t *side) {
+    auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point a) {
+      return std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - a).count();
+    };
+    float t_ms[8] = {0};
+    DGraph G;
+    G.n = g.n;
+    G.nnz = g.nnz;
+    G.row_ptr = g.row_ptr;
+    G.col = g.col;
+    G.w = g.w;
+    const bool do_lp = p.lp_iters > 0 && g.n > p.n0;
+    VC_TRY(status_reset(w.st, s));
+    VC_TRY(init_map(w, s));
+    VC_TRY(check_rowptr(G, w.st, s));
+    VC_TRY(build_bins(G, w, s));
+    VC_TRY(lp_first(G, w, nullptr, w.La, salt(0, 1), true, s));
+    if (p.flags & VIECUT_F_VALIDATE) VC_TRY(validate_sym(G, w.st, s));
+    VC_TRY(bound_level0(w, s));
+    int rc = sync_status();
+    if (rc) return rc;
+    if (st.err & (ERR_ROWPTR | ERR_COL | ERR_SELF)) return VIECUT_EINVAL;
+    if (st.err & ERR_WEIGHT) return VIECUT_EWEIGHT;
+    if (st.wsum / 2 > (unsigned long long)INT32_MAX) return VIECUT_EOVERFLOW;
+    if (st.err & (ERR_NOTSYM | ERR_UNSORTED)) return VIECUT_ENOTSYM;
+    t_ms[0] = ms_since(t0);
+    trace_bound(0, G.n);
+
+    int32_t known[8];
+    std::memcpy(known, st.bin_cnt, sizeof(known));
+    uint32_t status = 0;
+    int32_t level = 0, rounds = 0, cur = -1;
+    bool done = false;
+    if (st.lam_hat == 0) { status |= ST_DISCONNECTED; done = true; }
+    while (!done && G.n > p.n0) {
+      if (rounds >= p.max_rounds) { status |= ST_MAX_ROUNDS; break; }
+      const int32_t r = rounds++;
+      const int32_t n_start = G.n;
+      if (p.lp_iters > 0) {
+        auto tl = std::chrono::steady_clock::now();
+        int32_t *Lc = w.La, *Lo = w.Lb;
+        if (!(r == 0 && do_lp)) VC_TRY(lp_first(G, w, known, Lc, salt(r, 1), false, s));
+        trace_labels(r, 1, Lc, G.n);
+        for (int32_t t = 2; t <= p.lp_iters; t++) {
+          VC_TRY(lp_iter(G, w, known, Lc, Lo, salt(r, t), s));
+          std::swap(Lc, Lo);
+          trace_labels(r, t, Lc, G.n);
+        }
+        if (!tr.fn) { VC_TRY(hipStreamSynchronize(s)); }
+        t_ms[1] += ms_since(tl);
+        auto tc = std::chrono::steady_clock::now();
+        rc = contract(Lc, G, cur, level);
+        if (rc) return rc;
+        t_ms[2] += ms_since(tc);
+        std::memcpy(known, st.bin_cnt, sizeof(known));
+        if (st.stop) { status |= (uint32_t)st.stop; done = true; break; }
+      }
+      auto tp = std::chrono::steady_clock::now();
+      VC_TRY(pr_mark(G, w, s));
+      rc = sync_status();
+      if (rc) return rc;
+      trace_pr(r, level, G);
+      if (st.nmarked > 0) {
+        int32_t *rep = w.Lb;
+        VC_TRY(union_find(G, w, rep, s));
+        trace_rep(r, level, rep, G.n);
+        rc = contract(rep, G, cur, level);
+        if (rc) return rc;
+        std::memcpy(known, st.bin_cnt, sizeof(known));
+        if (st.stop) { status |= (uint32_t)st.stop; done = true; t_ms[3] += ms_since(tp); break; }
+      }
+      t_ms[3] += ms_since(tp);
+      if (G.n == n_start) { status |= ST_NO_PROGRESS; break; }
+    }
+
+    // exact solve on the remaining graph, transfer of the side
+    auto te = std::chrono::steady_clock::now();
+    int64_t cut = st.lam_hat;
+    int32_t out_level = st.wit_level;
+    bool from_kernel = false;
+    if (!done && !(status & (ST_COLLAPSED | ST_DISCONNECTED)) && G.n >= 2) {
+      std::vector<int32_t> rp = d2h(G.row_ptr, (int64_t)G.n + 1);
+      std::vector<int32_t> col = d2h(G.col, G.nnz), ww = d2h(G.w, G.nnz);
+      std::vector<uint8_t> kside((size_t)G.n);
+      int64_t lk = stoer_wagner_host(G.n, rp.data(), col.data(), ww.data(), kside.data());
+      if (lk < cut) {
+        cut = lk;
+        out_level = -1;
+        from_kernel = true;
+        VC_TRY(hipMemcpyAsync(w.flags8, kside.data(), (size_t)G.n, hipMemcpyHostToDevice, s));
+        VC_TRY(side_from_flags(w, w.flags8, side, s));
+      }
+    }
+    if (!from_kernel) VC_TRY(side_from_witness(w, side, s));
+    VC_TRY(hipStreamSynchronize(s));
+    t_ms[4] = ms_since(te);
+    t_ms[5] = ms_since(t0);
+    out->cut = cut;
+    out->rounds = rounds;
+    out->kernel_n = G.n;
+    out->witness_level = out_level;
+    out->status_bits = status;
+    out->levels = level;
+    out->reserved = 0;
+    std::memcpy(out->t_ms, t_ms, sizeof(t_ms));
+    return VIECUT_OK;
+  }
+};
+
+}  // namespace
+
+int check_args(const viecut_csr *g, const viecut_params *p) {
+  if (!g || !p) return VIECUT_EINVAL;
+  if (g->n < 2 || g->nnz < 0 || !g->row_ptr) return VIECUT_EINVAL;
+  if (g->nnz > 0 && (!g->col || !g->w)) return VIECUT_EINVAL;
+  if (p->lp_iters < 0 || p->n0 < 0 || p->max_rounds < 0) return VIECUT_EINVAL;
+  return VIECUT_OK;
+}
+
+int solve_one(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
+              viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user) {
+  int rc = check_args(g, p);
+  if (rc) return rc;
+  if (!out || !side) return VIECUT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  void *own = nullptr;
+  size_t need = work_bytes(g->n, g->nnz);
+  if (!ws) {
+    if (hipMalloc(&own, need) != hipSuccess) return VIECUT_ENOMEM;
+    ws = own;
+    ws_bytes = need;
+  }
+  Work w;
+  if (!carve(ws, ws_bytes, g->n, g->nnz, w)) {
+    if (own) (void)hipFree(own);
+    return VIECUT_ENOMEM;
+  }
+  Solver sv(w, s, *p);
+  sv.tr.fn = fn;
+  sv.tr.user = user;
+  viecut_result res{};
+  rc = sv.run(*g, &res, side);
+  if (rc != VIECUT_OK) (void)hipStreamSynchronize(s);
+  if (own) (void)hipFree(own);
+  if (rc == VIECUT_OK) *out = res;
+  return rc;
+}
+
+}  // namespace vc
+
+// ============================================================ C ABI
+extern "C" {
+
+void viecut_default_params(viecut_params *p) {
+  if (!p) return;
+  p->lp_iters = 2;
+  p->n0 = 10000;
+  p->max_rounds = 64;
+  p->flags = 0;
+  p->seed = 0;
+}
+
+size_t viecut_workspace_bytes(int32_t n, int32_t nnz, const viecut_params *p) {
+  (void)p;
+  if (n < 2 || nnz < 0) return 0;
+  return vc::work_bytes(n, nnz);
+}
+
+int viecut_mincut(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
+                  viecut_result *out, uint64_t *side) {
+  return vc::solve_one(g, p, ws, ws_bytes, stream, out, side, nullptr, nullptr);
+}
+
+int viecut_mincut_trace(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
+                        viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user) {
+  return vc::solve_one(g, p, ws, ws_bytes, stream, out, side, fn, user);
+}
+
+int viecut_validate(const viecut_csr *g, uint32_t flags, void *stream) {
+  viecut_params p;
+  viecut_default_params(&p);
+  p.flags = flags;
+  int rc = vc::check_args(g, &p);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void *ws = nullptr;
+  size_t need = vc::work_bytes(g->n, g->nnz);
+  if (hipMalloc(&ws, need) != hipSuccess) return VIECUT_ENOMEM;
+  vc::Work w;
+  vc::carve(ws, need, g->n, g->nnz, w);
+  vc::DGraph G;
+  G.n = g->n; G.nnz = g->nnz; G.row_ptr = g->row_ptr; G.col = g->col; G.w = g->w;
+  vc::Status st{};
+  rc = VIECUT_OK;
+  if (vc::status_reset(w.st, s) != hipSuccess || vc::check_rowptr(G, w.st, s) != hipSuccess ||
+      vc::build_bins(G, w, s) != hipSuccess || vc::lp_first(G, w, nullptr, w.La, 0u, true, s) != hipSuccess ||
+      ((flags & VIECUT_F_VALIDATE) && vc::validate_sym(G, w.st, s) != hipSuccess) ||
+      hipMemcpyAsync(&st, w.st, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = VIECUT_EDEVICE;
+  (void)hipFree(ws);
+  if (rc) return rc;
+  if (st.err & (vc::ERR_ROWPTR | vc::ERR_COL | vc::ERR_SELF)) return VIECUT_EINVAL;
+  if (st.err & vc::ERR_WEIGHT) return VIECUT_EWEIGHT;
+  if (st.wsum / 2 > (unsigned long long)INT32_MAX) return VIECUT_EOVERFLOW;
+  if (st.err & (vc::ERR_NOTSYM | vc::ERR_UNSORTED)) return VIECUT_ENOTSYM;
+  return VIECUT_OK;
+}
+
+const char *viecut_strerror(int code) {
+  switch (code) {
+    case VIECUT_OK: return "ok";
+    case VIECUT_EINVAL: return "invalid argument or malformed CSR";
+    case VIECUT_EWEIGHT: return "edge weight < 1";
+    case VIECUT_EOVERFLOW: return "total edge weight exceeds INT32_MAX";
+    case VIECUT_ENOMEM: return "workspace too small or device allocation failed";
+    case VIECUT_EDEVICE: return "HIP runtime error";
+    case VIECUT_ENOTSYM: return "graph not symmetric or rows not strictly increasing";
+    case VIECUT_EBUDGET: return "request exceeds the session memory budget";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

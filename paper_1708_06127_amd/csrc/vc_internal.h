@@ -1,0 +1,137 @@
+// Internal declarations of the HIP min-cut library (device status block,
+// workspace views, kernel launchers). Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/viecut.h"
+
+namespace vc {
+
+constexpr int kBlock = 256;   // threads per workgroup everywhere (4 wave64)
+constexpr int kBins = 7;      // degree classes for per-vertex work
+constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
+
+// Degree classes (by arc count d of the row):
+//   0: d<=8, 1: d<=16, 2: d<=32, 3: d<=64, 4: d<=512, 5: d<=4096, 6: d>4096
+__host__ __device__ inline int degree_bin(int32_t d) {
+  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 512 ? 4 : d <= 4096 ? 5 : 6;
+}
+
+enum : int32_t {
+  ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELF = 4, ERR_WEIGHT = 8, ERR_NOTSYM = 16, ERR_UNSORTED = 32
+};
+enum : int32_t { ST_COLLAPSED = 1, ST_DISCONNECTED = 2, ST_NO_PROGRESS = 4, ST_MAX_ROUNDS = 8 };
+
+// Device-resident status of one solve. Read back to the host once per round.
+struct Status {
+  unsigned long long minkey;   // min over the level of (deg << 32 | v)
+  unsigned long long wsum;     // sum of the input's arc weights
+  long long lam_hat;           // current upper bound
+  long long pad0;
+  int32_t err;                 // ERR_* bits
+  int32_t k;                   // vertices of the graph being built (relabel total)
+  int32_t ax;                  // emitted inter-cluster arcs
+  int32_t nnz;                 // arcs of the graph being built
+  int32_t nmarked;             // PR-marked edges
+  int32_t wit_v, wit_level;    // witness vertex / level of lam_hat
+  int32_t updated;             // lam_hat lowered at the last bound update
+  int32_t stop;                // ST_COLLAPSED / ST_DISCONNECTED
+  int32_t dmax;                // largest row length of the current level
+  int32_t huge_items;          // work items (chunks) of the huge bin
+  int32_t huge_slots;          // table slots of the huge bin
+  int32_t bin_cnt[8];          // vertices per degree class
+};
+
+// One graph level in device memory. Rows may be unsorted only for the input.
+struct DGraph {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  const int32_t *row_ptr = nullptr;
+  const int32_t *col = nullptr;
+  const int32_t *w = nullptr;
+};
+
+// Per-solve device buffers (carved from one workspace).
+struct Work {
+  int32_t n_in = 0;
+  int64_t nnz_in = 0;
+  Status *st = nullptr;
+  // two ping-pong CSR buffers for coarse levels
+  int32_t *rp[2] = {nullptr, nullptr};
+  int32_t *col[2] = {nullptr, nullptr};
+  int32_t *w[2] = {nullptr, nullptr};
+  long long *deg = nullptr;      // degrees of the current level
+  int32_t *La = nullptr, *Lb = nullptr;   // LP labels (ping-pong)
+  int32_t *ids = nullptr;        // relabel flags / prefix sums, n+1
+  int32_t *cl = nullptr;         // old vertex -> new vertex
+  int32_t *map = nullptr;        // input vertex -> current vertex
+  unsigned long long *witness = nullptr;  // ceil(n_in/64) words
+  int32_t *bins = nullptr;       // kBins lists of capacity n
+  int32_t *cnt = nullptr;        // per-vertex counts (n+1)
+  unsigned long long *keys[2] = {nullptr, nullptr};  // sort keys (nnz each)
+  int32_t *vals[2] = {nullptr, nullptr};             // sort values
+  int32_t *hist = nullptr;       // radix histogram, 256 * tiles
+  int32_t *scan_tmp = nullptr;   // scan block sums
+  size_t scan_tmp_elems = 0;
+  uint8_t *mark = nullptr;       // PR mark per arc
+  int32_t *parent = nullptr;     // union-find
+  int32_t *huge_tab_key = nullptr;  // global hash tables of the huge bin
+  uint32_t *huge_tab_val = nullptr;
+  unsigned long long *huge_best = nullptr;  // per huge vertex best key
+  int32_t *huge_meta = nullptr;  // per huge vertex: chunk offset, table offset, table size
+  int64_t huge_cap = 0;          // table slots available
+  uint8_t *flags8 = nullptr;     // side flags of the kernel graph (n)
+};
+
+size_t work_bytes(int32_t n, int64_t nnz);
+bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w);
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and return hipSuccess or the launch error.
+hipError_t fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+hipError_t status_reset(Status *st, hipStream_t s);
+hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t count, int32_t *total, int32_t *tmp,
+                          size_t tmp_elems, hipStream_t s);
+
+hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s);
+hipError_t reset_bins(Work &w, hipStream_t s);
+hipError_t build_bins(const DGraph &g, Work &w, hipStream_t s);
+// `known`: host copy of the bin counts, or nullptr when they are only on the device
+// iteration 1 of LP (labels are the identity): row argmax, at level 0 fused
+// with validation, the weighted degree and the minimum-degree key
+hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
+                    hipStream_t s);
+// iteration t >= 2: neighbour-label weight sums in hash tables
+hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
+                   hipStream_t s);
+hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s);
+// relabel: ids = prefix sum of used label values, cl[v] = ids[L[v]], k -> st->k
+hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s);
+hipError_t compose_map(Work &w, hipStream_t s);
+hipError_t init_map(Work &w, hipStream_t s);
+// contraction: inter-cluster triples (count -> st->ax, key bits from st->k)
+hipError_t contract_emit(const DGraph &g, Work &w, hipStream_t s);
+hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s);
+// sorted triples -> CSR buffer `dst` with k rows, degrees, bound update at `level`, witness
+hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
+                          hipStream_t s);
+hipError_t bound_level0(Work &w, hipStream_t s);
+hipError_t pr_mark(const DGraph &g, Work &w, hipStream_t s);
+hipError_t union_find(const DGraph &g, Work &w, int32_t *rep, hipStream_t s);
+hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStream_t s);
+hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s);
+
+// host driver entry points shared by the single, batched and session paths
+int check_args(const viecut_csr *g, const viecut_params *p);
+int solve_one(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
+              viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user);
+
+// host helpers
+uint64_t splitmix64_at(uint64_t seed, uint64_t index);
+int64_t stoer_wagner_host(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *w,
+                          uint8_t *side);
+
+}  // namespace vc

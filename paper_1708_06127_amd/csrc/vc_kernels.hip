@@ -1,0 +1,1174 @@
+// HIP kernels for gfx950 (wave64) of the inexact minimum-cut method:
+//  * synchronous label propagation (Section 4.1 of the paper): every vertex
+//    picks the neighbouring label of largest connection weight, reading only
+//    the previous iteration's labels; ties keep the own label when it is
+//    maximal, else go to the smallest (prio, label) with
+//    prio(x) = fmix32(x ^ salt) (MurmurHash3's finaliser, a bijection on
+//    32-bit words, so labels never tie on prio);
+//  * relabelling by prefix sum and cluster contraction (Section 4.1): the
+//    inter-cluster arcs are emitted as (cl(u), cl(v), w) triples, radix
+//    sorted on the packed key and reduced into a coarse CSR;
+//  * the minimum weighted degree as upper bound (Section 4);
+//  * Padberg-Rinaldi conditions 1-4 tested edge-parallel (Lemma
+//    "Padberg-Rinaldi") and a lock-free union-find over marked edges;
+//  * transfer of a side back to the input vertices as a bitmap.
+//
+// Work per vertex is binned by row length: 8/16/32/64 lanes per vertex for
+// short rows (neighbour-label sums in an LDS hash table per group), a whole
+// wave with a 1024-slot table up to 512 arcs, a workgroup with an 8192-slot
+// table up to 4096 arcs, and beyond that rows split into 4096-arc chunks
+// handled by many workgroups that share a global-memory table per row.
+#include "vc_internal.h"
+
+namespace vc {
+namespace {
+
+// ------------------------------------------------------------ primitives
+__device__ __forceinline__ uint32_t fmix32_dev(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+// inverse of fmix32: undo each xorshift and multiply by the modular inverse
+__device__ __forceinline__ uint32_t fmix32_inv_dev(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x7ED1B41Du;
+  h ^= (h >> 13) ^ (h >> 26);
+  h *= 0xA5CB9243u;
+  h ^= h >> 16;
+  return h;
+}
+// Candidate key: larger connection weight first, then smaller prio.
+__device__ __forceinline__ unsigned long long cand_key(uint32_t S, int32_t x, uint32_t salt) {
+  return ((unsigned long long)S << 32) | (unsigned long long)(~fmix32_dev((uint32_t)x ^ salt));
+}
+__device__ __forceinline__ int32_t key_label(unsigned long long key, uint32_t salt) {
+  return (int32_t)(fmix32_inv_dev(~(uint32_t)(key & 0xFFFFFFFFull)) ^ salt);
+}
+__device__ __forceinline__ uint32_t slot_hash(int32_t x) { return (uint32_t)x * 2654435761u; }
+
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+  return a < b ? a : b;
+}
+
+// Reductions over aligned groups of G lanes (G <= 64 stays inside a wave).
+template <int G>
+__device__ __forceinline__ unsigned long long grp_max(unsigned long long v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v = umax64(v, __shfl_xor(v, off, G));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ unsigned long long grp_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int grp_or(int v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, G);
+  return v;
+}
+
+// Block-wide reductions (all threads call; result valid in every thread).
+__device__ __forceinline__ unsigned long long block_max(unsigned long long v, unsigned long long *sh) {
+  v = grp_max<64>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long r = sh[0];
+  for (int i = 1; i < kBlock / 64; i++) r = umax64(r, sh[i]);
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ unsigned long long block_min(unsigned long long v, unsigned long long *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long r = sh[0];
+  for (int i = 1; i < kBlock / 64; i++) r = umin64(r, sh[i]);
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long *sh) {
+  v = grp_sum<64>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long r = 0;
+  for (int i = 0; i < kBlock / 64; i++) r += sh[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ int block_or(int v, unsigned long long *sh) {
+  return (int)block_max((unsigned long long)grp_or<64>(v), sh) | 0;
+}
+
+__device__ __forceinline__ int bits_for(int32_t k) {  // bits to hold values 0..k-1
+  int b = 0;
+  while (b < 31 && (1 << b) < k) b++;
+  return b;
+}
+
+// ------------------------------------------------------------ basic kernels
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+__global__ void k_status_reset(Status *st) {
+  if (threadIdx.x == 0) {
+    st->minkey = ~0ull;
+    st->wsum = 0;
+    st->lam_hat = 0x7FFFFFFFFFFFFFFFll;
+    st->err = 0;
+    st->k = 0;
+    st->ax = 0;
+    st->nnz = 0;
+    st->nmarked = 0;
+    st->wit_v = -1;
+    st->wit_level = 0;
+    st->updated = 0;
+    st->stop = 0;
+    st->dmax = 0;
+    st->huge_items = 0;
+    st->huge_slots = 0;
+  }
+  if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
+}
+
+// row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz, all within [0, nnz]
+__global__ void k_check_rowptr(const int32_t *rp, int32_t n, int64_t nnz, Status *st) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    int32_t a = rp[i], b = rp[i + 1];
+    if (a < 0 || b < a || (int64_t)b > nnz) bad = 1;
+    if (i == 0 && a != 0) bad = 1;
+    if (i == n - 1 && (int64_t)b != nnz) bad = 1;
+  }
+  if (bad) atomicOr(&st->err, ERR_ROWPTR);
+}
+
+// Degree classes: vertex lists per bin (capacity n each) + counts + max row length.
+__global__ void k_build_bins(const int32_t *rp, int32_t n, int64_t stride, int32_t *bins, Status *st) {
+  if (st->err) return;
+  int dmax = 0;
+  for (int64_t base = blockIdx.x * (int64_t)kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+    int64_t v = base + threadIdx.x;
+    bool act = v < n;
+    int32_t d = act ? rp[v + 1] - rp[v] : 0;
+    int b = act ? degree_bin(d) : -1;
+    dmax = d > dmax ? d : dmax;
+    // wave-aggregated append per bin
+    unsigned long long todo = __ballot(act);
+    while (todo) {
+      int leader = __ffsll((long long)todo) - 1;
+      int lb = __shfl(b, leader);
+      unsigned long long peers = __ballot(act && b == lb);
+      int lane = threadIdx.x & 63;
+      unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+      int rank = __popcll(peers & lt);
+      int base_pos = 0;
+      if (lane == leader) base_pos = atomicAdd(&st->bin_cnt[lb], __popcll(peers));
+      base_pos = __shfl(base_pos, leader);
+      if (act && b == lb) bins[(int64_t)lb * stride + base_pos + rank] = (int32_t)v;
+      todo &= ~peers;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    int o = __shfl_xor(dmax, off, 64);
+    dmax = o > dmax ? o : dmax;
+  }
+  if ((threadIdx.x & 63) == 0 && dmax > 0) atomicMax(&st->dmax, dmax);
+}
+
+// ------------------------------------------------------------ LP iteration 1
+// Identity labels: S(x) = w(v, x), so the new label is the row's argmax of
+// (w, -prio). At level 0 the same pass validates the row and computes the
+// weighted degree and the minimum-degree key.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                      const int32_t *__restrict__ w, int32_t n,
+                                                      const int32_t *__restrict__ list, const int32_t *cnt_p,
+                                                      int32_t *__restrict__ L, long long *__restrict__ deg,
+                                                      uint32_t salt, int level0, Status *st) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  if (st->err) return;
+  constexpr int NG = kBlock / G;
+  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+  const int32_t cnt = *cnt_p;
+  unsigned long long mykey = ~0ull, mysum = 0;
+  int myerr = 0;
+  for (int64_t base = blockIdx.x * (int64_t)NG; base < cnt; base += (int64_t)gridDim.x * NG) {
+    int64_t idx = base + gi;
+    bool act = idx < cnt;
+    int32_t v = act ? list[idx] : 0;
+    int32_t beg = act ? rp[v] : 0, end = act ? rp[v + 1] : 0;
+    unsigned long long best = 0, sum = 0;
+    int err = 0;
+    for (int32_t i = beg + lane; i < end; i += G) {
+      int32_t x = col[i], c = w[i];
+      if (level0) {
+        if (x < 0 || x >= n) err |= ERR_COL;
+        if (x == v) err |= ERR_SELF;
+        if (c < 1) err |= ERR_WEIGHT;
+      }
+      sum += (unsigned long long)(uint32_t)c;
+      best = umax64(best, cand_key((uint32_t)c, x, salt));
+    }
+    best = grp_max<G>(best);
+    sum = grp_sum<G>(sum);
+    err = grp_or<G>(err);
+    if (act && lane == 0) {
+      L[v] = end > beg ? key_label(best, salt) : v;
+      if (level0) {
+        deg[v] = (long long)sum;
+        unsigned long long s32 = sum > 0xFFFFFFFFull ? 0xFFFFFFFFull : sum;
+        mykey = umin64(mykey, (s32 << 32) | (uint32_t)v);
+        mysum += sum;
+        myerr |= err;
+      }
+    }
+  }
+  if (level0) {
+    unsigned long long k = block_min(mykey, sh);
+    unsigned long long s = block_sum(mysum, sh);
+    int e = (int)block_max((unsigned long long)myerr, sh);
+    if (threadIdx.x == 0) {
+      if (k != ~0ull) atomicMin(&st->minkey, k);
+      if (s) atomicAdd(&st->wsum, s);
+      if (e) atomicOr(&st->err, e);
+    }
+  }
+}
+
+// ------------------------------------------------------------ LP iteration t >= 2
+// S(x) = sum of w(v,u) over neighbours u with Lin[u] == x, accumulated in an
+// open-addressing hash table (int32 key, uint32 sum; sums are bounded by the
+// total weight <= INT32_MAX). Then the candidate of largest (S, -prio) wins
+// unless the vertex's own label already attains the maximum S.
+template <int G, int TBL>
+__global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                    const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
+                                                    int32_t *__restrict__ Lout, const int32_t *__restrict__ list,
+                                                    const int32_t *cnt_p, uint32_t salt, const Status *st) {
+  constexpr int NG = kBlock / G;
+  __shared__ int32_t tkey[NG][TBL];
+  __shared__ uint32_t tval[NG][TBL];
+  __shared__ unsigned long long red[kBlock / 64];
+  __shared__ uint32_t own_sh[NG];
+  if (st->err) return;
+  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+  const int32_t cnt = *cnt_p;
+  for (int64_t base = blockIdx.x * (int64_t)NG; base < cnt; base += (int64_t)gridDim.x * NG) {
+    int64_t idx = base + gi;
+    bool act = idx < cnt;
+    int32_t v = act ? list[idx] : 0;
+    int32_t beg = act ? rp[v] : 0, end = act ? rp[v + 1] : 0;
+    for (int s = lane; s < TBL; s += G) {
+      tkey[gi][s] = -1;
+      tval[gi][s] = 0;
+    }
+    if (lane == 0) own_sh[gi] = 0;
+    __syncthreads();
+    for (int32_t i = beg + lane; i < end; i += G) {
+      int32_t x = Lin[col[i]];
+      uint32_t c = (uint32_t)w[i];
+      uint32_t h = slot_hash(x) & (TBL - 1);
+      while (true) {
+        int32_t k = tkey[gi][h];
+        if (k == x) break;
+        if (k == -1) {
+          int32_t old = atomicCAS(&tkey[gi][h], -1, x);
+          if (old == -1 || old == x) break;
+        }
+        h = (h + 1) & (TBL - 1);
+      }
+      atomicAdd(&tval[gi][h], c);
+    }
+    __syncthreads();
+    unsigned long long best = 0;
+    const int32_t own = act ? Lin[v] : -1;
+    for (int s = lane; s < TBL; s += G) {
+      int32_t k = tkey[gi][s];
+      if (k >= 0) {
+        uint32_t S = tval[gi][s];
+        best = umax64(best, cand_key(S, k, salt));
+        if (k == own) own_sh[gi] = S;
+      }
+    }
+    if constexpr (G <= 64) {
+      best = grp_max<G>(best);
+    } else {
+      best = block_max(best, red);  // G == kBlock: one group per block
+    }
+    __syncthreads();
+    if (act && lane == 0) {
+      uint32_t S_own = own_sh[gi];
+      if (end == beg || (uint32_t)(best >> 32) == S_own) Lout[v] = own;
+      else Lout[v] = key_label(best, salt);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ huge rows
+// Rows longer than 4096 arcs: split into chunks; one workgroup per chunk.
+// plan: per huge vertex i, meta[3i] = first chunk, meta[3i+1] = table offset,
+// meta[3i+2] = table size (power of two >= 2 d, or 0 without a table).
+__global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_t *cnt_p, int32_t *meta,
+                            unsigned long long *best, int with_table, int64_t cap, Status *st) {
+  __shared__ int64_t sh_c[kBlock], sh_t[kBlock];
+  __shared__ int64_t carry_c, carry_t;
+  if (st->err) return;
+  const int32_t cnt = *cnt_p;
+  if (threadIdx.x == 0) { carry_c = 0; carry_t = 0; }
+  __syncthreads();
+  for (int32_t base = 0; base < cnt; base += kBlock) {
+    int32_t i = base + threadIdx.x;
+    int64_t c = 0, t = 0;
+    if (i < cnt) {
+      int32_t v = list[i];
+      int32_t d = rp[v + 1] - rp[v];
+      c = (d + kHugeChunk - 1) / kHugeChunk;
+      if (with_table) { t = 1; while (t < 2 * (int64_t)d) t <<= 1; }
+      best[i] = 0;
+    }
+    sh_c[threadIdx.x] = c;
+    sh_t[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {  // inclusive scan (Hillis-Steele)
+      int64_t ac = threadIdx.x >= off ? sh_c[threadIdx.x - off] : 0;
+      int64_t at = threadIdx.x >= off ? sh_t[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh_c[threadIdx.x] += ac;
+      sh_t[threadIdx.x] += at;
+      __syncthreads();
+    }
+    if (i < cnt) {
+      meta[3 * (int64_t)i] = (int32_t)(carry_c + sh_c[threadIdx.x] - c);
+      meta[3 * (int64_t)i + 1] = (int32_t)(carry_t + sh_t[threadIdx.x] - t);
+      meta[3 * (int64_t)i + 2] = (int32_t)t;
+    }
+    __syncthreads();
+    if (threadIdx.x == kBlock - 1) { carry_c += sh_c[kBlock - 1]; carry_t += sh_t[kBlock - 1]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->huge_items = (int32_t)carry_c;
+    st->huge_slots = (int32_t)carry_t;
+    if (carry_t > cap) atomicOr(&st->err, ERR_ROWPTR);  // cannot happen: sum of 2^ceil(log2 2d) <= 4 nnz
+  }
+}
+
+__device__ __forceinline__ int32_t huge_find(const int32_t *meta, int32_t cnt, int32_t p, int field) {
+  int32_t lo = 0, hi = cnt - 1;  // last i with meta[3i+field] <= p
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (meta[3 * (int64_t)mid + field] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_huge_clear(int32_t *tk, uint32_t *tv, const Status *st) {
+  if (st->err) return;
+  const int64_t slots = st->huge_slots;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kBlock) {
+    tk[i] = -1;
+    tv[i] = 0;
+  }
+}
+
+// one chunk per block iteration: level-0 validation/degree, first-iteration
+// argmax (no table), or table insertion of neighbour labels
+__global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ w, int32_t n,
+                                                        const int32_t *list, const int32_t *cnt_p,
+                                                        const int32_t *meta, const int32_t *__restrict__ Lin,
+                                                        int32_t *tk, uint32_t *tv, unsigned long long *best,
+                                                        long long *deg, uint32_t salt, int mode, Status *st) {
+  // mode 0: first iteration (argmax of (w,-prio)) + optional level-0 degree (mode 2)
+  // mode 1: table insertion
+  __shared__ unsigned long long sh[kBlock / 64];
+  if (st->err) return;
+  const int32_t cnt = *cnt_p;
+  const int32_t items = st->huge_items;
+  for (int32_t p = blockIdx.x; p < items; p += gridDim.x) {
+    int32_t i = huge_find(meta, cnt, p, 0);
+    int32_t v = list[i];
+    int32_t beg = rp[v] + (p - meta[3 * (int64_t)i]) * kHugeChunk;
+    int32_t end = min(rp[v + 1], beg + kHugeChunk);
+    if (mode == 1) {
+      int32_t *K = tk + meta[3 * (int64_t)i + 1];
+      uint32_t *V = tv + meta[3 * (int64_t)i + 1];
+      const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
+      for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
+        int32_t x = Lin[col[a]];
+        uint32_t h = slot_hash(x) & mask;
+        while (true) {
+          int32_t k = __hip_atomic_load(&K[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (k == x) break;
+          if (k == -1) {
+            int32_t old = atomicCAS(&K[h], -1, x);
+            if (old == -1 || old == x) break;
+          }
+          h = (h + 1) & mask;
+        }
+        atomicAdd(&V[h], (uint32_t)w[a]);
+      }
+    } else {
+      unsigned long long b = 0, sum = 0;
+      int err = 0;
+      for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
+        int32_t x = col[a], c = w[a];
+        if (mode == 2) {
+          if (x < 0 || x >= n) err |= ERR_COL;
+          if (x == v) err |= ERR_SELF;
+          if (c < 1) err |= ERR_WEIGHT;
+        }
+        sum += (unsigned long long)(uint32_t)c;
+        b = umax64(b, cand_key((uint32_t)c, x, salt));
+      }
+      b = block_max(b, sh);
+      sum = block_sum(sum, sh);
+      err = (int)block_max((unsigned long long)err, sh);
+      if (threadIdx.x == 0) {
+        atomicMax(&best[i], b);
+        if (mode == 2) {
+          atomicAdd((unsigned long long *)&deg[v], sum);
+          atomicAdd(&st->wsum, sum);
+          if (err) atomicOr(&st->err, err);
+        }
+      }
+    }
+  }
+}
+
+// table scan: per slot, contribute its candidate key to the row's maximum
+__global__ void k_huge_scan(const int32_t *meta, const int32_t *cnt_p, const int32_t *tk, const uint32_t *tv,
+                            unsigned long long *best, uint32_t salt, const Status *st) {
+  if (st->err) return;
+  const int32_t cnt = *cnt_p;
+  const int64_t slots = st->huge_slots;
+  for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < slots; s += (int64_t)gridDim.x * kBlock) {
+    int32_t k = tk[s];
+    if (k < 0) continue;
+    int32_t i = huge_find(meta, cnt, (int32_t)s, 1);
+    atomicMax(&best[i], cand_key(tv[s], k, salt));
+  }
+}
+
+// final decision per huge vertex
+__global__ void k_huge_final(const int32_t *rp, const int32_t *list, const int32_t *cnt_p, const int32_t *meta,
+                             const unsigned long long *best, const int32_t *Lin, const int32_t *tk,
+                             const uint32_t *tv, int32_t *Lout, long long *deg, uint32_t salt, int mode,
+                             Status *st) {
+  if (st->err) return;
+  const int32_t cnt = *cnt_p;
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+    int32_t v = list[i];
+    unsigned long long b = best[i];
+    if (mode == 1) {
+      // own label's sum by probing the row's table
+      const int32_t own = Lin[v];
+      const int32_t *K = tk + meta[3 * (int64_t)i + 1];
+      const uint32_t *V = tv + meta[3 * (int64_t)i + 1];
+      const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
+      uint32_t h = slot_hash(own) & mask, S_own = 0;
+      for (uint32_t probes = 0; probes <= mask; probes++) {
+        int32_t k = K[h];
+        if (k == own) { S_own = V[h]; break; }
+        if (k == -1) break;
+        h = (h + 1) & mask;
+      }
+      Lout[v] = ((uint32_t)(b >> 32) == S_own) ? own : key_label(b, salt);
+    } else {
+      Lout[v] = key_label(b, salt);
+      if (mode == 2) {
+        unsigned long long s = (unsigned long long)deg[v];
+        unsigned long long s32 = s > 0xFFFFFFFFull ? 0xFFFFFFFFull : s;
+        atomicMin(&st->minkey, (s32 << 32) | (uint32_t)v);
+      }
+    }
+  }
+}
+
+__global__ void k_zero_deg_list(const int32_t *list, const int32_t *cnt_p, long long *deg) {
+  const int32_t cnt = *cnt_p;
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) deg[list[i]] = 0;
+}
+
+// ------------------------------------------------------------ validation (flag)
+// every arc (v,u,c) has its reverse (u,v,c); rows strictly increasing
+__global__ void k_validate_sym(const int32_t *rp, const int32_t *col, const int32_t *w, int32_t n, Status *st) {
+  if (st->err) return;
+  int bad = 0;
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+      int32_t u = col[i];
+      if (i > rp[v] && col[i - 1] >= u) bad |= ERR_UNSORTED;
+      int32_t lo = rp[u], hi = rp[u + 1];
+      while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (col[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= rp[u + 1] || col[lo] != v || w[lo] != w[i]) bad |= ERR_NOTSYM;
+    }
+  }
+  if (bad) atomicOr(&st->err, bad);
+}
+
+// ------------------------------------------------------------ scan
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+// exclusive scan of one value per thread across the block; returns the block total
+__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t &total, int32_t *sh) {
+  int32_t inc = wave_incl_scan(x);
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 63) sh[wid] = inc;
+  __syncthreads();
+  int32_t off = 0;
+  total = 0;
+  for (int i = 0; i < kBlock / 64; i++) {
+    if (i < wid) off += sh[i];
+    total += sh[i];
+  }
+  __syncthreads();
+  return off + inc - x;
+}
+
+__global__ void k_scan_reduce(const int32_t *in, int64_t count, int32_t *bsum) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  int64_t base = blockIdx.x * (int64_t)kScanTile;
+  unsigned long long s = 0;
+  for (int j = 0; j < kScanItems; j++) {
+    int64_t i = base + j * kBlock + threadIdx.x;
+    if (i < count) s += (uint32_t)in[i];
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)s;
+}
+
+// in-place capable: out may equal in. offsets (optional) adds per-tile bases.
+__global__ void k_scan_tile(const int32_t *in, int32_t *out, int64_t count, const int32_t *offsets, int32_t *total) {
+  __shared__ int32_t tile[kScanTile];
+  __shared__ int32_t sh[kBlock / 64];
+  int64_t base = blockIdx.x * (int64_t)kScanTile;
+  for (int j = 0; j < kScanItems; j++) {
+    int64_t i = base + j * kBlock + threadIdx.x;
+    tile[j * kBlock + threadIdx.x] = i < count ? in[i] : 0;
+  }
+  __syncthreads();
+  int32_t loc[kScanItems];
+  int32_t acc = 0;
+  for (int j = 0; j < kScanItems; j++) {
+    loc[j] = acc;
+    acc += tile[threadIdx.x * kScanItems + j];
+  }
+  int32_t tot;
+  int32_t off = block_excl_scan(acc, tot, sh);
+  int32_t add = offsets ? offsets[blockIdx.x] : 0;
+  for (int j = 0; j < kScanItems; j++) tile[threadIdx.x * kScanItems + j] = add + off + loc[j];
+  __syncthreads();
+  for (int j = 0; j < kScanItems; j++) {
+    int64_t i = base + j * kBlock + threadIdx.x;
+    if (i < count) out[i] = tile[j * kBlock + threadIdx.x];
+  }
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = add + tot;
+}
+
+// ------------------------------------------------------------ relabel / map
+__global__ void k_flag_labels(const int32_t *L, int32_t n, int32_t *flags) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+    flags[L[v]] = 1;
+}
+__global__ void k_apply_ids(const int32_t *L, const int32_t *ids, int32_t n, int32_t *cl) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+    cl[v] = ids[L[v]];
+}
+__global__ void k_compose(int32_t *map, const int32_t *cl, int32_t n_in) {
+  for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < n_in; u += (int64_t)gridDim.x * kBlock)
+    map[u] = cl[map[u]];
+}
+__global__ void k_iota(int32_t *p, int32_t n) {
+  for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock)
+    p[u] = (int32_t)u;
+}
+
+// ------------------------------------------------------------ contraction
+// per vertex: number of arcs leaving its cluster
+__global__ void k_count_inter(const int32_t *rp, const int32_t *col, const int32_t *cl, int32_t n, int32_t *cnt) {
+  constexpr int G = 16;
+  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+  for (int64_t base = blockIdx.x * (int64_t)(kBlock / G); base < n; base += (int64_t)gridDim.x * (kBlock / G)) {
+    int64_t v = base + gi;
+    unsigned long long c = 0;
+    int32_t cv = 0;
+    if (v < n) {
+      cv = cl[v];
+      for (int32_t i = rp[v] + lane; i < rp[v + 1]; i += G) c += cl[col[i]] != cv;
+    }
+    c = grp_sum<G>(c);
+    if (v < n && lane == 0) cnt[v] = (int32_t)c;
+  }
+}
+
+__global__ void k_emit(const int32_t *rp, const int32_t *col, const int32_t *w, const int32_t *cl, int32_t n,
+                       const int32_t *off, const Status *st, unsigned long long *keys, int32_t *vals) {
+  constexpr int G = 16;
+  const int key_bits = bits_for(st->k);
+  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+  for (int64_t base = blockIdx.x * (int64_t)(kBlock / G); base < n; base += (int64_t)gridDim.x * (kBlock / G)) {
+    int64_t v = base + gi;
+    if (v >= n) continue;
+    const int32_t cv = cl[v];
+    int32_t o = off[v];
+    // ordered compaction of the row's inter-cluster arcs, G arcs at a time
+    for (int32_t i0 = rp[v]; i0 < rp[v + 1]; i0 += G) {
+      int32_t i = i0 + lane;
+      bool ok = false;
+      int32_t cu = 0;
+      if (i < rp[v + 1]) { cu = cl[col[i]]; ok = cu != cv; }
+      unsigned long long bal = __ballot(ok);
+      const int wl = threadIdx.x & 63, gbase = wl & ~(G - 1);
+      unsigned long long gm = (bal >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1));
+      int rank = __popcll(gm & ((1ull << lane) - 1));
+      if (ok) {
+        keys[o + rank] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cu;
+        vals[o + rank] = w[i];
+      }
+      o += __popcll(gm);
+    }
+  }
+}
+
+// ---- LSD radix sort of (u64 key, i32 value), 8-bit digits, stable
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;
+
+__global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shift, int32_t *hist, int32_t tiles) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = blockIdx.x * (int64_t)kRsTile;
+  for (int j = 0; j < kRsItems; j++) {
+    int64_t i = base + j * kBlock + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * (int64_t)tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long *__restrict__ kin,
+                                                        const int32_t *__restrict__ vin,
+                                                        unsigned long long *__restrict__ kout,
+                                                        int32_t *__restrict__ vout, int64_t count, int shift,
+                                                        const int32_t *__restrict__ offs, int32_t tiles) {
+  __shared__ int32_t wcnt[kBlock / 64][256];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = threadIdx.x; d < 256 * (kBlock / 64); d += kBlock) (&wcnt[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t base = blockIdx.x * (int64_t)kRsTile + (int64_t)wid * 64 * kRsItems;
+  unsigned long long key[kRsItems];
+  int32_t val[kRsItems], rank[kRsItems], dig[kRsItems];
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int j = 0; j < kRsItems; j++) {
+    int64_t i = base + j * 64 + lane;
+    bool ok = i < count;
+    key[j] = ok ? kin[i] : 0;
+    val[j] = ok ? vin[i] : 0;
+    int d = ok ? (int)((key[j] >> shift) & 255) : 0;
+    dig[j] = ok ? d : -1;
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      unsigned long long bb = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    int r = __popcll(peers & lt);
+    int old = ok ? wcnt[wid][d] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (ok && r == 0) wcnt[wid][d] = old + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[j] = old + r;
+  }
+  __syncthreads();
+  {  // per digit: exclusive offsets across the block's waves
+    int d = threadIdx.x;
+    int acc = 0;
+    for (int q = 0; q < kBlock / 64; q++) {
+      int t = wcnt[q][d];
+      wcnt[q][d] = acc;
+      acc += t;
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < kRsItems; j++) {
+    if (dig[j] < 0) continue;
+    int d = dig[j];
+    int64_t pos = (int64_t)offs[d * (int64_t)tiles + blockIdx.x] + wcnt[wid][d] + rank[j];
+    kout[pos] = key[j];
+    vout[pos] = val[j];
+  }
+}
+
+// sorted triples -> coarse CSR: segment heads, column, summed weight per segment
+__global__ void k_seg_heads(const unsigned long long *keys, int64_t count, int32_t *head) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
+    head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+// seg = exclusive scan of head; each element adds its weight to its segment
+// (wave-level segmented pre-reduction keeps atomics to one per segment piece)
+__global__ void k_seg_write(const unsigned long long *keys, const int32_t *vals, int64_t count, const int32_t *seg,
+                            const int32_t *head, int key_bits, int32_t *colo, int32_t *wo, int32_t *rowcnt,
+                            unsigned long long *degu) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long mask_lo = (1ull << key_bits) - 1;
+  for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
+    int64_t i = base + threadIdx.x;
+    bool ok = i < count;
+    unsigned long long k = ok ? keys[i] : ~0ull;
+    int32_t h = ok ? head[i] : 1;
+    int32_t s = ok ? seg[i] + h - 1 : -1;  // segment index of element i
+    unsigned long long x = ok ? (unsigned long long)(uint32_t)vals[i] : 0;
+    // segmented inclusive scan within the wave (segments keyed by s)
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      unsigned long long y = __shfl_up(x, off, 64);
+      int32_t sy = __shfl_up(s, off, 64);
+      if (lane >= off && sy == s) x += y;
+    }
+    int32_t s_next = __shfl_down(s, 1, 64);
+    bool last = (lane == 63) || (s_next != s);
+    if (ok && last) {
+      atomicAdd((uint32_t *)&wo[s], (uint32_t)x);
+      atomicAdd(&degu[k >> key_bits], x);
+    }
+    if (ok && h) {
+      colo[s] = (int32_t)(k & mask_lo);
+      atomicAdd(&rowcnt[k >> key_bits], 1);
+    }
+  }
+}
+
+__global__ void k_set_minkey(Status *st) {
+  if (threadIdx.x == 0) st->minkey = ~0ull;
+}
+__global__ void k_reset_bins(Status *st) {
+  if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) st->dmax = 0;
+}
+
+__global__ void k_min_degree(const unsigned long long *degu, int32_t n, Status *st) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  unsigned long long m = ~0ull;
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    unsigned long long d = degu[v];
+    d = d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d;
+    m = umin64(m, (d << 32) | (uint32_t)v);
+  }
+  m = block_min(m, sh);
+  if (threadIdx.x == 0 && m != ~0ull) atomicMin(&st->minkey, m);
+}
+
+// lam_hat update after a contraction to a graph of k vertices (one thread)
+__global__ void k_bound(Status *st, int32_t level, int32_t k) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->updated = 0;
+  if (k == 1) { st->stop |= ST_COLLAPSED; return; }
+  long long d = (long long)(st->minkey >> 32);
+  int32_t v = (int32_t)(st->minkey & 0xFFFFFFFFull);
+  if (d < st->lam_hat) {
+    st->lam_hat = d;
+    st->wit_v = v;
+    st->wit_level = level;
+    st->updated = 1;
+  }
+  if (st->lam_hat == 0) st->stop |= ST_DISCONNECTED;
+}
+
+// witness bitmap {u : map[u] == wit_v} when lam_hat was just lowered
+__global__ void k_witness(const int32_t *map, int32_t n_in, const Status *st, unsigned long long *wit) {
+  if (!st->updated) return;
+  const int32_t x = st->wit_v;
+  for (int64_t base = blockIdx.x * (int64_t)kBlock; base < n_in; base += (int64_t)gridDim.x * kBlock) {
+    int64_t u = base + threadIdx.x;
+    bool b = u < n_in && map[u] == x;
+    unsigned long long bal = __ballot(b);
+    if ((threadIdx.x & 63) == 0 && (base + (threadIdx.x & ~63)) < n_in) wit[(base + threadIdx.x) >> 6] = bal;
+  }
+}
+
+// ------------------------------------------------------------ Padberg-Rinaldi
+// One group of 16 lanes per vertex v; for each arc (v, x) with v < x the
+// group tests conditions 1-4 (2 and 3 strict), intersecting the two sorted
+// rows by binary search of the shorter row's entries in the longer row.
+__global__ __launch_bounds__(kBlock) void k_pr_mark(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ w,
+                                                     const unsigned long long *__restrict__ degu, int32_t n,
+                                                     uint8_t *__restrict__ mark, Status *st) {
+  constexpr int G = 16;
+  __shared__ unsigned long long sh[kBlock / 64];
+  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
+  const long long lam = st->lam_hat;
+  unsigned long long nm = 0;
+  for (int64_t base = blockIdx.x * (int64_t)(kBlock / G); base < n; base += (int64_t)gridDim.x * (kBlock / G)) {
+    int64_t v = base + gi;
+    if (v >= n) continue;
+    const int32_t vb = rp[v], ve = rp[v + 1];
+    const long long dv = (long long)degu[v];
+    for (int32_t i = vb; i < ve; i++) {
+      const int32_t x = col[i];
+      if (x <= v) {
+        if (lane == 0) mark[i] = 0;
+        continue;
+      }
+      const long long c = w[i];
+      const long long dx = (long long)degu[x];
+      bool m = (c >= lam) || (dv < 2 * c) || (dx < 2 * c);
+      if (!m) {
+        const int32_t xb = rp[x], xe = rp[x + 1];
+        // iterate over the shorter row, search in the longer one
+        const bool v_short = (ve - vb) <= (xe - xb);
+        const int32_t sb = v_short ? vb : xb, se = v_short ? ve : xe;
+        const int32_t lb = v_short ? xb : vb, le = v_short ? xe : ve;
+        long long sum4 = 0;
+        int pr3 = 0;
+        for (int32_t j = sb + lane; j < se; j += G) {
+          const int32_t u = col[j];
+          int32_t lo = lb, hi = le;
+          while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (col[mid] < u) lo = mid + 1; else hi = mid;
+          }
+          if (lo < le && col[lo] == u) {
+            const long long cvu = v_short ? w[j] : w[lo];
+            const long long cxu = v_short ? w[lo] : w[j];
+            if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) pr3 = 1;
+            sum4 += cvu < cxu ? cvu : cxu;
+          }
+        }
+        sum4 = (long long)grp_sum<G>((unsigned long long)sum4);
+        pr3 = grp_or<G>(pr3);
+        m = pr3 || (c + sum4 >= lam);
+      }
+      if (lane == 0) {
+        mark[i] = m ? 1 : 0;
+        nm += m ? 1 : 0;
+      }
+    }
+  }
+  nm = block_sum(nm, sh);
+  if (threadIdx.x == 0 && nm) atomicAdd(&st->nmarked, (int32_t)nm);
+}
+
+// ------------------------------------------------------------ union-find
+__device__ __forceinline__ int32_t uf_root(int32_t *parent, int32_t x) {
+  while (true) {
+    int32_t p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == x) return x;
+    x = p;
+  }
+}
+// link the larger root under the smaller one: each component's root ends as
+// its smallest vertex id, independent of the order of the links
+__global__ void k_uf_link(const int32_t *rp, const int32_t *col, const uint8_t *mark, int32_t n, int32_t *parent) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+      if (!mark[i]) continue;
+      int32_t a = (int32_t)v, b = col[i];
+      while (true) {
+        a = uf_root(parent, a);
+        b = uf_root(parent, b);
+        if (a == b) break;
+        if (a > b) { int32_t t = a; a = b; b = t; }
+        int32_t old = atomicCAS(&parent[b], b, a);
+        if (old == b) break;
+      }
+    }
+  }
+}
+__global__ void k_uf_compress(int32_t *parent, int32_t n, int32_t *rep) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+    rep[v] = uf_root(parent, (int32_t)v);
+}
+
+// ------------------------------------------------------------ side transfer
+// bit u = flag[map[u]] (kernel side) XOR flag[map[0]]: vertex 0 ends on side 0
+__global__ void k_side_flags(const int32_t *map, const uint8_t *flags, int32_t n_in, unsigned long long *side) {
+  const uint8_t f0 = flags[map[0]];
+  for (int64_t base = blockIdx.x * (int64_t)kBlock; base < n_in; base += (int64_t)gridDim.x * kBlock) {
+    int64_t u = base + threadIdx.x;
+    bool b = u < n_in && (flags[map[u]] != f0);
+    unsigned long long bal = __ballot(b);
+    if ((threadIdx.x & 63) == 0 && (base + (threadIdx.x & ~63)) < n_in) side[(base + threadIdx.x) >> 6] = bal;
+  }
+}
+__global__ void k_side_witness(const unsigned long long *wit, int32_t n_in, unsigned long long *side) {
+  const bool flip = wit[0] & 1ull;
+  const int32_t words = (n_in + 63) / 64;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < words; i += (int64_t)gridDim.x * kBlock) {
+    unsigned long long x = wit[i] ^ (flip ? ~0ull : 0ull);
+    int32_t rem = n_in - (int32_t)i * 64;
+    if (rem < 64) x &= (1ull << rem) - 1;
+    side[i] = x;
+  }
+}
+
+inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 8192) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+// ============================================================ launchers
+hipError_t fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_fill_i32<<<grid_for(count), kBlock, 0, s>>>(p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t status_reset(Status *st, hipStream_t s) {
+  k_status_reset<<<1, 64, 0, s>>>(st);
+  return hipGetLastError();
+}
+
+hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t count, int32_t *total, int32_t *tmp,
+                          size_t tmp_elems, hipStream_t s) {
+  if (count <= 0) {
+    if (total) return fill_i32(total, 0, 1, s);
+    return hipSuccess;
+  }
+  int64_t tiles = (count + kScanTile - 1) / kScanTile;
+  if (tiles == 1) {
+    k_scan_tile<<<1, kBlock, 0, s>>>(in, out, count, nullptr, total);
+    return hipGetLastError();
+  }
+  if ((size_t)tiles > tmp_elems) return hipErrorInvalidValue;
+  k_scan_reduce<<<(unsigned)tiles, kBlock, 0, s>>>(in, count, tmp);
+  hipError_t e = scan_exclusive(tmp, tmp, tiles, nullptr, tmp + tiles, tmp_elems - tiles, s);
+  if (e != hipSuccess) return e;
+  k_scan_tile<<<(unsigned)tiles, kBlock, 0, s>>>(in, out, count, tmp, total);
+  return hipGetLastError();
+}
+
+hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
+  k_check_rowptr<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.n, g.nnz, st);
+  return hipGetLastError();
+}
+
+hipError_t build_bins(const DGraph &g, Work &w, hipStream_t s) {
+  k_build_bins<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.n, w.n_in, w.bins, w.st);
+  return hipGetLastError();
+}
+
+namespace {
+// items of bin b: host-known count (>= 0) or -1 when only the device knows it
+inline int64_t bin_items(const int32_t *known, int b, int64_t fallback) { return known ? known[b] : fallback; }
+
+template <int G>
+void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t *L, uint32_t salt, int level0,
+                  hipStream_t s) {
+  const int64_t items = bin_items(known, b, g.n);
+  if (items <= 0) return;
+  const int32_t *list = w.bins + (int64_t)b * w.n_in;
+  k_lp_first<G><<<grid_for(items, kBlock / G, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
+                                                                    &w.st->bin_cnt[b], L, w.deg, salt, level0,
+                                                                    w.st);
+}
+template <int G, int TBL>
+void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int32_t *Lin, int32_t *Lout,
+                uint32_t salt, hipStream_t s) {
+  const int64_t items = bin_items(known, b, g.n);
+  if (items <= 0) return;
+  const int32_t *list = w.bins + (int64_t)b * w.n_in;
+  k_lp_tab<G, TBL><<<grid_for(items, kBlock / G, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, list,
+                                                                       &w.st->bin_cnt[b], salt, w.st);
+}
+}  // namespace
+
+hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
+                    hipStream_t s) {
+  const int l0 = level0 ? 1 : 0;
+  launch_first<8>(g, w, 0, known, L, salt, l0, s);
+  launch_first<16>(g, w, 1, known, L, salt, l0, s);
+  launch_first<32>(g, w, 2, known, L, salt, l0, s);
+  launch_first<64>(g, w, 3, known, L, salt, l0, s);
+  launch_first<64>(g, w, 4, known, L, salt, l0, s);
+  launch_first<64>(g, w, 5, known, L, salt, l0, s);
+  if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
+  // huge rows: chunked
+  const int32_t *list6 = w.bins + 6ll * w.n_in;
+  const int32_t *cnt6 = &w.st->bin_cnt[6];
+  if (level0) k_zero_deg_list<<<64, kBlock, 0, s>>>(list6, cnt6, w.deg);
+  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st);
+  k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(
+      g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, nullptr, nullptr, nullptr, w.huge_best, w.deg, salt,
+      level0 ? 2 : 0, w.st);
+  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, nullptr, nullptr, L,
+                                     w.deg, salt, level0 ? 2 : 0, w.st);
+  return hipGetLastError();
+}
+
+hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
+                   hipStream_t s) {
+  launch_tab<8, 16>(g, w, 0, known, Lin, Lout, salt, s);
+  launch_tab<16, 32>(g, w, 1, known, Lin, Lout, salt, s);
+  launch_tab<32, 64>(g, w, 2, known, Lin, Lout, salt, s);
+  launch_tab<64, 128>(g, w, 3, known, Lin, Lout, salt, s);
+  launch_tab<64, 1024>(g, w, 4, known, Lin, Lout, salt, s);
+  launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s);
+  if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
+  const int32_t *list6 = w.bins + 6ll * w.n_in;
+  const int32_t *cnt6 = &w.st->bin_cnt[6];
+  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st);
+  k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);
+  k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list6, cnt6,
+                                                                     w.huge_meta, Lin, w.huge_tab_key,
+                                                                     w.huge_tab_val, w.huge_best, nullptr, salt, 1,
+                                                                     w.st);
+  k_huge_scan<<<2048, kBlock, 0, s>>>(w.huge_meta, cnt6, w.huge_tab_key, w.huge_tab_val, w.huge_best, salt, w.st);
+  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, Lin, w.huge_tab_key,
+                                     w.huge_tab_val, Lout, nullptr, salt, 1, w.st);
+  return hipGetLastError();
+}
+
+hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s) {
+  k_validate_sym<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, st);
+  return hipGetLastError();
+}
+
+hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s) {
+  hipError_t e = fill_i32(w.ids, 0, (int64_t)n + 1, s);
+  if (e != hipSuccess) return e;
+  k_flag_labels<<<grid_for(n), kBlock, 0, s>>>(L, n, w.ids);
+  e = scan_exclusive(w.ids, w.ids, n, &w.st->k, w.scan_tmp, w.scan_tmp_elems, s);
+  if (e != hipSuccess) return e;
+  k_apply_ids<<<grid_for(n), kBlock, 0, s>>>(L, w.ids, n, w.cl);
+  return hipGetLastError();
+}
+
+hipError_t compose_map(Work &w, hipStream_t s) {
+  k_compose<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.cl, w.n_in);
+  return hipGetLastError();
+}
+
+hipError_t init_map(Work &w, hipStream_t s) {
+  k_iota<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.n_in);
+  return hipGetLastError();
+}
+
+hipError_t contract_emit(const DGraph &g, Work &w, hipStream_t s) {
+  k_count_inter<<<grid_for(g.n, kBlock / 16), kBlock, 0, s>>>(g.row_ptr, g.col, w.cl, g.n, w.cnt);
+  hipError_t e = scan_exclusive(w.cnt, w.cnt, g.n, &w.st->ax, w.scan_tmp, w.scan_tmp_elems, s);
+  if (e != hipSuccess) return e;
+  k_emit<<<grid_for(g.n, kBlock / 16), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, g.n, w.cnt, w.st, w.keys[0],
+                                                        w.vals[0]);
+  return hipGetLastError();
+}
+
+hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s) {
+  which = 0;
+  if (count <= 1) return hipSuccess;
+  const int32_t tiles = (int32_t)((count + kRsTile - 1) / kRsTile);
+  for (int shift = 0; shift < total_bits; shift += 8) {
+    k_rs_hist<<<tiles, kBlock, 0, s>>>(w.keys[which], count, shift, w.hist, tiles);
+    hipError_t e = scan_exclusive(w.hist, w.hist, 256ll * tiles, nullptr, w.scan_tmp, w.scan_tmp_elems, s);
+    if (e != hipSuccess) return e;
+    k_rs_scatter<<<tiles, kBlock, 0, s>>>(w.keys[which], w.vals[which], w.keys[which ^ 1], w.vals[which ^ 1], count,
+                                          shift, w.hist, tiles);
+    which ^= 1;
+  }
+  return hipGetLastError();
+}
+
+hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
+                          hipStream_t s) {
+  int32_t *rowcnt = w.rp[dst];
+  unsigned long long *degu = (unsigned long long *)w.deg;
+  // free scratch while the sorted triples sit in buffer `which`
+  int32_t *head = w.vals[which ^ 1];
+  int32_t *seg = (int32_t *)w.keys[which ^ 1];
+  hipError_t e = fill_i32(rowcnt, 0, (int64_t)k + 1, s);
+  if (e == hipSuccess) e = fill_i32((int32_t *)degu, 0, 2ll * k, s);
+  if (e == hipSuccess) e = fill_i32(w.w[dst], 0, count, s);
+  if (e != hipSuccess) return e;
+  if (count > 0) {
+    k_seg_heads<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], count, head);
+    e = scan_exclusive(head, seg, count, &w.st->nnz, w.scan_tmp, w.scan_tmp_elems, s);
+    if (e != hipSuccess) return e;
+    k_seg_write<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], w.vals[which], count, seg, head, key_bits,
+                                                   w.col[dst], w.w[dst], rowcnt, degu);
+  } else {
+    e = fill_i32(&w.st->nnz, 0, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  e = scan_exclusive(rowcnt, rowcnt, (int64_t)k + 1, nullptr, w.scan_tmp, w.scan_tmp_elems, s);
+  if (e != hipSuccess) return e;
+  k_set_minkey<<<1, 64, 0, s>>>(w.st);
+  k_min_degree<<<grid_for(k, kBlock, 1024), kBlock, 0, s>>>(degu, k, w.st);
+  k_bound<<<1, 64, 0, s>>>(w.st, level, k);
+  k_witness<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.n_in, w.st, w.witness);
+  return hipGetLastError();
+}
+
+hipError_t bound_level0(Work &w, hipStream_t s) {
+  k_bound<<<1, 64, 0, s>>>(w.st, 0, w.n_in);
+  k_witness<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.n_in, w.st, w.witness);
+  return hipGetLastError();
+}
+
+hipError_t reset_bins(Work &w, hipStream_t s) {
+  k_reset_bins<<<1, 64, 0, s>>>(w.st);
+  return hipGetLastError();
+}
+
+hipError_t pr_mark(const DGraph &g, Work &w, hipStream_t s) {
+  hipError_t e = fill_i32(&w.st->nmarked, 0, 1, s);
+  if (e != hipSuccess) return e;
+  k_pr_mark<<<grid_for(g.n, kBlock / 16, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w,
+                                                                 (const unsigned long long *)w.deg, g.n, w.mark,
+                                                                 w.st);
+  return hipGetLastError();
+}
+
+hipError_t union_find(const DGraph &g, Work &w, int32_t *rep, hipStream_t s) {
+  k_iota<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n);
+  k_uf_link<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.col, w.mark, g.n, w.parent);
+  k_uf_compress<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n, rep);
+  return hipGetLastError();
+}
+
+hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStream_t s) {
+  k_side_flags<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, flags, w.n_in, (unsigned long long *)side);
+  return hipGetLastError();
+}
+
+hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s) {
+  k_side_witness<<<grid_for((w.n_in + 63) / 64), kBlock, 0, s>>>(w.witness, w.n_in, (unsigned long long *)side);
+  return hipGetLastError();
+}
+
+}  // namespace vc

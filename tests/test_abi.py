@@ -1,0 +1,58 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/viecut.h, and its host-only entry points behave."""
+import ctypes
+import os
+import re
+
+import paper_1708_06127_amd as vc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "viecut.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(viecut_[a-z_0-9]+)\s*\(", text))
+    return sorted(n for n in names if not n.endswith("_fn"))
+
+
+def test_library_exports_every_declared_function():
+    lib = vc.load()
+    names = declared_functions()
+    assert "viecut_mincut" in names and "viecut_mincut_batch" in names and "viecut_session_step" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(vc.EXPORTED) == names
+
+
+def test_default_params():
+    p = vc.params()
+    assert (p.lp_iters, p.n0, p.max_rounds, p.flags, p.seed) == (2, 10000, 64, 0, 0)
+
+
+def test_strerror():
+    assert vc.strerror(0) == "ok"
+    for code in range(-7, 0):
+        assert vc.strerror(code) and vc.strerror(code) != "unknown error"
+    assert vc.strerror(-99) == "unknown error"
+
+
+def test_workspace_bytes():
+    assert vc.workspace_bytes(1, 0) == 0
+    a = vc.workspace_bytes(1000, 32000)
+    b = vc.workspace_bytes(2000, 64000)
+    assert 0 < a < b
+    # the 2^20-vertex, 33.6 M-arc workload fits easily in 288 GB
+    assert vc.workspace_bytes(1 << 20, 33_635_268) < 8 * 2**30
+
+
+def test_invalid_arguments_rejected_on_host():
+    lib = vc.load()
+    res = vc.Result()
+    g = vc.Csr()
+    g.n, g.nnz = 1, 0
+    p = vc.params()
+    assert lib.viecut_mincut(ctypes.byref(g), ctypes.byref(p), None, 0, None, ctypes.byref(res), None) == vc.EINVAL
+    g.n = 5
+    p.lp_iters = -1
+    assert lib.viecut_mincut(ctypes.byref(g), ctypes.byref(p), None, 0, None, ctypes.byref(res), None) == vc.EINVAL

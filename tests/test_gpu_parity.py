@@ -1,0 +1,202 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle,
+bit-exact on the cut value, the side bitmap, the loop statistics and - on the
+traced cases - every intermediate state (labels after each LP iteration,
+coarse CSR, cluster maps, bound trajectory, Padberg-Rinaldi marks,
+union-find representatives)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_1708_06127_amd as vc
+from gpu_common import canon_with_graphs, log, side_words, to_dev
+from helpers import load_golden, random_graph
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = ["strict_pr.txt", "cycle6_w3.txt", "k5_unit.txt", "barbell.txt", "weighted_path4.txt",
+          "two_triangles_disconnected.txt"]
+
+
+def compare(g, name, trace=False, **kw):
+    log("case", name, "n=%d nnz=%d" % (g.n, g.nnz), kw)
+    ref = oracle.mincut_graph(g, trace=trace, **kw)
+    rp, col, w = to_dev(g)
+    cut, side, info = vc.mincut(rp, col, w, trace=trace, **kw)
+    got = (cut, side_words(side, g.n).tobytes(), info["rounds"], info["kernel_n"], info["witness_level"],
+           info["status"])
+    want = (ref.cut, ref.side.tobytes(), ref.rounds, ref.kernel_n, ref.witness_level, ref.status)
+    assert got[0] == want[0], (name, "cut", got[0], want[0])
+    assert got == want, (name, got[2:], want[2:])
+    if trace:
+        a = canon_with_graphs(ref.events, g)
+        b = canon_with_graphs(info["events"], g)
+        assert len(a) == len(b), (name, [x[0] for x in a], [x[0] for x in b])
+        for x, y in zip(a, b):
+            assert x == y, (name, x[:2], y[:2])
+    return info
+
+
+@pytest.mark.parametrize("name", GOLDEN)
+@pytest.mark.parametrize("lp", [0, 1, 2, 3])
+@pytest.mark.parametrize("n0", [1, 100])
+def test_golden(name, lp, n0):
+    g, _ = load_golden(name)
+    compare(g, name, trace=True, lp_iters=lp, n0=n0, seed=lp + n0)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_small(seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(3, 80))
+    g = random_graph(n, float(rng.uniform(0.03, 0.6)), int(rng.choice([1, 2, 7, 100])), 5000 + seed,
+                     connected=bool(seed % 6))
+    compare(g, "random%d" % seed, trace=True, lp_iters=int(rng.integers(0, 4)), n0=int(rng.integers(1, 6)),
+            seed=seed)
+
+
+@pytest.mark.parametrize("n,w", [(3, 1), (10, 2), (1000, 3), (5001, 1)])
+def test_cycles(n, w):
+    g = gg.from_edges(n, [(i, (i + 1) % n) for i in range(n)], [w] * n)
+    info = compare(g, "cycle", trace=True, lp_iters=2, n0=1)
+    assert info["cut"] == 2 * w
+
+
+@pytest.mark.parametrize("n", [2, 5, 33, 70])
+def test_cliques(n):
+    g = gg.from_edges(n, list(itertools.combinations(range(n), 2)))
+    compare(g, "clique", trace=True, lp_iters=2, n0=1)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_planted_c1(seed):
+    g = gg.c1_planted(seed)
+    compare(g, "c1-%d" % seed, trace=(seed < 3), lp_iters=2, n0=64, seed=0)
+
+
+@pytest.mark.parametrize("i", range(0, 4096, 97))
+def test_planted_batch_members(i):
+    n, d, kx, wlo, whi, s = gg.c4_params(4096, 3)[i]
+    g = gg.planted(n, d, kx, wlo, whi, s)
+    compare(g, "c4-%d" % i, trace=(i % 5 == 0), lp_iters=2, n0=64, seed=0)
+
+
+@pytest.mark.parametrize("seed,n0", [(0, 64), (1, 10000), (2, 64)])
+def test_rhg_small(seed, n0):
+    g = gg.rhg(1 << 14, 32.0, 5.0, seed)
+    compare(g, "rhg14", trace=True, lp_iters=2, n0=n0)
+
+
+def test_rhg_weighted():
+    g = gg.rhg(20000, 24.0, 5.0, 9, wlo=1, whi=100)
+    compare(g, "rhg-w", trace=True, lp_iters=2, n0=64)
+
+
+def test_rmat_core_small():
+    g = gg.rmat_core(15, 16, seed=2, kcore=10)
+    compare(g, "rmat15", trace=True, lp_iters=2, n0=64)
+
+
+def hub_graph(seed, hub_deg):
+    """A hub joined to `hub_deg` vertices of a ring of cliques: rows in every
+    degree class, including the chunked (> 4096 arcs) one."""
+    rng = np.random.default_rng(seed)
+    n = hub_deg + 1
+    e = [(0, i) for i in range(1, n)]
+    for c in range(1, n - 8, 8):  # cliques of 8 along the ring
+        e += [(c + a, c + b) for a, b in itertools.combinations(range(8), 2)]
+    e += [(i, i + 1) for i in range(1, n - 1)]
+    mid = [(int(a), int(b)) for a, b in rng.integers(1, n, (n, 2)) if a != b]
+    e += mid
+    return gg.from_edges(n, e, rng.integers(1, 5, len(e)))
+
+
+@pytest.mark.parametrize("hub_deg", [100, 700, 3000, 9000, 40000])
+def test_degree_classes(hub_deg):
+    g = hub_graph(hub_deg, hub_deg)
+    compare(g, "hub%d" % hub_deg, trace=True, lp_iters=3, n0=16, seed=hub_deg)
+
+
+def test_isolated_vertex():
+    g = gg.from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    info = compare(g, "isolated", lp_iters=2, n0=1)
+    assert info["cut"] == 0
+
+
+def test_repeat_runs_identical():
+    g = gg.planted(8000, 20.0, 9, 1, 100, seed=77)
+    rp, col, w = to_dev(g)
+    outs = set()
+    for _ in range(3):
+        cut, side, info = vc.mincut(rp, col, w, n0=64)
+        outs.add((cut, side_words(side, g.n).tobytes(), info["rounds"], info["kernel_n"]))
+    assert len(outs) == 1
+
+
+def test_full_size_rhg_2p20():
+    """The 2^20-vertex random hyperbolic graph (average degree 32, gamma 5)
+    at full size: result and every intermediate state equal the oracle's."""
+    g = gg.c2_rhg()
+    compare(g, "c2", trace=True, lp_iters=2, n0=10000, seed=0)
+    compare(g, "c2-n0-64", trace=False, lp_iters=2, n0=64, seed=0)
+
+
+def test_full_size_rmat22_core():
+    """R-MAT scale 22 10-core at full size (hub rows > 10^5 arcs)."""
+    g = gg.c3_rmat()
+    compare(g, "c3", trace=True, lp_iters=2, n0=10000, seed=0)
+
+
+# ------------------------------------------------------------ error paths
+def test_error_codes_and_recovery():
+    import torch
+    ok = gg.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)])
+    rp, col, w = to_dev(ok)
+    # zero weight
+    w0 = w.clone()
+    w0[2] = 0
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(rp, col, w0)
+    assert e.value.code == vc.EWEIGHT
+    # column out of range
+    c2 = col.clone()
+    c2[0] = 99
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(rp, c2, w)
+    assert e.value.code == vc.EINVAL
+    # self loop
+    c3 = col.clone()
+    c3[0] = 0
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(rp, c3, w)
+    assert e.value.code == vc.EINVAL
+    # bad row pointer
+    r2 = rp.clone()
+    r2[2] = 100
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(r2, col, w)
+    assert e.value.code == vc.EINVAL
+    # overflow of the total weight
+    big = gg.from_edges(3, [(0, 1), (1, 2)], [2**31 - 1, 5])
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(*to_dev(big))
+    assert e.value.code == vc.EOVERFLOW
+    # asymmetric weights (checked with validate=True)
+    w4 = w.clone()
+    w4[0] = 3
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(rp, col, w4, validate=True)
+    assert e.value.code == vc.ENOTSYM
+    assert vc.validate(rp, col, w4) == vc.ENOTSYM
+    assert vc.validate(rp, col, w) == vc.OK
+    # workspace too small
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(rp, col, w, ws=ws)
+    assert e.value.code == vc.ENOMEM
+    # still usable, and with a caller workspace
+    ws = vc.workspace(ok.n, ok.nnz)
+    cut, _, _ = vc.mincut(rp, col, w, ws=ws, n0=1)
+    assert cut == 2

@@ -55,7 +55,9 @@ Layout make_layout(int32_t n, int64_t nnz) {
   Layout L;
   const int64_t tiles = (nnz + 4095) / 4096 + 1;
   const int64_t huge_rows = nnz / (kHugeChunk + 1) + 1;
-  int64_t maxscan = std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles});
+  const int64_t ntiles = (nnz + n) / kTile + 2;
+  const int64_t nseg = ntiles + 3 * (nnz / kTile + 1) + 2;
+  int64_t maxscan = std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg});
   L.add(sizeof(Status));                       // 0 st
   for (int b = 0; b < 2; b++) {
     L.add(4 * ((size_t)n + 1));                // rp
@@ -84,6 +86,10 @@ Layout make_layout(int32_t n, int64_t nnz) {
   L.add(8 * (size_t)huge_rows);                // 26 huge best
   L.add(12 * (size_t)huge_rows);               // 27 huge meta
   L.add((size_t)n + 1);                        // 28 flags8
+  L.add(16 * (size_t)ntiles);                  // 29 tile_meta
+  L.add(24 * (size_t)ntiles);                  // 30 part
+  L.add(8 * (size_t)nseg);                     // 31 seg
+  L.add(4 * (size_t)nseg + 4);                 // 32 seg_cnt
   return L;
 }
 
@@ -120,7 +126,8 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w) {
   w.hist = (int32_t *)at(20);
   w.scan_tmp = (int32_t *)at(21);
   const int64_t tiles = (nnz + 4095) / 4096 + 1;
-  w.scan_tmp_elems = (size_t)scan_tmp_need(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles}));
+  const int64_t nseg = (nnz + n) / kTile + 2 + 3 * (nnz / kTile + 1) + 2;
+  w.scan_tmp_elems = (size_t)scan_tmp_need(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg}));
   w.mark = (uint8_t *)at(22);
   w.parent = (int32_t *)at(23);
   w.huge_tab_key = (int32_t *)at(24);
@@ -129,6 +136,10 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w) {
   w.huge_meta = (int32_t *)at(27);
   w.huge_cap = 4 * std::max<int64_t>(nnz, 1);
   w.flags8 = (uint8_t *)at(28);
+  w.tile_meta = (int4 *)at(29);
+  w.part = (unsigned long long *)at(30);
+  w.seg = (int32_t *)at(31);
+  w.seg_cnt = (int32_t *)at(32);
   return true;
 }
 
@@ -224,33 +235,38 @@ struct Solver {
 
   // Contract the partition `L` of G into the other CSR buffer. Returns the
   // new graph in G/cur; reads the status (k, ax, then nnz / stop / bins).
-  int contract(const int32_t *L, DGraph &G, int &cur, int32_t &level) {
+  // Contract the partition `L` of G into the other CSR buffer; G/cur become
+  // the new graph, whose arc tiles and long-row lists are built here.
+  // `known` holds the host copy of G's long-row counts (nullptr: unknown) and
+  // is invalidated for the new graph.
+  int contract(const int32_t *L, DGraph &G, int &cur, int32_t &level, const int32_t *&known) {
     VC_TRY(relabel(L, G.n, w, s));
     VC_TRY(compose_map(w, s));
-    VC_TRY(contract_emit(G, w, s));
+    VC_TRY(contract_emit(G, w, known, s));
     int rc = sync_status();
     if (rc) return rc;
     const int32_t k = st.k;
     const int64_t ax = st.ax;
     const int kb = bits_for_host(k);
-    int which = 0;
+    int which = 1;  // the emission leaves the packed triples in buffer 1
     VC_TRY(radix_sort(w, ax, 2 * kb, which, s));
     const int dst = cur == 0 ? 1 : 0;
     level++;
     VC_TRY(contract_build(w, which, ax, kb, k, dst, level, s));
+    rc = sync_status();
+    if (rc) return rc;
     DGraph H;
     H.n = k;
+    H.nnz = st.nnz;
     H.row_ptr = w.rp[dst];
     H.col = w.col[dst];
     H.w = w.w[dst];
-    VC_TRY(reset_bins(w, s));
-    VC_TRY(build_bins(H, w, s));
-    rc = sync_status();
-    if (rc) return rc;
-    H.nnz = st.nnz;
     const int32_t n_prev = G.n;
     G = H;
     cur = dst;
+    VC_TRY(reset_bins(w, s));
+    VC_TRY(build_tiles(G, w, s));
+    known = nullptr;
     trace_graph(level, G, n_prev);
     if (!(st.stop & ST_COLLAPSED)) trace_bound(level, G.n);
     return VIECUT_OK;
@@ -272,7 +288,7 @@ struct Solver {
     VC_TRY(status_reset(w.st, s));
     VC_TRY(init_map(w, s));
     VC_TRY(check_rowptr(G, w.st, s));
-    VC_TRY(build_bins(G, w, s));
+    VC_TRY(build_tiles(G, w, s));
     VC_TRY(lp_first(G, w, nullptr, w.La, salt(0, 1), true, s));
     if (p.flags & VIECUT_F_VALIDATE) VC_TRY(validate_sym(G, w.st, s));
     VC_TRY(bound_level0(w, s));
@@ -285,8 +301,13 @@ struct Solver {
     t_ms[0] = ms_since(t0);
     trace_bound(0, G.n);
 
-    int32_t known[8];
-    std::memcpy(known, st.bin_cnt, sizeof(known));
+    int32_t known_buf[8];
+    std::memcpy(known_buf, st.bin_cnt, sizeof(known_buf));
+    const int32_t *known = known_buf;
+    auto refresh_known = [&]() {
+      std::memcpy(known_buf, st.bin_cnt, sizeof(known_buf));
+      known = known_buf;
+    };
     uint32_t status = 0;
     int32_t level = 0, rounds = 0, cur = -1;
     bool done = false;
@@ -308,24 +329,23 @@ struct Solver {
         if (!tr.fn) { VC_TRY(hipStreamSynchronize(s)); }
         t_ms[1] += ms_since(tl);
         auto tc = std::chrono::steady_clock::now();
-        rc = contract(Lc, G, cur, level);
+        rc = contract(Lc, G, cur, level, known);
         if (rc) return rc;
         t_ms[2] += ms_since(tc);
-        std::memcpy(known, st.bin_cnt, sizeof(known));
         if (st.stop) { status |= (uint32_t)st.stop; done = true; break; }
       }
       auto tp = std::chrono::steady_clock::now();
-      VC_TRY(pr_mark(G, w, s));
+      VC_TRY(pr_mark(G, w, known, s));
       rc = sync_status();
       if (rc) return rc;
+      refresh_known();
       trace_pr(r, level, G);
       if (st.nmarked > 0) {
         int32_t *rep = w.Lb;
-        VC_TRY(union_find(G, w, rep, s));
+        VC_TRY(union_find(G, w, known, rep, s));
         trace_rep(r, level, rep, G.n);
-        rc = contract(rep, G, cur, level);
+        rc = contract(rep, G, cur, level, known);
         if (rc) return rc;
-        std::memcpy(known, st.bin_cnt, sizeof(known));
         if (st.stop) { status |= (uint32_t)st.stop; done = true; t_ms[3] += ms_since(tp); break; }
       }
       t_ms[3] += ms_since(tp);
@@ -452,7 +472,7 @@ int viecut_validate(const viecut_csr *g, uint32_t flags, void *stream) {
   vc::Status st{};
   rc = VIECUT_OK;
   if (vc::status_reset(w.st, s) != hipSuccess || vc::check_rowptr(G, w.st, s) != hipSuccess ||
-      vc::build_bins(G, w, s) != hipSuccess || vc::lp_first(G, w, nullptr, w.La, 0u, true, s) != hipSuccess ||
+      vc::build_tiles(G, w, s) != hipSuccess || vc::lp_first(G, w, nullptr, w.La, 0u, true, s) != hipSuccess ||
       ((flags & VIECUT_F_VALIDATE) && vc::validate_sym(G, w.st, s) != hipSuccess) ||
       hipMemcpyAsync(&st, w.st, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

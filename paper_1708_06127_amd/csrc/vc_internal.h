@@ -13,11 +13,22 @@ namespace vc {
 constexpr int kBlock = 256;   // threads per workgroup everywhere (4 wave64)
 constexpr int kBins = 7;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
+// Row-aligned arc tiles: tile t holds the rows v with rp[v] + v in
+// [t*kTile, (t+1)*kTile). A row with d >= kTile arcs is always the last row of
+// its tile and is left to the long-row kernels; the short rows of a tile then
+// hold at most kTile rows and fewer than 2*kTile arcs.
+constexpr int kTB = 64;       // threads of a tile workgroup (one wave: barriers are cheap)
+constexpr int kTile = 256;
+constexpr int kTileArcs = 2 * kTile;
+constexpr int kPerThread = kTileArcs / kTB;  // up to 8 consecutive arcs per thread
 
-// Degree classes (by arc count d of the row):
-//   0: d<=8, 1: d<=16, 2: d<=32, 3: d<=64, 4: d<=512, 5: d<=4096, 6: d>4096
+// Degree classes (by arc count d of the row). Only the long classes are
+// listed per level: 4: kTile <= d < 1024 (a wave per row, LDS table),
+// 5: 1024 <= d <= 4096 (a workgroup per row, LDS table), 6: d > 4096 (rows
+// split into 4096-arc chunks sharing a global table). Shorter rows are
+// handled by the arc tiles.
 __host__ __device__ inline int degree_bin(int32_t d) {
-  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 512 ? 4 : d <= 4096 ? 5 : 6;
+  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d < 1024 ? 4 : d <= 4096 ? 5 : 6;
 }
 
 enum : int32_t {
@@ -84,6 +95,11 @@ struct Work {
   int32_t *huge_meta = nullptr;  // per huge vertex: chunk offset, table offset, table size
   int64_t huge_cap = 0;          // table slots available
   uint8_t *flags8 = nullptr;     // side flags of the kernel graph (n)
+  int4 *tile_meta = nullptr;     // per arc tile: first row, short rows, first arc, arcs
+  int32_t ntiles = 0;            // tiles of the current level
+  unsigned long long *part = nullptr;  // per-block partial results (3 per tile)
+  int32_t *seg = nullptr;        // emission segments: (first arc, count) pairs
+  int32_t *seg_cnt = nullptr;    // their counts, then exclusive offsets
 };
 
 size_t work_bytes(int32_t n, int64_t nnz);
@@ -98,7 +114,8 @@ hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t count, int32_
 
 hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s);
 hipError_t reset_bins(Work &w, hipStream_t s);
-hipError_t build_bins(const DGraph &g, Work &w, hipStream_t s);
+// per level: arc tiles (w.ntiles set from g.nnz, which must be host-known) and long-row lists
+hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s);
 // `known`: host copy of the bin counts, or nullptr when they are only on the device
 // iteration 1 of LP (labels are the identity): row argmax, at level 0 fused
 // with validation, the weighted degree and the minimum-degree key
@@ -112,15 +129,17 @@ hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s);
 hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s);
 hipError_t compose_map(Work &w, hipStream_t s);
 hipError_t init_map(Work &w, hipStream_t s);
-// contraction: inter-cluster triples (count -> st->ax, key bits from st->k)
-hipError_t contract_emit(const DGraph &g, Work &w, hipStream_t s);
+// contraction: inter-cluster triples packed into buffer 1 (count -> st->ax, key bits from st->k)
+hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);
+// sorts the `count` triples held in buffer `which` (in/out: the buffer holding the result)
 hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s);
 // sorted triples -> CSR buffer `dst` with k rows, degrees, bound update at `level`, witness
 hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
                           hipStream_t s);
 hipError_t bound_level0(Work &w, hipStream_t s);
-hipError_t pr_mark(const DGraph &g, Work &w, hipStream_t s);
-hipError_t union_find(const DGraph &g, Work &w, int32_t *rep, hipStream_t s);
+// PR marks on the v < x arcs (st->nmarked != 0 iff some edge was marked)
+hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);
+hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s);
 hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStream_t s);
 hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s);
 

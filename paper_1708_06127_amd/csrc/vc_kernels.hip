@@ -65,6 +65,12 @@ __device__ __forceinline__ unsigned long long grp_max(unsigned long long v) {
   return v;
 }
 template <int G>
+__device__ __forceinline__ unsigned long long grp_min(unsigned long long v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off, G));
+  return v;
+}
+template <int G>
 __device__ __forceinline__ unsigned long long grp_sum(unsigned long long v) {
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
@@ -119,6 +125,16 @@ __device__ __forceinline__ int bits_for(int32_t k) {  // bits to hold values 0..
   return b;
 }
 
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
 // ------------------------------------------------------------ basic kernels
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t count) {
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
@@ -157,37 +173,54 @@ __global__ void k_check_rowptr(const int32_t *rp, int32_t n, int64_t nnz, Status
   if (bad) atomicOr(&st->err, ERR_ROWPTR);
 }
 
-// Degree classes: vertex lists per bin (capacity n each) + counts + max row length.
-__global__ void k_build_bins(const int32_t *rp, int32_t n, int64_t stride, int32_t *bins, Status *st) {
-  if (st->err) return;
-  int dmax = 0;
-  for (int64_t base = blockIdx.x * (int64_t)kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
-    int64_t v = base + threadIdx.x;
-    bool act = v < n;
-    int32_t d = act ? rp[v + 1] - rp[v] : 0;
-    int b = act ? degree_bin(d) : -1;
-    dmax = d > dmax ? d : dmax;
-    // wave-aggregated append per bin
-    unsigned long long todo = __ballot(act);
-    while (todo) {
-      int leader = __ffsll((long long)todo) - 1;
-      int lb = __shfl(b, leader);
-      unsigned long long peers = __ballot(act && b == lb);
-      int lane = threadIdx.x & 63;
-      unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-      int rank = __popcll(peers & lt);
-      int base_pos = 0;
-      if (lane == leader) base_pos = atomicAdd(&st->bin_cnt[lb], __popcll(peers));
-      base_pos = __shfl(base_pos, leader);
-      if (act && b == lb) bins[(int64_t)lb * stride + base_pos + rank] = (int32_t)v;
-      todo &= ~peers;
-    }
+// Arc tiles: tile t starts at the first row v with rp[v] + v >= t * kTile.
+// meta[t] = {first row, short rows, first arc, arcs of the short rows}; a
+// trailing row with >= kTile arcs is excluded (the long-row kernels take it).
+__device__ __forceinline__ int32_t tile_start(const int32_t *rp, int32_t n, int64_t target) {
+  int32_t lo = 0, hi = n;  // rp[n] + n >= target for every tile start
+  while (lo < hi) {
+    int32_t mid = (lo + hi) >> 1;
+    if ((int64_t)rp[mid] + mid < target) lo = mid + 1; else hi = mid;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    int o = __shfl_xor(dmax, off, 64);
-    dmax = o > dmax ? o : dmax;
+  return lo;
+}
+__global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta) {
+  for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * kBlock) {
+    const int32_t r0 = tile_start(rp, n, t * (int64_t)kTile);
+    int32_t r1 = t + 1 == ntiles ? n : tile_start(rp, n, (t + 1) * (int64_t)kTile);
+    if (r1 > r0 && rp[r1] - rp[r1 - 1] >= kTile) r1--;
+    meta[t] = make_int4(r0, r1 - r0, rp[r0], rp[r1] - rp[r0]);
   }
-  if ((threadIdx.x & 63) == 0 && dmax > 0) atomicMax(&st->dmax, dmax);
+}
+
+// largest j in [0, rows) with s_rp[j] <= i (the row holding local arc i)
+__device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int32_t i) {
+  int32_t lo = 0, hi = rows - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (s_rp[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Lists of long rows (classes 4-6 of degree_bin), appended per workgroup:
+// LDS counters, then one global reservation per class and workgroup.
+__global__ void k_long_rows(const int32_t *rp, int32_t n, int64_t stride, int32_t *bins, Status *st) {
+  __shared__ int32_t cnt[3], base[3];
+  for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t v = b0 + threadIdx.x;
+    const int32_t d = v < n ? rp[v + 1] - rp[v] : 0;
+    const int cls = d >= kTile ? degree_bin(d) - 4 : -1;
+    const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < 3)
+      base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&st->bin_cnt[4 + threadIdx.x], cnt[threadIdx.x]) : 0;
+    __syncthreads();
+    if (cls >= 0) bins[(int64_t)(4 + cls) * stride + base[cls] + pos] = (int32_t)v;
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ LP iteration 1
@@ -315,6 +348,234 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
       uint32_t S_own = own_sh[gi];
       if (end == beg || (uint32_t)(best >> 32) == S_own) Lout[v] = own;
       else Lout[v] = key_label(best, salt);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ tiled LP (short rows)
+// A tile's arcs are split into 256 runs of q = ceil(arcs/256) <= 8
+// consecutive arcs, one per thread. Every global load of a thread's run is
+// issued before the barrier that publishes the tile's row offsets in LDS;
+// the row of each arc is then found by one binary search and a forward walk.
+
+// Iteration 1 on a tile: running (w, -prio) maximum and weight sum per row
+// run, flushed to per-row LDS slots; one thread per row writes the label. At
+// level 0 the pass also validates arcs and yields degrees, and each block
+// leaves its minimum-degree key, weight sum and error bits in `part`.
+template <bool L0>
+__global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ w, int32_t n,
+                                                        const int4 *__restrict__ meta, int32_t ntiles,
+                                                        int32_t *__restrict__ L, long long *__restrict__ deg,
+                                                        uint32_t salt, const Status *st,
+                                                        unsigned long long *__restrict__ part) {
+  __shared__ int32_t s_rp[kTile + 1];
+  __shared__ unsigned long long s_best[kTile];
+  __shared__ unsigned long long s_sum[kTile];
+  const bool bad = st->err != 0;
+  unsigned long long mykey = ~0ull, mysum = 0;
+  int myerr = 0;
+  for (int32_t t = blockIdx.x; t < ntiles && !bad; t += gridDim.x) {
+    const int4 m = meta[t];
+    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t i0 = threadIdx.x * q;
+    int32_t xs[kPerThread], cs[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++) {
+      const bool ok = k < q && i0 + k < acnt;
+      xs[k] = ok ? col[a0 + i0 + k] : 0;
+      cs[k] = ok ? w[a0 + i0 + k] : 0;
+    }
+    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    for (int j = threadIdx.x; j < rows; j += kTB) {
+      s_best[j] = 0;
+      s_sum[j] = 0;
+    }
+    __syncthreads();
+    if (i0 < acnt) {
+      int32_t j = row_of(s_rp, rows, i0);
+      unsigned long long best = 0, sum = 0;
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {
+        const int32_t i = i0 + k;
+        if (k < q && i < acnt) {
+          if (i >= s_rp[j + 1]) {
+            atomicMax(&s_best[j], best);
+            if (L0) atomicAdd(&s_sum[j], sum);
+            best = 0;
+            sum = 0;
+            do { j++; } while (i >= s_rp[j + 1]);
+          }
+          const int32_t x = xs[k], c = cs[k];
+          if (L0) {
+            if (x < 0 || x >= n) myerr |= ERR_COL;
+            if (x == r0 + j) myerr |= ERR_SELF;
+            if (c < 1) myerr |= ERR_WEIGHT;
+            sum += (unsigned long long)(uint32_t)c;
+          }
+          best = umax64(best, cand_key((uint32_t)c, x, salt));
+        }
+      }
+      atomicMax(&s_best[j], best);
+      if (L0) atomicAdd(&s_sum[j], sum);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < rows; j += kTB) {
+      const int32_t v = r0 + j;
+      L[v] = s_rp[j + 1] > s_rp[j] ? key_label(s_best[j], salt) : v;
+      if (L0) {
+        const unsigned long long d = s_sum[j];
+        deg[v] = (long long)d;
+        mykey = umin64(mykey, ((d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d) << 32) | (uint32_t)v);
+        mysum += d;
+      }
+    }
+    __syncthreads();
+  }
+  if (L0) {
+    const unsigned long long k = grp_min<64>(mykey);
+    const unsigned long long sm = grp_sum<64>(mysum);
+    const int e = grp_or<64>(myerr);
+    if (threadIdx.x == 0) {
+      part[3 * (int64_t)blockIdx.x] = k;
+      part[3 * (int64_t)blockIdx.x + 1] = sm;
+      part[3 * (int64_t)blockIdx.x + 2] = (unsigned long long)e;
+    }
+  }
+}
+
+// combine per-block (min key, weight sum, error bits) into the status
+__global__ void k_reduce_parts(const unsigned long long *part, int32_t count, Status *st) {
+  __shared__ unsigned long long red[kBlock / 64];
+  unsigned long long k = ~0ull, sm = 0, e = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
+    k = umin64(k, part[3 * i]);
+    sm += part[3 * i + 1];
+    e |= part[3 * i + 2];
+  }
+  k = block_min(k, red);
+  sm = block_sum(sm, red);
+  e = block_max(e, red);  // error bits are few: the maximum is nonzero iff any bit is set
+  if (threadIdx.x == 0) {
+    if (k != ~0ull) atomicMin(&st->minkey, k);
+    if (sm) atomicAdd(&st->wsum, sm);
+    if (e) atomicOr(&st->err, (int)e);
+  }
+}
+
+// Iteration t >= 2 on a tile. Row j of the tile owns the hash region
+// [2*s_rp[j], 2*s_rp[j+1]) of the tile's LDS table (twice its arc count, so
+// probing always ends), keyed by neighbour label and summing weights. A
+// thread inserts its q arcs and then scans the 2q table slots of the same
+// rows, so the row of every slot is known without a search.
+__global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
+                                                     int32_t *__restrict__ Lout, const int4 *__restrict__ meta,
+                                                     int32_t ntiles, uint32_t salt, const Status *st) {
+  __shared__ int32_t s_rp[kTile + 1];
+  __shared__ int32_t s_own[kTile];
+  __shared__ uint32_t s_ownS[kTile];
+  __shared__ unsigned long long s_best[kTile];
+  __shared__ int32_t tkey[2 * kTileArcs];
+  __shared__ uint32_t tval[2 * kTileArcs];
+  if (st->err) return;
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 m = meta[t];
+    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t i0 = threadIdx.x * q;
+    int32_t xs[kPerThread], cs[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++) {
+      const bool ok = k < q && i0 + k < acnt;
+      xs[k] = ok ? col[a0 + i0 + k] : 0;
+      cs[k] = ok ? w[a0 + i0 + k] : 0;
+    }
+    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    for (int j = threadIdx.x; j < rows; j += kTB) {
+      s_own[j] = Lin[r0 + j];
+      s_ownS[j] = 0;
+      s_best[j] = 0;
+    }
+    for (int e = threadIdx.x; e < 2 * acnt; e += kTB) {
+      tkey[e] = -1;
+      tval[e] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++)
+      if (k < q && i0 + k < acnt) xs[k] = Lin[xs[k]];
+    __syncthreads();
+    const int32_t iend = min(i0 + q, acnt);
+    const int32_t j0 = i0 < acnt ? row_of(s_rp, rows, i0) : 0;
+    if (i0 < acnt) {
+      int32_t j = j0;
+      int32_t px = -1;
+      uint32_t pc = 0;
+      auto insert = [&](int32_t row, int32_t x, uint32_t c) {
+        const int32_t base = 2 * s_rp[row];
+        const uint32_t size = 2u * (uint32_t)(s_rp[row + 1] - s_rp[row]);
+        uint32_t h = (uint32_t)(((unsigned long long)slot_hash(x) * size) >> 32);
+        while (true) {
+          const int32_t k = tkey[base + h];
+          if (k == x) break;
+          if (k == -1) {
+            const int32_t old = atomicCAS(&tkey[base + h], -1, x);
+            if (old == -1 || old == x) break;
+          }
+          h = (h + 1 == size) ? 0 : h + 1;
+        }
+        atomicAdd(&tval[base + h], c);
+      };
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {
+        const int32_t i = i0 + k;
+        if (k < q && i < acnt) {
+          if (i >= s_rp[j + 1]) {
+            if (px >= 0) insert(j, px, pc);
+            px = -1;
+            do { j++; } while (i >= s_rp[j + 1]);
+          }
+          const int32_t x = xs[k];
+          const uint32_t c = (uint32_t)cs[k];
+          if (x == px) {
+            pc += c;  // consecutive arcs with the same label: one insertion
+          } else {
+            if (px >= 0) insert(j, px, pc);
+            px = x;
+            pc = c;
+          }
+        }
+      }
+      if (px >= 0) insert(j, px, pc);
+    }
+    __syncthreads();
+    if (i0 < acnt) {
+      int32_t j = j0;
+      unsigned long long best = 0;
+      for (int32_t e = 2 * i0; e < 2 * iend; e++) {
+        if (e >= 2 * s_rp[j + 1]) {
+          atomicMax(&s_best[j], best);
+          best = 0;
+          do { j++; } while (e >= 2 * s_rp[j + 1]);
+        }
+        const int32_t k = tkey[e];
+        if (k >= 0) {
+          const uint32_t S = tval[e];
+          best = umax64(best, cand_key(S, k, salt));
+          if (k == s_own[j]) s_ownS[j] = S;
+        }
+      }
+      atomicMax(&s_best[j], best);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < rows; j += kTB) {
+      const int32_t own = s_own[j];
+      if (s_rp[j + 1] == s_rp[j]) { Lout[r0 + j] = own; continue; }
+      const unsigned long long b = s_best[j];
+      Lout[r0 + j] = ((uint32_t)(b >> 32) == s_ownS[j]) ? own : key_label(b, salt);
     }
     __syncthreads();
   }
@@ -530,15 +791,6 @@ __global__ void k_validate_sym(const int32_t *rp, const int32_t *col, const int3
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 
-__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  return x;
-}
 // exclusive scan of one value per thread across the block; returns the block total
 __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t &total, int32_t *sh) {
   int32_t inc = wave_incl_scan(x);
@@ -615,50 +867,207 @@ __global__ void k_iota(int32_t *p, int32_t n) {
 }
 
 // ------------------------------------------------------------ contraction
-// per vertex: number of arcs leaving its cluster
-__global__ void k_count_inter(const int32_t *rp, const int32_t *col, const int32_t *cl, int32_t n, int32_t *cnt) {
-  constexpr int G = 16;
-  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
-  for (int64_t base = blockIdx.x * (int64_t)(kBlock / G); base < n; base += (int64_t)gridDim.x * (kBlock / G)) {
-    int64_t v = base + gi;
-    unsigned long long c = 0;
-    int32_t cv = 0;
-    if (v < n) {
-      cv = cl[v];
-      for (int32_t i = rp[v] + lane; i < rp[v + 1]; i += G) c += cl[col[i]] != cv;
+// Inter-cluster arcs, written compacted (in arc order) into the source
+// segment's own arc range of the triple buffer: segment s = tile s, or long
+// row (class 5 / 6) after the tiles. seg[2s] = first arc, seg[2s+1] = count.
+// A scan over the counts and k_compact then pack the segments.
+__device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus, const int32_t *cs, int q,
+                                           int32_t i0, int32_t acnt, const int32_t *s_rp, int32_t rows,
+                                           const int32_t *s_cl, int32_t cl_row, int key_bits, int64_t out0,
+                                           unsigned long long *keys, int32_t *vals, int32_t *sh,
+                                           int32_t &total) {
+  unsigned long long k[kPerThread];
+  uint32_t fl = 0;
+  if (i0 < acnt) {
+    int32_t j = s_rp ? row_of(s_rp, rows, i0) : 0;
+#pragma unroll
+    for (int m = 0; m < kPerThread; m++) {
+      const int32_t i = i0 + m;
+      k[m] = 0;
+      if (m < q && i < acnt) {
+        if (s_rp)
+          while (i >= s_rp[j + 1]) j++;
+        const int32_t cv = s_rp ? s_cl[j] : cl_row;
+        if (cus[m] != cv) {
+          k[m] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cus[m];
+          fl |= 1u << m;
+        }
+      }
     }
-    c = grp_sum<G>(c);
-    if (v < n && lane == 0) cnt[v] = (int32_t)c;
+  }
+  const int32_t off = block_excl_scan(__popc(fl), total, sh);
+#pragma unroll
+  for (int m = 0; m < kPerThread; m++)
+    if (fl & (1u << m)) {
+      const int64_t o = out0 + off + __popc(fl & ((1u << m) - 1));
+      keys[o] = k[m];
+      vals[o] = cs[m];
+    }
+  (void)xs;
+}
+
+// Tile emission with a combiner: the tile's inter-cluster arcs are first
+// summed per (cl(u), cl(v)) pair in an LDS hash table, and only the distinct
+// pairs are written (the sort and the final segmented sum are insensitive to
+// how a pair's weight is split).
+constexpr int kCombSlots = kTileArcs;  // > arcs of a tile, so probing ends
+__global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
+                                                       const int4 *__restrict__ meta, int32_t ntiles,
+                                                       const Status *st, unsigned long long *__restrict__ keys,
+                                                       int32_t *__restrict__ vals, int32_t *__restrict__ seg) {
+  __shared__ int32_t s_rp[kTile + 1];
+  __shared__ int32_t s_cl[kTile];
+  __shared__ unsigned long long tkey[kCombSlots];
+  __shared__ uint32_t tval[kCombSlots];
+  const int key_bits = bits_for(st->k);
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 m = meta[t];
+    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t i0 = threadIdx.x * q;
+    int32_t xs[kPerThread], cs[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++) {
+      const bool ok = k < q && i0 + k < acnt;
+      xs[k] = ok ? col[a0 + i0 + k] : 0;
+      cs[k] = ok ? w[a0 + i0 + k] : 0;
+    }
+    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    for (int j = threadIdx.x; j < rows; j += kTB) s_cl[j] = cl[r0 + j];
+    for (int e = threadIdx.x; e < kCombSlots; e += kTB) {
+      tkey[e] = ~0ull;
+      tval[e] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++)
+      if (k < q && i0 + k < acnt) xs[k] = cl[xs[k]];
+    __syncthreads();
+    if (i0 < acnt) {
+      int32_t j = row_of(s_rp, rows, i0);
+      unsigned long long pk = ~0ull;
+      uint32_t pc = 0;
+      auto insert = [&](unsigned long long key, uint32_t c) {
+        const uint32_t fold = (uint32_t)key ^ (uint32_t)(key >> 32);
+        uint32_t h = (fold * 2654435761u) & (kCombSlots - 1);
+        while (true) {
+          const unsigned long long k = tkey[h];
+          if (k == key) break;
+          if (k == ~0ull) {
+            const unsigned long long old = atomicCAS(&tkey[h], ~0ull, key);
+            if (old == ~0ull || old == key) break;
+          }
+          h = (h + 1) & (kCombSlots - 1);
+        }
+        atomicAdd(&tval[h], c);
+      };
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {
+        const int32_t i = i0 + k;
+        if (k < q && i < acnt) {
+          while (i >= s_rp[j + 1]) j++;
+          const int32_t cv = s_cl[j], cu = xs[k];
+          if (cu != cv) {
+            const unsigned long long key = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cu;
+            if (key == pk) {
+              pc += (uint32_t)cs[k];
+            } else {
+              if (pk != ~0ull) insert(pk, pc);
+              pk = key;
+              pc = (uint32_t)cs[k];
+            }
+          }
+        }
+      }
+      if (pk != ~0ull) insert(pk, pc);
+    }
+    __syncthreads();
+    // compact the distinct pairs into the tile's region
+    constexpr int kSlotsPerThread = kCombSlots / kTB;
+    uint32_t fl = 0;
+#pragma unroll
+    for (int k = 0; k < kSlotsPerThread; k++)
+      if (tkey[threadIdx.x * kSlotsPerThread + k] != ~0ull) fl |= 1u << k;
+    const int32_t cnt = __popc(fl);
+    const int32_t inc = wave_incl_scan(cnt);
+    const int32_t off = inc - cnt, tot = __shfl(inc, 63, 64);
+#pragma unroll
+    for (int k = 0; k < kSlotsPerThread; k++)
+      if (fl & (1u << k)) {
+        const int64_t o = (int64_t)a0 + off + __popc(fl & ((1u << k) - 1));
+        keys[o] = tkey[threadIdx.x * kSlotsPerThread + k];
+        vals[o] = (int32_t)tval[threadIdx.x * kSlotsPerThread + k];
+      }
+    if (threadIdx.x == 0) {
+      seg[2 * (int64_t)t] = a0;
+      seg[2 * (int64_t)t + 1] = tot;
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_emit(const int32_t *rp, const int32_t *col, const int32_t *w, const int32_t *cl, int32_t n,
-                       const int32_t *off, const Status *st, unsigned long long *keys, int32_t *vals) {
-  constexpr int G = 16;
+// long rows: one workgroup per row, chunks of kBlock * kPerThread arcs
+__global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
+                                                       const int32_t *list, const int32_t *cnt_p, const Status *st,
+                                                       unsigned long long *__restrict__ keys,
+                                                       int32_t *__restrict__ vals, int32_t *__restrict__ seg) {
+  __shared__ int32_t sh[kBlock / 64];
   const int key_bits = bits_for(st->k);
-  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
-  for (int64_t base = blockIdx.x * (int64_t)(kBlock / G); base < n; base += (int64_t)gridDim.x * (kBlock / G)) {
-    int64_t v = base + gi;
-    if (v >= n) continue;
-    const int32_t cv = cl[v];
-    int32_t o = off[v];
-    // ordered compaction of the row's inter-cluster arcs, G arcs at a time
-    for (int32_t i0 = rp[v]; i0 < rp[v + 1]; i0 += G) {
-      int32_t i = i0 + lane;
-      bool ok = false;
-      int32_t cu = 0;
-      if (i < rp[v + 1]) { cu = cl[col[i]]; ok = cu != cv; }
-      unsigned long long bal = __ballot(ok);
-      const int wl = threadIdx.x & 63, gbase = wl & ~(G - 1);
-      unsigned long long gm = (bal >> gbase) & ((G == 64) ? ~0ull : ((1ull << G) - 1));
-      int rank = __popcll(gm & ((1ull << lane) - 1));
-      if (ok) {
-        keys[o + rank] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cu;
-        vals[o + rank] = w[i];
+  const int32_t cnt = *cnt_p;
+  for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+    const int32_t v0 = list[r];
+    const int32_t cv = cl[v0];
+    const int32_t beg = rp[v0], end = rp[v0 + 1];
+    int64_t out = beg;
+    for (int32_t c0 = beg; c0 < end; c0 += kBlock * kPerThread) {
+      const int32_t acnt = min(kBlock * kPerThread, end - c0);
+      const int32_t i0 = threadIdx.x * kPerThread;
+      int32_t cus[kPerThread], cs[kPerThread];
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {
+        const bool ok = i0 + k < acnt;
+        cus[k] = ok ? col[c0 + i0 + k] : 0;
+        cs[k] = ok ? w[c0 + i0 + k] : 0;
       }
-      o += __popcll(gm);
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++)
+        if (i0 + k < acnt) cus[k] = cl[cus[k]];
+      int32_t tot;
+      emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, key_bits, out, keys, vals, sh, tot);
+      out += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      seg[2 * (int64_t)r] = beg;
+      seg[2 * (int64_t)r + 1] = (int32_t)(out - beg);
     }
   }
+}
+
+// pack the segments into buffer 1: output element e comes from the last
+// segment s with off[s] <= e (binary search of the exclusive offsets), so the
+// work is balanced whatever the segment lengths
+__global__ void k_compact(const int32_t *seg, const int32_t *off, int32_t nseg, const Status *st,
+                          const unsigned long long *kin, const int32_t *vin, unsigned long long *kout,
+                          int32_t *vout) {
+  const int64_t total = st->ax;
+  for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
+    int32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int64_t src = seg[2 * (int64_t)lo] + (e - off[lo]);
+    kout[e] = kin[src];
+    vout[e] = vin[src];
+  }
+}
+
+// counts of the interleaved (first arc, count) segment table
+__global__ void k_seg_counts(const int32_t *seg, int32_t nseg, int32_t *cnt) {
+  for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * kBlock)
+    cnt[s] = seg[2 * s + 1];
 }
 
 // ---- LSD radix sort of (u64 key, i32 value), 8-bit digits, stable
@@ -669,10 +1078,20 @@ __global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shi
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  int64_t base = blockIdx.x * (int64_t)kRsTile;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = blockIdx.x * (int64_t)kRsTile + (int64_t)wid * 64 * kRsItems;
+  const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (int j = 0; j < kRsItems; j++) {
-    int64_t i = base + j * kBlock + threadIdx.x;
-    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+    const int64_t i = base + j * 64 + lane;
+    const bool ok = i < count;
+    const int d = ok ? (int)((keys[i] >> shift) & 255) : 0;
+    unsigned long long peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const unsigned long long bb = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    if (ok && (peers & lt) == 0) atomicAdd(&h[d], __popcll(peers));
   }
   __syncthreads();
   hist[threadIdx.x * (int64_t)tiles + blockIdx.x] = h[threadIdx.x];
@@ -881,30 +1300,217 @@ __global__ __launch_bounds__(kBlock) void k_pr_mark(const int32_t *__restrict__ 
   if (threadIdx.x == 0 && nm) atomicAdd(&st->nmarked, (int32_t)nm);
 }
 
+// Arc-parallel marking on the tiles: each thread tests its arcs (v, x) with
+// v < x. Conditions 1 and 2 need only the weights and degrees; 3 and 4 need
+// the common neighbourhood, intersected sequentially by the thread when the
+// shorter row has at most kPrSeq entries, otherwise the arc is queued for a
+// wave (k_pr_heavy). `flag` records that some edge was marked.
+constexpr int kPrSeq = 64;
+
+__device__ __forceinline__ bool pr_cheap(long long c, long long dv, long long dx, long long lam) {
+  return c >= lam || dv < 2 * c || dx < 2 * c;
+}
+// conditions 3 and 4 by a sequential intersection of sorted rows
+__device__ bool pr_intersect_seq(const int32_t *col, const int32_t *w, int32_t vb, int32_t ve, int32_t xb, int32_t xe,
+                                 long long c, long long dv, long long dx, long long lam) {
+  const bool v_short = (ve - vb) <= (xe - xb);
+  const int32_t sb = v_short ? vb : xb, se = v_short ? ve : xe;
+  const int32_t lb = v_short ? xb : vb, le = v_short ? xe : ve;
+  long long sum4 = c;
+  int32_t lo = lb;
+  for (int32_t j = sb; j < se; j++) {
+    const int32_t u = col[j];
+    int32_t hi = le;  // rows are sorted: the search window only moves right
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if (col[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    if (lo < le && col[lo] == u) {
+      const long long cvu = v_short ? w[j] : w[lo];
+      const long long cxu = v_short ? w[lo] : w[j];
+      if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
+      sum4 += cvu < cxu ? cvu : cxu;
+      if (sum4 >= lam) return true;
+    }
+  }
+  return sum4 >= lam;
+}
+
+__device__ __forceinline__ void pr_arc(const int32_t *rp, const int32_t *col, const int32_t *w,
+                                       const unsigned long long *degu, int32_t v, int32_t i, long long lam,
+                                       uint8_t *mark, int32_t *heavy, Status *st, bool &any) {
+  const int32_t x = col[i];
+  if (x <= v) { mark[i] = 0; return; }
+  const long long c = w[i];
+  const long long dv = (long long)degu[v], dx = (long long)degu[x];
+  bool m = pr_cheap(c, dv, dx, lam);
+  if (!m) {
+    const int32_t vb = rp[v], ve = rp[v + 1], xb = rp[x], xe = rp[x + 1];
+    if (min(ve - vb, xe - xb) > kPrSeq) {
+      heavy[atomicAdd(&st->huge_items, 1)] = i;  // decided by k_pr_heavy
+      mark[i] = 0;
+      return;
+    }
+    m = pr_intersect_seq(col, w, vb, ve, xb, xe, c, dv, dx, lam);
+  }
+  mark[i] = m ? 1 : 0;
+  any = any || m;
+}
+
+__global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ w,
+                                                     const unsigned long long *__restrict__ degu,
+                                                     const int4 *__restrict__ meta, int32_t ntiles,
+                                                     uint8_t *__restrict__ mark, int32_t *heavy, Status *st) {
+  __shared__ int32_t s_rp[kTile + 1];
+  __shared__ int s_any;
+  const long long lam = st->lam_hat;
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 m = meta[t];
+    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t i0 = threadIdx.x * q;
+    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    bool any = false;
+    if (i0 < acnt) {
+      int32_t j = row_of(s_rp, rows, i0);
+      const int32_t iend = min(i0 + q, acnt);
+      for (int32_t i = i0; i < iend; i++) {
+        while (i >= s_rp[j + 1]) j++;
+        pr_arc(rp, col, w, degu, r0 + j, a0 + i, lam, mark, heavy, st, any);
+      }
+    }
+    if (any) s_any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_any && st->nmarked == 0) atomicExch(&st->nmarked, 1);
+    __syncthreads();
+  }
+}
+
+__global__ void k_pr_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                          const int32_t *__restrict__ w, const unsigned long long *__restrict__ degu,
+                          const int32_t *list, const int32_t *cnt_p, uint8_t *__restrict__ mark, int32_t *heavy,
+                          Status *st) {
+  __shared__ int s_any;
+  const long long lam = st->lam_hat;
+  const int32_t cnt = *cnt_p;
+  for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+    const int32_t v = list[r];
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    bool any = false;
+    for (int32_t i = rp[v] + threadIdx.x; i < rp[v + 1]; i += kBlock)
+      pr_arc(rp, col, w, degu, v, i, lam, mark, heavy, st, any);
+    if (any) s_any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_any && st->nmarked == 0) atomicExch(&st->nmarked, 1);
+    __syncthreads();
+  }
+}
+
+// queued arcs: one wave each, lanes over the shorter row
+__global__ void k_pr_heavy(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const int32_t *__restrict__ w, const unsigned long long *__restrict__ degu, int32_t n,
+                           const int32_t *heavy, uint8_t *__restrict__ mark, Status *st) {
+  const long long lam = st->lam_hat;
+  const int32_t cnt = st->huge_items;
+  const int lane = threadIdx.x & 63;
+  for (int64_t h = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; h < cnt; h += ((int64_t)gridDim.x * kBlock) >> 6) {
+    const int32_t i = heavy[h];
+    // the row of arc i: largest v with rp[v] <= i
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int32_t mid = (lo + hi + 1) >> 1;
+      if (rp[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const int32_t v = lo, x = col[i];
+    const long long c = w[i];
+    const long long dv = (long long)degu[v], dx = (long long)degu[x];
+    const int32_t vb = rp[v], ve = rp[v + 1], xb = rp[x], xe = rp[x + 1];
+    const bool v_short = (ve - vb) <= (xe - xb);
+    const int32_t sb = v_short ? vb : xb, se = v_short ? ve : xe;
+    const int32_t lb = v_short ? xb : vb, le = v_short ? xe : ve;
+    unsigned long long sum4 = 0;
+    int pr3 = 0;
+    for (int32_t j = sb + lane; j < se; j += 64) {
+      const int32_t u = col[j];
+      int32_t a = lb, b = le;
+      while (a < b) {
+        int32_t mid = (a + b) >> 1;
+        if (col[mid] < u) a = mid + 1; else b = mid;
+      }
+      if (a < le && col[a] == u) {
+        const long long cvu = v_short ? w[j] : w[a];
+        const long long cxu = v_short ? w[a] : w[j];
+        if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) pr3 = 1;
+        sum4 += (unsigned long long)(cvu < cxu ? cvu : cxu);
+      }
+    }
+    sum4 = grp_sum<64>(sum4);
+    pr3 = grp_or<64>(pr3);
+    const bool m = pr3 || (c + (long long)sum4 >= lam);
+    if (lane == 0) {
+      mark[i] = m ? 1 : 0;
+      if (m && st->nmarked == 0) atomicExch(&st->nmarked, 1);
+    }
+  }
+}
+
 // ------------------------------------------------------------ union-find
+// Root of x with path halving. Only non-roots are rewritten, and always to
+// one of their ancestors, so concurrent halving and linking stay consistent.
 __device__ __forceinline__ int32_t uf_root(int32_t *parent, int32_t x) {
   while (true) {
     int32_t p = __hip_atomic_load(&parent[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (p == x) return x;
-    x = p;
+    int32_t gp = __hip_atomic_load(&parent[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gp != p) __hip_atomic_store(&parent[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    x = gp;
   }
 }
 // link the larger root under the smaller one: each component's root ends as
 // its smallest vertex id, independent of the order of the links
-__global__ void k_uf_link(const int32_t *rp, const int32_t *col, const uint8_t *mark, int32_t n, int32_t *parent) {
-  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
-    for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
-      if (!mark[i]) continue;
-      int32_t a = (int32_t)v, b = col[i];
-      while (true) {
-        a = uf_root(parent, a);
-        b = uf_root(parent, b);
-        if (a == b) break;
-        if (a > b) { int32_t t = a; a = b; b = t; }
-        int32_t old = atomicCAS(&parent[b], b, a);
-        if (old == b) break;
+__device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) {
+  while (true) {
+    a = uf_root(parent, a);
+    b = uf_root(parent, b);
+    if (a == b) return;
+    if (a > b) { int32_t t = a; a = b; b = t; }
+    if (atomicCAS(&parent[b], b, a) == b) return;
+  }
+}
+__global__ void k_uf_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                          const uint8_t *__restrict__ mark, const int4 *__restrict__ meta, int32_t ntiles,
+                          int32_t *parent) {
+  __shared__ int32_t s_rp[kTile + 1];
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 m = meta[t];
+    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t i0 = threadIdx.x * q;
+    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    __syncthreads();
+    if (i0 < acnt) {
+      int32_t j = row_of(s_rp, rows, i0);
+      const int32_t iend = min(i0 + q, acnt);
+      for (int32_t i = i0; i < iend; i++) {
+        while (i >= s_rp[j + 1]) j++;
+        if (mark[a0 + i]) uf_union(parent, r0 + j, col[a0 + i]);
       }
     }
+    __syncthreads();
+  }
+}
+__global__ void k_uf_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                          const uint8_t *__restrict__ mark, const int32_t *list, const int32_t *cnt_p,
+                          int32_t *parent) {
+  const int32_t cnt = *cnt_p;
+  for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+    const int32_t v = list[r];
+    for (int32_t i = rp[v] + threadIdx.x; i < rp[v + 1]; i += kBlock)
+      if (mark[i]) uf_union(parent, v, col[i]);
   }
 }
 __global__ void k_uf_compress(int32_t *parent, int32_t n, int32_t *rep) {
@@ -979,14 +1585,17 @@ hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t build_bins(const DGraph &g, Work &w, hipStream_t s) {
-  k_build_bins<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.n, w.n_in, w.bins, w.st);
+hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s) {
+  w.ntiles = (int32_t)((g.nnz + g.n + kTile - 1) / kTile);
+  k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta);
+  k_long_rows<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, w.n_in, w.bins, w.st);
   return hipGetLastError();
 }
 
 namespace {
 // items of bin b: host-known count (>= 0) or -1 when only the device knows it
 inline int64_t bin_items(const int32_t *known, int b, int64_t fallback) { return known ? known[b] : fallback; }
+inline int64_t long_rows_bound(const DGraph &g) { return g.nnz / kTile + 1; }
 
 template <int G>
 void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t *L, uint32_t salt, int level0,
@@ -1001,7 +1610,7 @@ void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t
 template <int G, int TBL>
 void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int32_t *Lin, int32_t *Lout,
                 uint32_t salt, hipStream_t s) {
-  const int64_t items = bin_items(known, b, g.n);
+  const int64_t items = bin_items(known, b, long_rows_bound(g));
   if (items <= 0) return;
   const int32_t *list = w.bins + (int64_t)b * w.n_in;
   k_lp_tab<G, TBL><<<grid_for(items, kBlock / G, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, list,
@@ -1012,12 +1621,25 @@ void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
                     hipStream_t s) {
   const int l0 = level0 ? 1 : 0;
-  launch_first<8>(g, w, 0, known, L, salt, l0, s);
-  launch_first<16>(g, w, 1, known, L, salt, l0, s);
-  launch_first<32>(g, w, 2, known, L, salt, l0, s);
-  launch_first<64>(g, w, 3, known, L, salt, l0, s);
-  launch_first<64>(g, w, 4, known, L, salt, l0, s);
-  launch_first<64>(g, w, 5, known, L, salt, l0, s);
+  const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
+  if (level0) {
+    k_first_tile<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt, w.st,
+                                             w.part);
+    k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
+  } else {
+    k_first_tile<false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt,
+                                              w.st, w.part);
+  }
+  // long rows: a wave per row up to 4096 arcs, chunked beyond
+  for (int b = 4; b <= 5; b++) {
+    const int64_t items = known ? known[b] : g.nnz / kTile + 1;
+    if (items > 0) {
+      const int32_t *list = w.bins + (int64_t)b * w.n_in;
+      k_lp_first<64><<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
+                                                                          &w.st->bin_cnt[b], L, w.deg, salt, l0,
+                                                                          w.st);
+    }
+  }
   if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
   // huge rows: chunked
   const int32_t *list6 = w.bins + 6ll * w.n_in;
@@ -1034,11 +1656,9 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
 
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
                    hipStream_t s) {
-  launch_tab<8, 16>(g, w, 0, known, Lin, Lout, salt, s);
-  launch_tab<16, 32>(g, w, 1, known, Lin, Lout, salt, s);
-  launch_tab<32, 64>(g, w, 2, known, Lin, Lout, salt, s);
-  launch_tab<64, 128>(g, w, 3, known, Lin, Lout, salt, s);
-  launch_tab<64, 1024>(g, w, 4, known, Lin, Lout, salt, s);
+  k_lp_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta,
+                                                               w.ntiles, salt, w.st);
+  launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s);
   launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s);
   if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
   const int32_t *list6 = w.bins + 6ll * w.n_in;
@@ -1080,17 +1700,29 @@ hipError_t init_map(Work &w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t contract_emit(const DGraph &g, Work &w, hipStream_t s) {
-  k_count_inter<<<grid_for(g.n, kBlock / 16), kBlock, 0, s>>>(g.row_ptr, g.col, w.cl, g.n, w.cnt);
-  hipError_t e = scan_exclusive(w.cnt, w.cnt, g.n, &w.st->ax, w.scan_tmp, w.scan_tmp_elems, s);
+hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s) {
+  const int64_t long_max = g.nnz / kTile + 1;
+  const int64_t nseg = w.ntiles + 3 * long_max;
+  hipError_t e = fill_i32(w.seg + 2ll * w.ntiles, 0, 6 * long_max, s);
   if (e != hipSuccess) return e;
-  k_emit<<<grid_for(g.n, kBlock / 16), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, g.n, w.cnt, w.st, w.keys[0],
-                                                        w.vals[0]);
+  k_emit_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles,
+                                                                 w.st, w.keys[0], w.vals[0], w.seg);
+  for (int b = 4; b <= 6; b++) {
+    const int64_t items = known ? known[b] : long_max;
+    if (items <= 0) continue;
+    int32_t *seg = w.seg + 2 * (w.ntiles + (b - 4) * long_max);
+    k_emit_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in,
+                                                            &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0], seg);
+  }
+  k_seg_counts<<<grid_for(nseg), kBlock, 0, s>>>(w.seg, (int32_t)nseg, w.seg_cnt);
+  e = scan_exclusive(w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, w.scan_tmp, w.scan_tmp_elems, s);
+  if (e != hipSuccess) return e;
+  k_compact<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st, w.keys[0],
+                                                              w.vals[0], w.keys[1], w.vals[1]);
   return hipGetLastError();
 }
 
 hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s) {
-  which = 0;
   if (count <= 1) return hipSuccess;
   const int32_t tiles = (int32_t)((count + kRsTile - 1) / kRsTile);
   for (int shift = 0; shift < total_bits; shift += 8) {
@@ -1145,18 +1777,34 @@ hipError_t reset_bins(Work &w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t pr_mark(const DGraph &g, Work &w, hipStream_t s) {
+hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s) {
   hipError_t e = fill_i32(&w.st->nmarked, 0, 1, s);
+  if (e == hipSuccess) e = fill_i32(&w.st->huge_items, 0, 1, s);
   if (e != hipSuccess) return e;
-  k_pr_mark<<<grid_for(g.n, kBlock / 16, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w,
-                                                                 (const unsigned long long *)w.deg, g.n, w.mark,
-                                                                 w.st);
+  const unsigned long long *degu = (const unsigned long long *)w.deg;
+  int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
+  k_pr_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles,
+                                                               w.mark, heavy, w.st);
+  for (int b = 4; b <= 6; b++) {
+    const int64_t items = known ? known[b] : g.nnz / kTile + 1;
+    if (items <= 0) continue;
+    k_pr_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.bins + (int64_t)b * w.n_in,
+                                                          &w.st->bin_cnt[b], w.mark, heavy, w.st);
+  }
+  k_pr_heavy<<<1024, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, g.n, heavy, w.mark, w.st);
   return hipGetLastError();
 }
 
-hipError_t union_find(const DGraph &g, Work &w, int32_t *rep, hipStream_t s) {
+hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s) {
   k_iota<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n);
-  k_uf_link<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.col, w.mark, g.n, w.parent);
+  k_uf_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, w.mark, w.tile_meta, w.ntiles,
+                                                               w.parent);
+  for (int b = 4; b <= 6; b++) {
+    const int64_t items = known ? known[b] : g.nnz / kTile + 1;
+    if (items <= 0) continue;
+    k_uf_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, w.mark, w.bins + (int64_t)b * w.n_in,
+                                                          &w.st->bin_cnt[b], w.parent);
+  }
   k_uf_compress<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n, rep);
   return hipGetLastError();
 }

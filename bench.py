@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rhg2p20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the graphs are solved on a single device "
@@ -76,6 +78,12 @@ def main():
     import paper_1708_06127_amd as vc
 
     wl = WORKLOADS[args.workload]
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     g = make_graph(args.workload)
     print("# generated %s: n=%d m=%d in %.1f s" % (args.workload, g.n, g.m, time.perf_counter() - t0),

@@ -201,8 +201,15 @@ def c4_params(count: int = 4096, seed: int = 3):
     return [(int(ns[i]), float(ds[i]), int(kx[i]), 1, 100, seed + i) for i in range(count)]
 
 
-def c4_batch(count: int = 4096, seed: int = 3):
-    return [planted(*p) for p in c4_params(count, seed)]
+def c4_batch(count: int = 4096, seed: int = 3, members=None, threads: int = 0):
+    """The planted batch (or the listed members of it), generated on a
+    thread pool (the generator releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ps = c4_params(count, seed)
+    idx = list(range(count)) if members is None else list(members)
+    threads = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda i: planted(*ps[i]), idx))
 
 
 def c5_request_params(count: int, seed: int = 4):

@@ -235,3 +235,103 @@ def validate(row_ptr, col, w, *, check_symmetry=True, stream=None) -> int:
     """Device-side input validation; returns the status code (0 = valid)."""
     g = csr(row_ptr, col, w)
     return int(load().viecut_validate(ctypes.byref(g), F_VALIDATE if check_symmetry else 0, _stream_ptr(stream)))
+
+
+def _graph_csrs(graphs):
+    cs = (Csr * max(len(graphs), 1))()
+    for i, (rp, col, w) in enumerate(graphs):
+        cs[i] = csr(rp, col, w)
+    return cs
+
+
+def batch_workspace_bytes(graphs, p: Params | None = None) -> int:
+    p = p or params()
+    return int(load().viecut_batch_workspace_bytes(_graph_csrs(graphs), len(graphs), ctypes.byref(p)))
+
+
+def mincut_batch(graphs, *, lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, ws=None, sides=None,
+                 stream=None):
+    """Solve many graphs (a list of (row_ptr, col, w) int32 CUDA tensors) in
+    one batched execution. Returns a list of (cut, side, info) tuples; a graph
+    whose input is invalid gets (None, side, info) with info["error"] set to
+    its status code, and the others are unaffected."""
+    torch = _torch()
+    lib = load()
+    count = len(graphs)
+    p = params(lp_iters, n0, max_rounds, seed, validate)
+    cs = _graph_csrs(graphs)
+    if sides is None:
+        sides = [torch.empty(max((rp.numel() - 1 + 63) // 64, 1), dtype=torch.int64, device=rp.device)
+                 for rp, _, _ in graphs]
+    sp_arr = (ctypes.c_void_p * max(count, 1))(*[s.data_ptr() for s in sides])
+    outs = (Result * max(count, 1))()
+    ws_ptr, ws_bytes = (ws.data_ptr(), ws.numel()) if ws is not None else (None, 0)
+    rc = lib.viecut_mincut_batch(cs, count, ctypes.byref(p), ws_ptr, ws_bytes, _stream_ptr(stream), outs, sp_arr)
+    _check(rc)
+    res = []
+    for i in range(count):
+        info = outs[i].as_dict()
+        if info["status"] & 0x80000000:
+            info["error"] = -(info["status"] & 0x7FFFFFFF)
+            res.append((None, sides[i], info))
+        else:
+            res.append((int(outs[i].cut), sides[i], info))
+    return res
+
+
+class Session:
+    """Served execution: requests stay resident on the device, are admitted
+    while they fit the memory budget, and advance one batched round per
+    step() together with the requests already in flight."""
+
+    def __init__(self, hbm_budget: int, *, lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False,
+                 stream=None):
+        lib = load()
+        self._p = params(lp_iters, n0, max_rounds, seed, validate)
+        self._h = ctypes.c_void_p()
+        self._keep = {}
+        _check(lib.viecut_session_create(int(hbm_budget), ctypes.byref(self._p), _stream_ptr(stream),
+                                         ctypes.byref(self._h)))
+
+    def submit(self, request_id: int, row_ptr, col, w, side=None):
+        torch = _torch()
+        g = csr(row_ptr, col, w)
+        if side is None:
+            side = torch.empty(max((g.n + 63) // 64, 1), dtype=torch.int64, device=row_ptr.device)
+        _check(load().viecut_session_submit(self._h, ctypes.byref(g), side.data_ptr(), int(request_id)))
+        self._keep[int(request_id)] = (row_ptr, col, w, side)
+        return side
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(load().viecut_session_step(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def poll(self, max_results=4096):
+        ids = (ctypes.c_int64 * max_results)()
+        outs = (Result * max_results)()
+        k = load().viecut_session_poll(self._h, ids, outs, max_results)
+        if k < 0:
+            _check(k)
+        done = []
+        for i in range(k):
+            rid = int(ids[i])
+            rp, col, w, side = self._keep.pop(rid)
+            info = outs[i].as_dict()
+            if info["status"] & 0x80000000:
+                info["error"] = -(info["status"] & 0x7FFFFFFF)
+                done.append((rid, None, side, info))
+            else:
+                done.append((rid, int(outs[i].cut), side, info))
+        return done
+
+    def close(self):
+        if self._h:
+            load().viecut_session_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

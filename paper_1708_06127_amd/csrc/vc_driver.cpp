@@ -51,7 +51,10 @@ int64_t scan_tmp_need(int64_t count) {
   return need + 64;
 }
 
-Layout make_layout(int32_t n, int64_t nnz) {
+// map_n: entries of the input -> current vertex map (n for a single solve,
+// 64 per word of the padded input index space for a batched one); extra:
+// rows of the gather staging beyond n (one per graph in a batch).
+Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   Layout L;
   const int64_t tiles = (nnz + 4095) / 4096 + 1;
   const int64_t huge_rows = nnz / (kHugeChunk + 1) + 1;
@@ -69,10 +72,10 @@ Layout make_layout(int32_t n, int64_t nnz) {
   L.add(4 * (size_t)n + 4);                    // 9 Lb
   L.add(4 * ((size_t)n + 1));                  // 10 ids
   L.add(4 * (size_t)n + 4);                    // 11 cl
-  L.add(4 * (size_t)n + 4);                    // 12 map
-  L.add(8 * (((size_t)n + 63) / 64) + 8);      // 13 witness
+  L.add(4 * (size_t)map_n + 4);                // 12 map
+  L.add(8 * (((size_t)map_n + 63) / 64) + 8);  // 13 witness
   L.add(4 * (size_t)kBins * n + 4);            // 14 bins
-  L.add(4 * ((size_t)n + 1));                  // 15 cnt
+  L.add(4 * ((size_t)n + (size_t)extra + 1));  // 15 cnt (batched: gather staging rows)
   L.add(8 * (size_t)std::max<int64_t>(nnz, 1));  // 16 keys0
   L.add(8 * (size_t)std::max<int64_t>(nnz, 1));  // 17 keys1
   L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // 18 vals0
@@ -95,10 +98,12 @@ Layout make_layout(int32_t n, int64_t nnz) {
 
 }  // namespace
 
-size_t work_bytes(int32_t n, int64_t nnz) { return make_layout(n, nnz).total + 256; }
+size_t work_bytes(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
+  return make_layout(n, nnz, map_n < 0 ? n : map_n, extra).total + 256;
+}
 
-bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w) {
-  Layout L = make_layout(n, nnz);
+bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_n, int64_t extra) {
+  Layout L = make_layout(n, nnz, map_n < 0 ? n : map_n, extra);
   uintptr_t base = ((uintptr_t)ws + 255) & ~uintptr_t(255);
   if (base + L.total > (uintptr_t)ws + bytes) return false;
   auto at = [&](int i) { return (void *)(base + L.off[i]); };

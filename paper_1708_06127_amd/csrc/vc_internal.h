@@ -54,6 +54,80 @@ struct Status {
   int32_t huge_items;          // work items (chunks) of the huge bin
   int32_t huge_slots;          // table slots of the huge bin
   int32_t bin_cnt[8];          // vertices per degree class
+  int32_t ring_cnt;            // (batched) finished graphs pushed to the ring so far
+  int32_t active_cnt;          // (batched) graphs still in the round loop
+  int32_t pad1[2];
+};
+
+// ------------------------------------------------------------ batched solves
+// Many graphs are solved as one disjoint union: their CSRs are concatenated
+// (graph g owns the vertex range [base, base + k) and the arc range
+// [aoff, aoff + nnz) of the current level), every phase is one launch over
+// the union, and a per-vertex graph index `gv` gives the kernels each row's
+// graph. What makes the result of a graph independent of its neighbours in
+// the union: label priorities use graph-local ids and a per-graph salt,
+// relabelling by prefix sum keeps every graph's clusters contiguous and in
+// the same order, and bounds, witnesses, marks and stop rules are kept per
+// graph (GStat).
+enum : int32_t { GS_FREE = 0, GS_FRESH = 1, GS_ACTIVE = 2, GS_DONE = 3 };
+enum : int32_t { FIN_NONE = 0, FIN_SOLVE = 1, FIN_STOP = 2, FIN_ERROR = 3 };
+
+struct GStat {
+  unsigned long long minkey;   // min over the graph's vertices of (deg << 32 | local v)
+  unsigned long long wsum;     // arc weight sum of the input
+  long long lam_hat;           // current upper bound
+  int32_t err;                 // ERR_* bits of the input
+  int32_t wit_v, wit_level;    // witness vertex (local id) and its level
+  int32_t updated;             // lam_hat lowered at the last bound update
+  int32_t status;              // ST_* bits
+  int32_t nmarked;             // some edge of the graph was PR-marked in this round
+  int32_t base, k;             // first vertex and vertex count at the current level
+  int32_t aoff, nnz;           // first arc and arc count at the current level
+  int32_t level, rounds;       // contractions performed, rounds started
+  int32_t n_start;             // vertices at the start of the current round
+  int32_t state;               // GS_*
+  int32_t fin;                 // FIN_*: how the graph left the loop
+  int32_t buf;                 // CSR buffer holding its current level
+  int32_t contracted;          // contracted by the current contraction step
+  int32_t slot;                // own index
+  uint32_t salt;               // tie-break salt of the current LP iteration
+  int32_t pad;
+};
+static_assert(sizeof(GStat) == 104, "GStat layout");
+
+// Static descriptor of an admitted graph (device copy).
+struct GDesc {
+  const int32_t *rp, *col, *w; // the caller's CSR (device)
+  int32_t n, nnz;
+  int32_t voff, aoff;          // its vertex / arc offset in the union at admission
+  int32_t woff, words;         // its range of 64-vertex words in the input index space
+  int32_t slot;
+  int32_t rchunk0, achunk0;    // first row chunk / arc chunk of the packing work
+  int32_t pad;
+};
+
+// Copy of a finished graph's last level out of the union (for the exact solve).
+struct GatherDesc {
+  const int32_t *rp, *col, *w;   // union buffer holding that level
+  int32_t base, k, aoff, nnz;    // its vertex and arc ranges there
+  int32_t drp, darc;             // destination offsets in the staging arrays
+  int32_t rchunk0, achunk0;      // first row chunk / arc chunk of the copy work
+};
+
+// Side bitmap of a finished graph.
+struct SideDesc {
+  unsigned long long *side;      // caller's array, ceil(n/64) words
+  int32_t woff, n;               // its words in the input index space, vertex count
+  int32_t mode;                  // 0: witness bitmap, 1: kernel-graph flags through the map, 2: release only
+  int32_t foff, fbase;           // flags of kernel vertex (map - fbase) at foff + (map - fbase)
+  int32_t wchunk0;               // first output word of this graph in the launch
+};
+
+// Device views used by the kernels in batched mode (all nullptr for a single solve).
+struct BatchView {
+  const int32_t *gv = nullptr;   // graph index per vertex of the current level
+  GStat *gs = nullptr;           // per-graph state, indexed by slot
+  int32_t slots = 0;
 };
 
 // One graph level in device memory. Rows may be unsorted only for the input.
@@ -102,8 +176,8 @@ struct Work {
   int32_t *seg_cnt = nullptr;    // their counts, then exclusive offsets
 };
 
-size_t work_bytes(int32_t n, int64_t nnz);
-bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w);
+size_t work_bytes(int32_t n, int64_t nnz, int64_t map_n = -1, int64_t extra = 0);
+bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_n = -1, int64_t extra = 0);
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipSuccess or the launch error.
@@ -120,13 +194,16 @@ hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s);
 // iteration 1 of LP (labels are the identity): row argmax, at level 0 fused
 // with validation, the weighted degree and the minimum-degree key
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
-                    hipStream_t s);
+                    hipStream_t s, const BatchView *bv = nullptr);
 // iteration t >= 2: neighbour-label weight sums in hash tables
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
-                   hipStream_t s);
-hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s);
+                   hipStream_t s, const BatchView *bv = nullptr);
+hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchView *bv = nullptr);
 // relabel: ids = prefix sum of used label values, cl[v] = ids[L[v]], k -> st->k
-hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s);
+// (batched: only graphs in the round loop keep their vertices; gv_new receives
+// the graph index of every new vertex)
+hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const BatchView *bv = nullptr,
+                   int32_t *gv_new = nullptr);
 hipError_t compose_map(Work &w, hipStream_t s);
 hipError_t init_map(Work &w, hipStream_t s);
 // contraction: inter-cluster triples packed into buffer 1 (count -> st->ax, key bits from st->k)
@@ -135,13 +212,38 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
 hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s);
 // sorted triples -> CSR buffer `dst` with k rows, degrees, bound update at `level`, witness
 hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
-                          hipStream_t s);
+                          hipStream_t s, bool single_bound = true);
 hipError_t bound_level0(Work &w, hipStream_t s);
 // PR marks on the v < x arcs (st->nmarked != 0 iff some edge was marked)
-hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);
+hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv = nullptr);
 hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s);
 hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStream_t s);
 hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s);
+
+// ---- batched-solve launchers (see the kernels for what each does)
+hipError_t b_gs_init(GStat *gs, const GDesc *d, int32_t count, int32_t buf, hipStream_t s);
+hipError_t b_pack(const GDesc *d, int32_t count, int32_t rchunks, int32_t achunks, int32_t *gv, int32_t *map,
+                  int32_t *wg, int32_t *rpu, int32_t *colu, int32_t *wu, GStat *gs, hipStream_t s);
+hipError_t b_salts(GStat *gs, int32_t slots, uint64_t seed, int32_t lp_iters, int32_t t, bool pre, hipStream_t s);
+hipError_t b_gdeg(const long long *deg, int32_t v0, int32_t v1, const int32_t *gv, GStat *gs, bool with_sum,
+                  hipStream_t s);
+hipError_t b_gbound0(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap, hipStream_t s);
+hipError_t b_step_top(GStat *gs, int32_t slots, int32_t n0, int32_t max_rounds, Status *st, GStat *ring,
+                      int32_t ring_cap, hipStream_t s);
+hipError_t b_step_end(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap, hipStream_t s);
+hipError_t b_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, hipStream_t s);
+hipError_t b_gbound(GStat *gs, int32_t slots, const int32_t *rp, int32_t buf, Status *st, GStat *ring,
+                    int32_t ring_cap, hipStream_t s);
+hipError_t b_gwitness(const int32_t *map, const int32_t *wg, const GStat *gs, int32_t words,
+                      unsigned long long *wit, hipStream_t s);
+hipError_t b_compose(int32_t *map, const int32_t *cl, int64_t entries, const int32_t *wg, const GStat *gs,
+                     hipStream_t s);
+hipError_t b_gather(const GatherDesc *d, int32_t count, int32_t rchunks, int32_t achunks, int32_t *orp,
+                    int32_t *ocol, int32_t *ow, hipStream_t s);
+hipError_t b_side(const SideDesc *d, int32_t count, int32_t words, const int32_t *map,
+                  const unsigned long long *wit, const uint8_t *flags, int32_t *wg, hipStream_t s);
+constexpr int kPackRows = 2048;  // rows (input index entries) per chunk of the packing and gather work
+constexpr int kPackArcs = 8192;  // arcs per chunk of the packing and gather work
 
 // host driver entry points shared by the single, batched and session paths
 int check_args(const viecut_csr *g, const viecut_params *p);

@@ -157,6 +157,8 @@ __global__ void k_status_reset(Status *st) {
     st->dmax = 0;
     st->huge_items = 0;
     st->huge_slots = 0;
+    st->ring_cnt = 0;
+    st->active_cnt = 0;
   }
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
 }
@@ -232,9 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
                                                       const int32_t *__restrict__ w, int32_t n,
                                                       const int32_t *__restrict__ list, const int32_t *cnt_p,
                                                       int32_t *__restrict__ L, long long *__restrict__ deg,
-                                                      uint32_t salt, int level0, Status *st) {
+                                                      uint32_t salt, int level0, Status *st,
+                                                      const int32_t *__restrict__ gv, GStat *gs) {
   __shared__ unsigned long long sh[kBlock / 64];
-  if (st->err) return;
+  if (!gv && st->err) return;
   constexpr int NG = kBlock / G;
   const int gi = threadIdx.x / G, lane = threadIdx.x % G;
   const int32_t cnt = *cnt_p;
@@ -245,6 +248,13 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
     bool act = idx < cnt;
     int32_t v = act ? list[idx] : 0;
     int32_t beg = act ? rp[v] : 0, end = act ? rp[v + 1] : 0;
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv && act) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
+    }
     unsigned long long best = 0, sum = 0;
     int err = 0;
     for (int32_t i = beg + lane; i < end; i += G) {
@@ -255,23 +265,27 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
         if (c < 1) err |= ERR_WEIGHT;
       }
       sum += (unsigned long long)(uint32_t)c;
-      best = umax64(best, cand_key((uint32_t)c, x, salt));
+      best = umax64(best, cand_key((uint32_t)c, x - b0, sl));
     }
     best = grp_max<G>(best);
     sum = grp_sum<G>(sum);
     err = grp_or<G>(err);
     if (act && lane == 0) {
-      L[v] = end > beg ? key_label(best, salt) : v;
+      L[v] = end > beg ? key_label(best, sl) + b0 : v;
       if (level0) {
         deg[v] = (long long)sum;
-        unsigned long long s32 = sum > 0xFFFFFFFFull ? 0xFFFFFFFFull : sum;
-        mykey = umin64(mykey, (s32 << 32) | (uint32_t)v);
-        mysum += sum;
-        myerr |= err;
+        if (gv) {
+          if (err) atomicOr(&gs[gv[v]].err, err);
+        } else {
+          unsigned long long s32 = sum > 0xFFFFFFFFull ? 0xFFFFFFFFull : sum;
+          mykey = umin64(mykey, (s32 << 32) | (uint32_t)v);
+          mysum += sum;
+          myerr |= err;
+        }
       }
     }
   }
-  if (level0) {
+  if (level0 && !gv) {
     unsigned long long k = block_min(mykey, sh);
     unsigned long long s = block_sum(mysum, sh);
     int e = (int)block_max((unsigned long long)myerr, sh);
@@ -292,13 +306,14 @@ template <int G, int TBL>
 __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
                                                     int32_t *__restrict__ Lout, const int32_t *__restrict__ list,
-                                                    const int32_t *cnt_p, uint32_t salt, const Status *st) {
+                                                    const int32_t *cnt_p, uint32_t salt, const Status *st,
+                                                    const int32_t *__restrict__ gv, const GStat *gs) {
   constexpr int NG = kBlock / G;
   __shared__ int32_t tkey[NG][TBL];
   __shared__ uint32_t tval[NG][TBL];
   __shared__ unsigned long long red[kBlock / 64];
   __shared__ uint32_t own_sh[NG];
-  if (st->err) return;
+  if (!gv && st->err) return;
   const int gi = threadIdx.x / G, lane = threadIdx.x % G;
   const int32_t cnt = *cnt_p;
   for (int64_t base = blockIdx.x * (int64_t)NG; base < cnt; base += (int64_t)gridDim.x * NG) {
@@ -330,11 +345,18 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
     __syncthreads();
     unsigned long long best = 0;
     const int32_t own = act ? Lin[v] : -1;
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv && act) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
+    }
     for (int s = lane; s < TBL; s += G) {
       int32_t k = tkey[gi][s];
       if (k >= 0) {
         uint32_t S = tval[gi][s];
-        best = umax64(best, cand_key(S, k, salt));
+        best = umax64(best, cand_key(S, k - b0, sl));
         if (k == own) own_sh[gi] = S;
       }
     }
@@ -347,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
     if (act && lane == 0) {
       uint32_t S_own = own_sh[gi];
       if (end == beg || (uint32_t)(best >> 32) == S_own) Lout[v] = own;
-      else Lout[v] = key_label(best, salt);
+      else Lout[v] = key_label(best, sl) + b0;
     }
     __syncthreads();
   }
@@ -363,18 +385,22 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
 // run, flushed to per-row LDS slots; one thread per row writes the label. At
 // level 0 the pass also validates arcs and yields degrees, and each block
 // leaves its minimum-degree key, weight sum and error bits in `part`.
-template <bool L0>
+template <bool L0, bool B>
 __global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ w, int32_t n,
                                                         const int4 *__restrict__ meta, int32_t ntiles,
                                                         int32_t *__restrict__ L, long long *__restrict__ deg,
                                                         uint32_t salt, const Status *st,
-                                                        unsigned long long *__restrict__ part) {
+                                                        unsigned long long *__restrict__ part,
+                                                        const int32_t *__restrict__ gv, GStat *gs) {
   __shared__ int32_t s_rp[kTile + 1];
   __shared__ unsigned long long s_best[kTile];
   __shared__ unsigned long long s_sum[kTile];
-  const bool bad = st->err != 0;
+  // batched: graph-local id offset and salt of each row
+  __shared__ int32_t s_base[B ? kTile : 1];
+  __shared__ uint32_t s_salt[B ? kTile : 1];
+  const bool bad = !B && st->err != 0;
   unsigned long long mykey = ~0ull, mysum = 0;
   int myerr = 0;
   for (int32_t t = blockIdx.x; t < ntiles && !bad; t += gridDim.x) {
@@ -393,10 +419,18 @@ __global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ 
     for (int j = threadIdx.x; j < rows; j += kTB) {
       s_best[j] = 0;
       s_sum[j] = 0;
+      if constexpr (B) {
+        const GStat &g = gs[gv[r0 + j]];
+        s_base[j] = g.base;
+        s_salt[j] = g.salt;
+      }
     }
     __syncthreads();
     if (i0 < acnt) {
       int32_t j = row_of(s_rp, rows, i0);
+      int32_t bj = 0;
+      uint32_t sj = salt;
+      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
       unsigned long long best = 0, sum = 0;
 #pragma unroll
       for (int k = 0; k < kPerThread; k++) {
@@ -408,15 +442,22 @@ __global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ 
             best = 0;
             sum = 0;
             do { j++; } while (i >= s_rp[j + 1]);
+            if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
           }
           const int32_t x = xs[k], c = cs[k];
           if (L0) {
-            if (x < 0 || x >= n) myerr |= ERR_COL;
-            if (x == r0 + j) myerr |= ERR_SELF;
-            if (c < 1) myerr |= ERR_WEIGHT;
+            int e = 0;
+            if (x < 0 || x >= n) e |= ERR_COL;
+            if (x == r0 + j) e |= ERR_SELF;
+            if (c < 1) e |= ERR_WEIGHT;
+            if constexpr (B) {
+              if (e) atomicOr(&gs[gv[r0 + j]].err, e);  // rare: straight to the graph's flags
+            } else {
+              myerr |= e;
+            }
             sum += (unsigned long long)(uint32_t)c;
           }
-          best = umax64(best, cand_key((uint32_t)c, x, salt));
+          best = umax64(best, cand_key((uint32_t)c, x - bj, sj));
         }
       }
       atomicMax(&s_best[j], best);
@@ -425,17 +466,22 @@ __global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ 
     __syncthreads();
     for (int j = threadIdx.x; j < rows; j += kTB) {
       const int32_t v = r0 + j;
-      L[v] = s_rp[j + 1] > s_rp[j] ? key_label(s_best[j], salt) : v;
+      int32_t bj = 0;
+      uint32_t sj = salt;
+      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
+      L[v] = s_rp[j + 1] > s_rp[j] ? key_label(s_best[j], sj) + bj : v;
       if (L0) {
         const unsigned long long d = s_sum[j];
         deg[v] = (long long)d;
-        mykey = umin64(mykey, ((d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d) << 32) | (uint32_t)v);
-        mysum += d;
+        if constexpr (!B) {
+          mykey = umin64(mykey, ((d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d) << 32) | (uint32_t)v);
+          mysum += d;
+        }
       }
     }
     __syncthreads();
   }
-  if (L0) {
+  if constexpr (L0 && !B) {
     const unsigned long long k = grp_min<64>(mykey);
     const unsigned long long sm = grp_sum<64>(mysum);
     const int e = grp_or<64>(myerr);
@@ -471,17 +517,21 @@ __global__ void k_reduce_parts(const unsigned long long *part, int32_t count, St
 // probing always ends), keyed by neighbour label and summing weights. A
 // thread inserts its q arcs and then scans the 2q table slots of the same
 // rows, so the row of every slot is known without a search.
+template <bool B>
 __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
                                                      int32_t *__restrict__ Lout, const int4 *__restrict__ meta,
-                                                     int32_t ntiles, uint32_t salt, const Status *st) {
+                                                     int32_t ntiles, uint32_t salt, const Status *st,
+                                                     const int32_t *__restrict__ gv, const GStat *gs) {
   __shared__ int32_t s_rp[kTile + 1];
   __shared__ int32_t s_own[kTile];
   __shared__ uint32_t s_ownS[kTile];
   __shared__ unsigned long long s_best[kTile];
   __shared__ int32_t tkey[2 * kTileArcs];
   __shared__ uint32_t tval[2 * kTileArcs];
-  if (st->err) return;
+  __shared__ int32_t s_base[B ? kTile : 1];
+  __shared__ uint32_t s_salt[B ? kTile : 1];
+  if (!B && st->err) return;
   for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
@@ -499,6 +549,11 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
       s_own[j] = Lin[r0 + j];
       s_ownS[j] = 0;
       s_best[j] = 0;
+      if constexpr (B) {
+        const GStat &g = gs[gv[r0 + j]];
+        s_base[j] = g.base;
+        s_salt[j] = g.salt;
+      }
     }
     for (int e = threadIdx.x; e < 2 * acnt; e += kTB) {
       tkey[e] = -1;
@@ -554,17 +609,21 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
     __syncthreads();
     if (i0 < acnt) {
       int32_t j = j0;
+      int32_t bj = 0;
+      uint32_t sj = salt;
+      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
       unsigned long long best = 0;
       for (int32_t e = 2 * i0; e < 2 * iend; e++) {
         if (e >= 2 * s_rp[j + 1]) {
           atomicMax(&s_best[j], best);
           best = 0;
           do { j++; } while (e >= 2 * s_rp[j + 1]);
+          if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
         }
         const int32_t k = tkey[e];
         if (k >= 0) {
           const uint32_t S = tval[e];
-          best = umax64(best, cand_key(S, k, salt));
+          best = umax64(best, cand_key(S, k - bj, sj));
           if (k == s_own[j]) s_ownS[j] = S;
         }
       }
@@ -575,7 +634,10 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
       const int32_t own = s_own[j];
       if (s_rp[j + 1] == s_rp[j]) { Lout[r0 + j] = own; continue; }
       const unsigned long long b = s_best[j];
-      Lout[r0 + j] = ((uint32_t)(b >> 32) == s_ownS[j]) ? own : key_label(b, salt);
+      int32_t bj = 0;
+      uint32_t sj = salt;
+      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
+      Lout[r0 + j] = ((uint32_t)(b >> 32) == s_ownS[j]) ? own : key_label(b, sj) + bj;
     }
     __syncthreads();
   }
@@ -655,11 +717,12 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
                                                         const int32_t *list, const int32_t *cnt_p,
                                                         const int32_t *meta, const int32_t *__restrict__ Lin,
                                                         int32_t *tk, uint32_t *tv, unsigned long long *best,
-                                                        long long *deg, uint32_t salt, int mode, Status *st) {
+                                                        long long *deg, uint32_t salt, int mode, Status *st,
+                                                        const int32_t *__restrict__ gv, GStat *gs) {
   // mode 0: first iteration (argmax of (w,-prio)) + optional level-0 degree (mode 2)
   // mode 1: table insertion
   __shared__ unsigned long long sh[kBlock / 64];
-  if (st->err) return;
+  if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
   for (int32_t p = blockIdx.x; p < items; p += gridDim.x) {
@@ -686,6 +749,13 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
         atomicAdd(&V[h], (uint32_t)w[a]);
       }
     } else {
+      int32_t b0 = 0;
+      uint32_t sl = salt;
+      if (gv) {
+        const GStat &g = gs[gv[v]];
+        b0 = g.base;
+        sl = g.salt;
+      }
       unsigned long long b = 0, sum = 0;
       int err = 0;
       for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
@@ -696,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
           if (c < 1) err |= ERR_WEIGHT;
         }
         sum += (unsigned long long)(uint32_t)c;
-        b = umax64(b, cand_key((uint32_t)c, x, salt));
+        b = umax64(b, cand_key((uint32_t)c, x - b0, sl));
       }
       b = block_max(b, sh);
       sum = block_sum(sum, sh);
@@ -705,8 +775,12 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
         atomicMax(&best[i], b);
         if (mode == 2) {
           atomicAdd((unsigned long long *)&deg[v], sum);
-          atomicAdd(&st->wsum, sum);
-          if (err) atomicOr(&st->err, err);
+          if (gv) {
+            if (err) atomicOr(&gs[gv[v]].err, err);
+          } else {
+            atomicAdd(&st->wsum, sum);
+            if (err) atomicOr(&st->err, err);
+          }
         }
       }
     }
@@ -715,15 +789,23 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
 
 // table scan: per slot, contribute its candidate key to the row's maximum
 __global__ void k_huge_scan(const int32_t *meta, const int32_t *cnt_p, const int32_t *tk, const uint32_t *tv,
-                            unsigned long long *best, uint32_t salt, const Status *st) {
-  if (st->err) return;
+                            unsigned long long *best, uint32_t salt, const Status *st, const int32_t *list,
+                            const int32_t *__restrict__ gv, const GStat *gs) {
+  if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
   const int64_t slots = st->huge_slots;
   for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < slots; s += (int64_t)gridDim.x * kBlock) {
     int32_t k = tk[s];
     if (k < 0) continue;
     int32_t i = huge_find(meta, cnt, (int32_t)s, 1);
-    atomicMax(&best[i], cand_key(tv[s], k, salt));
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv) {
+      const GStat &g = gs[gv[list[i]]];
+      b0 = g.base;
+      sl = g.salt;
+    }
+    atomicMax(&best[i], cand_key(tv[s], k - b0, sl));
   }
 }
 
@@ -731,12 +813,19 @@ __global__ void k_huge_scan(const int32_t *meta, const int32_t *cnt_p, const int
 __global__ void k_huge_final(const int32_t *rp, const int32_t *list, const int32_t *cnt_p, const int32_t *meta,
                              const unsigned long long *best, const int32_t *Lin, const int32_t *tk,
                              const uint32_t *tv, int32_t *Lout, long long *deg, uint32_t salt, int mode,
-                             Status *st) {
-  if (st->err) return;
+                             Status *st, const int32_t *__restrict__ gv, const GStat *gs) {
+  if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
   for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
     int32_t v = list[i];
     unsigned long long b = best[i];
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
+    }
     if (mode == 1) {
       // own label's sum by probing the row's table
       const int32_t own = Lin[v];
@@ -750,10 +839,10 @@ __global__ void k_huge_final(const int32_t *rp, const int32_t *list, const int32
         if (k == -1) break;
         h = (h + 1) & mask;
       }
-      Lout[v] = ((uint32_t)(b >> 32) == S_own) ? own : key_label(b, salt);
+      Lout[v] = ((uint32_t)(b >> 32) == S_own) ? own : key_label(b, sl) + b0;
     } else {
-      Lout[v] = key_label(b, salt);
-      if (mode == 2) {
+      Lout[v] = key_label(b, sl) + b0;
+      if (mode == 2 && !gv) {
         unsigned long long s = (unsigned long long)deg[v];
         unsigned long long s32 = s > 0xFFFFFFFFull ? 0xFFFFFFFFull : s;
         atomicMin(&st->minkey, (s32 << 32) | (uint32_t)v);
@@ -769,10 +858,28 @@ __global__ void k_zero_deg_list(const int32_t *list, const int32_t *cnt_p, long 
 
 // ------------------------------------------------------------ validation (flag)
 // every arc (v,u,c) has its reverse (u,v,c); rows strictly increasing
-__global__ void k_validate_sym(const int32_t *rp, const int32_t *col, const int32_t *w, int32_t n, Status *st) {
-  if (st->err) return;
+__global__ void k_validate_sym(const int32_t *rp, const int32_t *col, const int32_t *w, int32_t n, Status *st,
+                               const int32_t *gv, GStat *gs) {
+  if (!gv && st->err) return;
   int bad = 0;
   for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    if (gv) {  // batched: only graphs still at level 0 are checked, each into its own flags
+      GStat &g = gs[gv[v]];
+      if (g.state != GS_FRESH) continue;
+      int e = 0;
+      for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+        int32_t u = col[i];
+        if (i > rp[v] && col[i - 1] >= u) e |= ERR_UNSORTED;
+        int32_t lo = rp[u], hi = rp[u + 1];
+        while (lo < hi) {
+          int32_t mid = (lo + hi) >> 1;
+          if (col[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= rp[u + 1] || col[lo] != v || w[lo] != w[i]) e |= ERR_NOTSYM;
+      }
+      if (e) atomicOr(&g.err, e);
+      continue;
+    }
     for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
       int32_t u = col[i];
       if (i > rp[v] && col[i - 1] >= u) bad |= ERR_UNSORTED;
@@ -849,17 +956,44 @@ __global__ void k_scan_tile(const int32_t *in, int32_t *out, int64_t count, cons
 }
 
 // ------------------------------------------------------------ relabel / map
-__global__ void k_flag_labels(const int32_t *L, int32_t n, int32_t *flags) {
+// Batched: vertices of graphs that left the round loop are dropped here
+// (cl = -1); their rows then emit nothing, as both ends of each of their
+// arcs map to -1.
+__global__ void k_flag_labels(const int32_t *L, int32_t n, int32_t *flags, const int32_t *gv, const GStat *gs) {
   for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
-    flags[L[v]] = 1;
+    if (!gv || gs[gv[v]].state == GS_ACTIVE) flags[L[v]] = 1;
 }
-__global__ void k_apply_ids(const int32_t *L, const int32_t *ids, int32_t n, int32_t *cl) {
-  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
-    cl[v] = ids[L[v]];
+__global__ void k_apply_ids(const int32_t *L, const int32_t *ids, int32_t n, int32_t *cl, const int32_t *gv,
+                            const GStat *gs, int32_t *gv_new) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    if (!gv) {
+      cl[v] = ids[L[v]];
+      continue;
+    }
+    const int32_t g = gv[v];
+    if (gs[g].state == GS_ACTIVE) {
+      const int32_t c = ids[L[v]];
+      cl[v] = c;
+      gv_new[c] = g;  // every member of a cluster writes the same graph index
+    } else {
+      cl[v] = -1;
+    }
+  }
 }
-__global__ void k_compose(int32_t *map, const int32_t *cl, int32_t n_in) {
-  for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < n_in; u += (int64_t)gridDim.x * kBlock)
-    map[u] = cl[map[u]];
+// map[u] <- cl[map[u]]. Batched: u runs over the padded input index space
+// (64 entries per word, word -> slot in wg; padding entries hold -1), and
+// graphs out of the loop keep the map of their last level.
+__global__ void k_compose(int32_t *map, const int32_t *cl, int32_t n_in, const int32_t *wg, const GStat *gs) {
+  for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < n_in; u += (int64_t)gridDim.x * kBlock) {
+    if (wg) {
+      const int32_t slot = wg[u >> 6];
+      const int32_t m = map[u];
+      if (slot < 0 || m < 0 || gs[slot].state != GS_ACTIVE) continue;
+      map[u] = cl[m];
+    } else {
+      map[u] = cl[map[u]];
+    }
+  }
 }
 __global__ void k_iota(int32_t *p, int32_t n) {
   for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < n; u += (int64_t)gridDim.x * kBlock)
@@ -1336,11 +1470,13 @@ __device__ bool pr_intersect_seq(const int32_t *col, const int32_t *w, int32_t v
   return sum4 >= lam;
 }
 
-__device__ __forceinline__ void pr_arc(const int32_t *rp, const int32_t *col, const int32_t *w,
+// Returns whether arc i was marked. lam < 0: the row's graph is out of the
+// round loop (batched), nothing is marked.
+__device__ __forceinline__ bool pr_arc(const int32_t *rp, const int32_t *col, const int32_t *w,
                                        const unsigned long long *degu, int32_t v, int32_t i, long long lam,
-                                       uint8_t *mark, int32_t *heavy, Status *st, bool &any) {
+                                       uint8_t *mark, int32_t *heavy, Status *st) {
   const int32_t x = col[i];
-  if (x <= v) { mark[i] = 0; return; }
+  if (x <= v || lam < 0) { mark[i] = 0; return false; }
   const long long c = w[i];
   const long long dv = (long long)degu[v], dx = (long long)degu[x];
   bool m = pr_cheap(c, dv, dx, lam);
@@ -1349,28 +1485,49 @@ __device__ __forceinline__ void pr_arc(const int32_t *rp, const int32_t *col, co
     if (min(ve - vb, xe - xb) > kPrSeq) {
       heavy[atomicAdd(&st->huge_items, 1)] = i;  // decided by k_pr_heavy
       mark[i] = 0;
-      return;
+      return false;
     }
     m = pr_intersect_seq(col, w, vb, ve, xb, xe, c, dv, dx, lam);
   }
   mark[i] = m ? 1 : 0;
-  any = any || m;
+  return m;
+}
+// batched: bound of the row's graph, or -1 when it is out of the loop
+__device__ __forceinline__ long long graph_lam(const GStat &g) { return g.state == GS_ACTIVE ? g.lam_hat : -1; }
+// batched: record that graph g has a marked edge (once per thread and graph)
+__device__ __forceinline__ void flag_marked(GStat *gs, int32_t g, int32_t &flagged) {
+  if (g == flagged) return;
+  flagged = g;
+  if (__hip_atomic_load(&gs[g].nmarked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    atomicExch(&gs[g].nmarked, 1);
 }
 
+template <bool B>
 __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w,
                                                      const unsigned long long *__restrict__ degu,
                                                      const int4 *__restrict__ meta, int32_t ntiles,
-                                                     uint8_t *__restrict__ mark, int32_t *heavy, Status *st) {
+                                                     uint8_t *__restrict__ mark, int32_t *heavy, Status *st,
+                                                     const int32_t *__restrict__ gv, GStat *gs) {
   __shared__ int32_t s_rp[kTile + 1];
   __shared__ int s_any;
-  const long long lam = st->lam_hat;
+  __shared__ long long s_lam[B ? kTile : 1];
+  __shared__ int32_t s_g[B ? kTile : 1];
+  const long long lam0 = B ? 0 : st->lam_hat;
+  int32_t flagged = -1;
   for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
     const int32_t q = (acnt + kTB - 1) / kTB;
     const int32_t i0 = threadIdx.x * q;
     for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    if constexpr (B) {
+      for (int j = threadIdx.x; j < rows; j += kTB) {
+        const int32_t g = gv[r0 + j];
+        s_g[j] = g;
+        s_lam[j] = graph_lam(gs[g]);
+      }
+    }
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
     bool any = false;
@@ -1379,7 +1536,9 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
       const int32_t iend = min(i0 + q, acnt);
       for (int32_t i = i0; i < iend; i++) {
         while (i >= s_rp[j + 1]) j++;
-        pr_arc(rp, col, w, degu, r0 + j, a0 + i, lam, mark, heavy, st, any);
+        const bool mk = pr_arc(rp, col, w, degu, r0 + j, a0 + i, B ? s_lam[j] : lam0, mark, heavy, st);
+        any = any || mk;
+        if (B && mk) flag_marked(gs, s_g[j], flagged);
       }
     }
     if (any) s_any = 1;
@@ -1392,17 +1551,22 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
 __global__ void k_pr_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                           const int32_t *__restrict__ w, const unsigned long long *__restrict__ degu,
                           const int32_t *list, const int32_t *cnt_p, uint8_t *__restrict__ mark, int32_t *heavy,
-                          Status *st) {
+                          Status *st, const int32_t *__restrict__ gv, GStat *gs) {
   __shared__ int s_any;
-  const long long lam = st->lam_hat;
   const int32_t cnt = *cnt_p;
+  int32_t flagged = -1;
   for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
     const int32_t v = list[r];
+    const int32_t g = gv ? gv[v] : 0;
+    const long long lam = gv ? graph_lam(gs[g]) : st->lam_hat;
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
     bool any = false;
-    for (int32_t i = rp[v] + threadIdx.x; i < rp[v + 1]; i += kBlock)
-      pr_arc(rp, col, w, degu, v, i, lam, mark, heavy, st, any);
+    for (int32_t i = rp[v] + threadIdx.x; i < rp[v + 1]; i += kBlock) {
+      const bool mk = pr_arc(rp, col, w, degu, v, i, lam, mark, heavy, st);
+      any = any || mk;
+      if (gv && mk) flag_marked(gs, g, flagged);
+    }
     if (any) s_any = 1;
     __syncthreads();
     if (threadIdx.x == 0 && s_any && st->nmarked == 0) atomicExch(&st->nmarked, 1);
@@ -1413,8 +1577,9 @@ __global__ void k_pr_long(const int32_t *__restrict__ rp, const int32_t *__restr
 // queued arcs: one wave each, lanes over the shorter row
 __global__ void k_pr_heavy(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const int32_t *__restrict__ w, const unsigned long long *__restrict__ degu, int32_t n,
-                           const int32_t *heavy, uint8_t *__restrict__ mark, Status *st) {
-  const long long lam = st->lam_hat;
+                           const int32_t *heavy, uint8_t *__restrict__ mark, Status *st,
+                           const int32_t *__restrict__ gv, GStat *gs) {
+  const long long lam_single = gv ? 0 : st->lam_hat;
   const int32_t cnt = st->huge_items;
   const int lane = threadIdx.x & 63;
   for (int64_t h = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; h < cnt; h += ((int64_t)gridDim.x * kBlock) >> 6) {
@@ -1426,6 +1591,7 @@ __global__ void k_pr_heavy(const int32_t *__restrict__ rp, const int32_t *__rest
       if (rp[mid] <= i) lo = mid; else hi = mid - 1;
     }
     const int32_t v = lo, x = col[i];
+    const long long lam = gv ? gs[gv[v]].lam_hat : lam_single;  // queued arcs belong to graphs in the loop
     const long long c = w[i];
     const long long dv = (long long)degu[v], dx = (long long)degu[x];
     const int32_t vb = rp[v], ve = rp[v + 1], xb = rp[x], xe = rp[x + 1];
@@ -1454,6 +1620,7 @@ __global__ void k_pr_heavy(const int32_t *__restrict__ rp, const int32_t *__rest
     if (lane == 0) {
       mark[i] = m ? 1 : 0;
       if (m && st->nmarked == 0) atomicExch(&st->nmarked, 1);
+      if (m && gv && gs[gv[v]].nmarked == 0) atomicExch(&gs[gv[v]].nmarked, 1);
     }
   }
 }
@@ -1540,6 +1707,344 @@ __global__ void k_side_witness(const unsigned long long *wit, int32_t n_in, unsi
   }
 }
 
+// ------------------------------------------------------------ batched solves
+// SplitMix64 output number `index` (1-based) for a state starting at `seed`
+// (Steele, Lea, Flood 2014), as on the host.
+__device__ __forceinline__ uint64_t splitmix64_at_dev(uint64_t seed, uint64_t index) {
+  uint64_t z = seed + index * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// A graph leaves the round loop: its state is frozen and a snapshot is
+// pushed to the ring the host drains at its next status read.
+__device__ void finish_graph(GStat &g, int fin, Status *st, GStat *ring, int32_t ring_cap) {
+  if (g.state == GS_ACTIVE) atomicSub(&st->active_cnt, 1);
+  g.state = GS_DONE;
+  g.fin = fin;
+  const int32_t idx = atomicAdd(&st->ring_cnt, 1);
+  ring[idx % ring_cap] = g;
+}
+
+// fresh slots: state at admission
+__global__ void k_gs_init(GStat *gs, const GDesc *d, int32_t count, int32_t buf) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) {
+    GStat g;
+    g.minkey = ~0ull;
+    g.wsum = 0;
+    g.lam_hat = 0x7FFFFFFFFFFFFFFFll;
+    g.err = 0;
+    g.wit_v = -1;
+    g.wit_level = 0;
+    g.updated = 0;
+    g.status = 0;
+    g.nmarked = 0;
+    g.base = d[i].voff;
+    g.k = d[i].n;
+    g.aoff = d[i].aoff;
+    g.nnz = d[i].nnz;
+    g.level = 0;
+    g.rounds = 0;
+    g.n_start = d[i].n;
+    g.state = GS_FRESH;
+    g.fin = FIN_NONE;
+    g.buf = buf;
+    g.contracted = 0;
+    g.slot = d[i].slot;
+    g.salt = 0;
+    g.pad = 0;
+    gs[d[i].slot] = g;
+  }
+}
+
+// last descriptor whose chunk offset (field at byte offset `off` of the
+// struct) is <= c
+template <class D>
+__device__ __forceinline__ int32_t desc_find(const D *d, int32_t count, int32_t c, int32_t D::*field) {
+  int32_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (d[mid].*field <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Packing pass 1, per input row of the fresh graphs: graph index, identity
+// map over the padded index range, word owners, row pointer checks.
+__global__ void k_pack_rows1(const GDesc *d, int32_t count, int32_t chunks, int32_t *gv, int32_t *map, int32_t *wg,
+                             GStat *gs) {
+  for (int32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const GDesc &g = d[desc_find(d, count, c, &GDesc::rchunk0)];
+    const int64_t v0 = (int64_t)(c - g.rchunk0) * kPackRows;
+    const int64_t lim = 64ll * g.words;
+    int bad = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v0 + kPackRows && v < lim; v += kBlock) {
+      const int64_t pu = 64ll * g.woff + v;
+      if (v < g.n) {
+        gv[g.voff + v] = g.slot;
+        map[pu] = g.voff + (int32_t)v;
+        const int32_t a = g.rp[v], b = g.rp[v + 1];
+        if (a < 0 || b < a || b > g.nnz) bad = 1;
+        if (v == 0 && a != 0) bad = 1;
+        if (v == g.n - 1 && b != g.nnz) bad = 1;
+      } else {
+        map[pu] = -1;
+      }
+      if ((v & 63) == 0) wg[g.woff + (v >> 6)] = g.slot;
+    }
+    if (bad) atomicOr(&gs[g.slot].err, ERR_ROWPTR);
+  }
+}
+
+// Packing pass 2: union row pointers (a graph with a malformed row pointer
+// gets empty rows but its last, which holds all its arcs).
+__global__ void k_pack_rows2(const GDesc *d, int32_t count, int32_t chunks, int32_t *rpu, const GStat *gs) {
+  for (int32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const GDesc &g = d[desc_find(d, count, c, &GDesc::rchunk0)];
+    const bool bad = (gs[g.slot].err & ERR_ROWPTR) != 0;
+    const int64_t v0 = (int64_t)(c - g.rchunk0) * kPackRows;
+    for (int64_t v = v0 + threadIdx.x; v < v0 + kPackRows && v < g.n; v += kBlock) {
+      rpu[g.voff + v] = g.aoff + (bad ? 0 : g.rp[v]);
+      if (v == g.n - 1) rpu[g.voff + g.n] = g.aoff + g.nnz;
+    }
+  }
+}
+
+// Packing of the arcs: columns shifted to union ids (out-of-range columns are
+// flagged and replaced by the graph's vertex 0, so no arc leaves its graph).
+__global__ void k_pack_arcs(const GDesc *d, int32_t count, int32_t chunks, int32_t *colu, int32_t *wu, GStat *gs) {
+  for (int32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const GDesc &g = d[desc_find(d, count, c, &GDesc::achunk0)];
+    const int64_t a0 = (int64_t)(c - g.achunk0) * kPackArcs;
+    int e = 0;
+    for (int64_t a = a0 + threadIdx.x; a < a0 + kPackArcs && a < g.nnz; a += kBlock) {
+      int32_t x = g.col[a];
+      const int32_t c2 = g.w[a];
+      if (x < 0 || x >= g.n) { e |= ERR_COL; x = 0; }
+      if (c2 < 1) e |= ERR_WEIGHT;
+      colu[g.aoff + a] = g.voff + x;
+      wu[g.aoff + a] = c2;
+    }
+    if (e) atomicOr(&gs[g.slot].err, e);
+  }
+}
+
+// salt of LP iteration t of each graph's current round (pre: before the
+// round counter is advanced at the top of the round)
+__global__ void k_salts(GStat *gs, int32_t slots, uint64_t seed, int32_t lp_iters, int32_t t, int32_t pre) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
+    GStat &g = gs[i];
+    if (g.state != GS_ACTIVE && g.state != GS_FRESH) continue;
+    const int64_t r = pre ? g.rounds : g.rounds - 1;
+    g.salt = (uint32_t)(splitmix64_at_dev(seed, (uint64_t)r * (uint64_t)lp_iters + (uint64_t)t) & 0xFFFFFFFFull);
+  }
+}
+
+// Per-graph minimum-degree key (and weight sum) over vertices [v0, v1).
+// Lanes hold consecutive vertices, so a wave mostly covers one graph: then
+// one atomic per wave, else one per lane.
+__global__ void k_gdeg(const unsigned long long *degu, int32_t v0, int32_t v1, const int32_t *gv, GStat *gs,
+                       int with_sum) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = v0 + blockIdx.x * (int64_t)kBlock; base < v1; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t v = base + threadIdx.x;
+    const bool ok = v < v1;
+    const int32_t g = ok ? gv[v] : -1;
+    unsigned long long key = ~0ull, sum = 0;
+    if (ok) {
+      const unsigned long long d = degu[v];
+      sum = d;
+      key = ((d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d) << 32) | (uint32_t)((int32_t)v - gs[g].base);
+    }
+    const int32_t g0 = __shfl(g, 0, 64);
+    if (__all(g == g0)) {
+      if (g0 < 0) continue;
+      key = grp_min<64>(key);
+      sum = grp_sum<64>(sum);
+      if (lane == 0) {
+        atomicMin(&gs[g0].minkey, key);
+        if (with_sum && sum) atomicAdd(&gs[g0].wsum, sum);
+      }
+    } else if (ok) {
+      atomicMin(&gs[g].minkey, key);
+      if (with_sum && sum) atomicAdd(&gs[g].wsum, sum);
+    }
+  }
+}
+
+// level 0 of the fresh graphs: input errors, then the bound from the minimum
+// weighted degree; the graph enters the round loop
+__global__ void k_gbound0(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
+    GStat &g = gs[i];
+    if (g.state != GS_FRESH) continue;
+    g.updated = 0;
+    if (g.err || g.wsum / 2 > 0x7FFFFFFFull) {
+      finish_graph(g, FIN_ERROR, st, ring, ring_cap);
+      continue;
+    }
+    g.state = GS_ACTIVE;
+    atomicAdd(&st->active_cnt, 1);
+    g.lam_hat = (long long)(g.minkey >> 32);
+    g.wit_v = (int32_t)(g.minkey & 0xFFFFFFFFull);
+    g.wit_level = 0;
+    g.updated = 1;
+    if (g.lam_hat == 0) {
+      g.status |= ST_DISCONNECTED;
+      finish_graph(g, FIN_STOP, st, ring, ring_cap);
+    }
+  }
+}
+
+// top of a round: leave the loop at <= n0 vertices or at the round cap,
+// else start the round
+__global__ void k_step_top(GStat *gs, int32_t slots, int32_t n0, int32_t max_rounds, Status *st, GStat *ring,
+                           int32_t ring_cap) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
+    GStat &g = gs[i];
+    g.nmarked = 0;
+    if (g.state != GS_ACTIVE) continue;
+    if (g.k <= n0) {
+      finish_graph(g, FIN_SOLVE, st, ring, ring_cap);
+    } else if (g.rounds >= max_rounds) {
+      g.status |= ST_MAX_ROUNDS;
+      finish_graph(g, FIN_SOLVE, st, ring, ring_cap);
+    } else {
+      g.rounds++;
+      g.n_start = g.k;
+    }
+  }
+}
+
+// end of a round: a round that did not shrink the graph ends its loop
+__global__ void k_step_end(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
+    GStat &g = gs[i];
+    if (g.state == GS_ACTIVE && g.k == g.n_start) {
+      g.status |= ST_NO_PROGRESS;
+      finish_graph(g, FIN_SOLVE, st, ring, ring_cap);
+    }
+  }
+}
+
+// after the relabelling scan: each graph's vertex range at the new level
+// (mode 0: cluster contraction, every graph in the loop is contracted; mode
+// 1: marked-edge contraction, only graphs with a marked edge are)
+__global__ void k_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
+    GStat &g = gs[i];
+    if (g.state != GS_ACTIVE) continue;
+    const int32_t nb = ids[g.base];
+    g.k = ids[g.base + g.k] - nb;
+    g.base = nb;
+    g.minkey = ~0ull;
+    g.contracted = mode == 0 ? 1 : (g.nmarked != 0);
+  }
+}
+
+// after a contraction: arc range, level count, collapse, bound update
+__global__ void k_gbound(GStat *gs, int32_t slots, const int32_t *rp, int32_t buf, Status *st, GStat *ring,
+                         int32_t ring_cap) {
+  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
+    GStat &g = gs[i];
+    g.updated = 0;
+    if (g.state != GS_ACTIVE) continue;
+    g.aoff = rp[g.base];
+    g.nnz = rp[g.base + g.k] - g.aoff;
+    g.buf = buf;
+    if (!g.contracted) continue;
+    g.level++;
+    if (g.k == 1) {
+      g.status |= ST_COLLAPSED;
+      finish_graph(g, FIN_STOP, st, ring, ring_cap);
+      continue;
+    }
+    const long long d = (long long)(g.minkey >> 32);
+    if (d < g.lam_hat) {
+      g.lam_hat = d;
+      g.wit_v = (int32_t)(g.minkey & 0xFFFFFFFFull);
+      g.wit_level = g.level;
+      g.updated = 1;
+    }
+    if (g.lam_hat == 0) {
+      g.status |= ST_DISCONNECTED;
+      finish_graph(g, FIN_STOP, st, ring, ring_cap);
+    }
+  }
+}
+
+// witness words of the graphs whose bound was just lowered: one wave per
+// word of the padded input index space
+__global__ void k_gwitness(const int32_t *map, const int32_t *wg, const GStat *gs, int32_t words,
+                           unsigned long long *wit) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; q < words;
+       q += ((int64_t)gridDim.x * kBlock) >> 6) {
+    const int32_t slot = wg[q];
+    if (slot < 0 || !gs[slot].updated) continue;
+    const int32_t target = gs[slot].base + gs[slot].wit_v;
+    const unsigned long long bal = __ballot(map[q * 64 + lane] == target);
+    if (lane == 0) wit[q] = bal;
+  }
+}
+
+// kernel graphs of finished graphs, rebased to local ids, into staging
+__global__ void k_gather(const GatherDesc *d, int32_t count, int32_t rchunks, int32_t chunks, int32_t *orp,
+                         int32_t *ocol, int32_t *ow) {
+  for (int32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    if (c < rchunks) {
+      const GatherDesc &g = d[desc_find(d, count, c, &GatherDesc::rchunk0)];
+      const int64_t v0 = (int64_t)(c - g.rchunk0) * kPackRows;
+      for (int64_t v = v0 + threadIdx.x; v < v0 + kPackRows && v <= g.k; v += kBlock)
+        orp[g.drp + v] = g.rp[g.base + v] - g.aoff;
+    } else {
+      const int32_t ca = c - rchunks;
+      const GatherDesc &g = d[desc_find(d, count, ca, &GatherDesc::achunk0)];
+      const int64_t a0 = (int64_t)(ca - g.achunk0) * kPackArcs;
+      for (int64_t a = a0 + threadIdx.x; a < a0 + kPackArcs && a < g.nnz; a += kBlock) {
+        ocol[g.darc + a] = g.col[g.aoff + a] - g.base;
+        ow[g.darc + a] = g.w[g.aoff + a];
+      }
+    }
+  }
+}
+
+// Side bitmaps of finished graphs, one wave per output word; the word is
+// released (wg = -1) once written. mode 0: the witness bitmap; mode 1:
+// flags of the kernel graph's vertices, through the frozen map; mode 2: no
+// output (failed input), release only. Vertex 0 ends on side 0.
+__global__ void k_side_batch(const SideDesc *d, int32_t count, int32_t words, const int32_t *map,
+                             const unsigned long long *wit, const uint8_t *flags, int32_t *wg) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; q < words;
+       q += ((int64_t)gridDim.x * kBlock) >> 6) {
+    const SideDesc &g = d[desc_find(d, count, (int32_t)q, &SideDesc::wchunk0)];
+    const int32_t j = (int32_t)q - g.wchunk0;
+    const int64_t word = (int64_t)g.woff + j;
+    if (g.mode == 2) {  // failed graph: release only
+      if (lane == 0) wg[word] = -1;
+      continue;
+    }
+    unsigned long long x;
+    if (g.mode == 0) {
+      const bool flip = wit[g.woff] & 1ull;
+      x = wit[word] ^ (flip ? ~0ull : 0ull);
+    } else {
+      const uint8_t f0 = flags[g.foff + (map[64ll * g.woff] - g.fbase)];
+      const int32_t u = j * 64 + lane;
+      const bool b = u < g.n && flags[g.foff + (map[word * 64 + lane] - g.fbase)] != f0;
+      x = __ballot(b);
+    }
+    if (lane == 0) {
+      const int32_t rem = g.n - j * 64;
+      if (rem < 64) x &= (1ull << rem) - 1;
+      g.side[j] = x;
+      wg[word] = -1;
+    }
+  }
+}
+
 inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 8192) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -1609,26 +2114,35 @@ void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t
 }
 template <int G, int TBL>
 void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int32_t *Lin, int32_t *Lout,
-                uint32_t salt, hipStream_t s) {
+                uint32_t salt, hipStream_t s, const int32_t *gv, const GStat *gs) {
   const int64_t items = bin_items(known, b, long_rows_bound(g));
   if (items <= 0) return;
   const int32_t *list = w.bins + (int64_t)b * w.n_in;
   k_lp_tab<G, TBL><<<grid_for(items, kBlock / G, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, list,
-                                                                       &w.st->bin_cnt[b], salt, w.st);
+                                                                       &w.st->bin_cnt[b], salt, w.st, gv, gs);
 }
 }  // namespace
 
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
-                    hipStream_t s) {
+                    hipStream_t s, const BatchView *bv) {
   const int l0 = level0 ? 1 : 0;
+  const int32_t *gv = bv ? bv->gv : nullptr;
+  GStat *gs = bv ? bv->gs : nullptr;
   const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
-  if (level0) {
-    k_first_tile<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt, w.st,
-                                             w.part);
+  if (bv) {
+    if (level0)
+      k_first_tile<true, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt,
+                                                     w.st, w.part, gv, gs);
+    else
+      k_first_tile<false, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
+                                                      salt, w.st, w.part, gv, gs);
+  } else if (level0) {
+    k_first_tile<true, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt,
+                                                    w.st, w.part, nullptr, nullptr);
     k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
   } else {
-    k_first_tile<false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt,
-                                              w.st, w.part);
+    k_first_tile<false, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
+                                                     salt, w.st, w.part, nullptr, nullptr);
   }
   // long rows: a wave per row up to 4096 arcs, chunked beyond
   for (int b = 4; b <= 5; b++) {
@@ -1637,7 +2151,7 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
       const int32_t *list = w.bins + (int64_t)b * w.n_in;
       k_lp_first<64><<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
                                                                           &w.st->bin_cnt[b], L, w.deg, salt, l0,
-                                                                          w.st);
+                                                                          w.st, gv, gs);
     }
   }
   if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
@@ -1648,18 +2162,24 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st);
   k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(
       g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, nullptr, nullptr, nullptr, w.huge_best, w.deg, salt,
-      level0 ? 2 : 0, w.st);
+      level0 ? 2 : 0, w.st, gv, gs);
   k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, nullptr, nullptr, L,
-                                     w.deg, salt, level0 ? 2 : 0, w.st);
+                                     w.deg, salt, level0 ? 2 : 0, w.st, gv, gs);
   return hipGetLastError();
 }
 
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
-                   hipStream_t s) {
-  k_lp_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta,
-                                                               w.ntiles, salt, w.st);
-  launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s);
-  launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s);
+                   hipStream_t s, const BatchView *bv) {
+  const int32_t *gv = bv ? bv->gv : nullptr;
+  GStat *gs = bv ? bv->gs : nullptr;
+  if (bv)
+    k_lp_tile<true><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta,
+                                                                       w.ntiles, salt, w.st, gv, gs);
+  else
+    k_lp_tile<false><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta,
+                                                                        w.ntiles, salt, w.st, nullptr, nullptr);
+  launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
+  launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);
   if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
   const int32_t *list6 = w.bins + 6ll * w.n_in;
   const int32_t *cnt6 = &w.st->bin_cnt[6];
@@ -1668,30 +2188,35 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list6, cnt6,
                                                                      w.huge_meta, Lin, w.huge_tab_key,
                                                                      w.huge_tab_val, w.huge_best, nullptr, salt, 1,
-                                                                     w.st);
-  k_huge_scan<<<2048, kBlock, 0, s>>>(w.huge_meta, cnt6, w.huge_tab_key, w.huge_tab_val, w.huge_best, salt, w.st);
+                                                                     w.st, gv, gs);
+  k_huge_scan<<<2048, kBlock, 0, s>>>(w.huge_meta, cnt6, w.huge_tab_key, w.huge_tab_val, w.huge_best, salt, w.st,
+                                      list6, gv, gs);
   k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, Lin, w.huge_tab_key,
-                                     w.huge_tab_val, Lout, nullptr, salt, 1, w.st);
+                                     w.huge_tab_val, Lout, nullptr, salt, 1, w.st, gv, gs);
   return hipGetLastError();
 }
 
-hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s) {
-  k_validate_sym<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, st);
+hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchView *bv) {
+  k_validate_sym<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, st, bv ? bv->gv : nullptr,
+                                                  bv ? bv->gs : nullptr);
   return hipGetLastError();
 }
 
-hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s) {
+hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const BatchView *bv, int32_t *gv_new) {
+  const int32_t *gv = bv ? bv->gv : nullptr;
+  const GStat *gs = bv ? bv->gs : nullptr;
   hipError_t e = fill_i32(w.ids, 0, (int64_t)n + 1, s);
   if (e != hipSuccess) return e;
-  k_flag_labels<<<grid_for(n), kBlock, 0, s>>>(L, n, w.ids);
-  e = scan_exclusive(w.ids, w.ids, n, &w.st->k, w.scan_tmp, w.scan_tmp_elems, s);
+  k_flag_labels<<<grid_for(n), kBlock, 0, s>>>(L, n, w.ids, gv, gs);
+  // batched: ids[n] = total too, the end of the last graph's range
+  e = scan_exclusive(w.ids, w.ids, bv ? (int64_t)n + 1 : n, &w.st->k, w.scan_tmp, w.scan_tmp_elems, s);
   if (e != hipSuccess) return e;
-  k_apply_ids<<<grid_for(n), kBlock, 0, s>>>(L, w.ids, n, w.cl);
+  k_apply_ids<<<grid_for(n), kBlock, 0, s>>>(L, w.ids, n, w.cl, gv, gs, gv_new);
   return hipGetLastError();
 }
 
 hipError_t compose_map(Work &w, hipStream_t s) {
-  k_compose<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.cl, w.n_in);
+  k_compose<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.cl, w.n_in, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1737,7 +2262,7 @@ hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStr
 }
 
 hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
-                          hipStream_t s) {
+                          hipStream_t s, bool single_bound) {
   int32_t *rowcnt = w.rp[dst];
   unsigned long long *degu = (unsigned long long *)w.deg;
   // free scratch while the sorted triples sit in buffer `which`
@@ -1759,6 +2284,7 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
   }
   e = scan_exclusive(rowcnt, rowcnt, (int64_t)k + 1, nullptr, w.scan_tmp, w.scan_tmp_elems, s);
   if (e != hipSuccess) return e;
+  if (!single_bound) return hipGetLastError();
   k_set_minkey<<<1, 64, 0, s>>>(w.st);
   k_min_degree<<<grid_for(k, kBlock, 1024), kBlock, 0, s>>>(degu, k, w.st);
   k_bound<<<1, 64, 0, s>>>(w.st, level, k);
@@ -1777,21 +2303,28 @@ hipError_t reset_bins(Work &w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s) {
+hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv) {
+  const int32_t *gv = bv ? bv->gv : nullptr;
+  GStat *gs = bv ? bv->gs : nullptr;
   hipError_t e = fill_i32(&w.st->nmarked, 0, 1, s);
   if (e == hipSuccess) e = fill_i32(&w.st->huge_items, 0, 1, s);
   if (e != hipSuccess) return e;
   const unsigned long long *degu = (const unsigned long long *)w.deg;
   int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
-  k_pr_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles,
-                                                               w.mark, heavy, w.st);
+  if (bv)
+    k_pr_tile<true><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta,
+                                                                       w.ntiles, w.mark, heavy, w.st, gv, gs);
+  else
+    k_pr_tile<false><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta,
+                                                                        w.ntiles, w.mark, heavy, w.st, nullptr,
+                                                                        nullptr);
   for (int b = 4; b <= 6; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
     if (items <= 0) continue;
     k_pr_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.bins + (int64_t)b * w.n_in,
-                                                          &w.st->bin_cnt[b], w.mark, heavy, w.st);
+                                                          &w.st->bin_cnt[b], w.mark, heavy, w.st, gv, gs);
   }
-  k_pr_heavy<<<1024, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, g.n, heavy, w.mark, w.st);
+  k_pr_heavy<<<1024, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, g.n, heavy, w.mark, w.st, gv, gs);
   return hipGetLastError();
 }
 
@@ -1816,6 +2349,93 @@ hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStr
 
 hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s) {
   k_side_witness<<<grid_for((w.n_in + 63) / 64), kBlock, 0, s>>>(w.witness, w.n_in, (unsigned long long *)side);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batched launchers
+hipError_t b_gs_init(GStat *gs, const GDesc *d, int32_t count, int32_t buf, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_gs_init<<<grid_for(count), kBlock, 0, s>>>(gs, d, count, buf);
+  return hipGetLastError();
+}
+
+hipError_t b_pack(const GDesc *d, int32_t count, int32_t rchunks, int32_t achunks, int32_t *gv, int32_t *map,
+                  int32_t *wg, int32_t *rpu, int32_t *colu, int32_t *wu, GStat *gs, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (rchunks > 0) {
+    k_pack_rows1<<<grid_for(rchunks, 1, 1u << 16), kBlock, 0, s>>>(d, count, rchunks, gv, map, wg, gs);
+    k_pack_rows2<<<grid_for(rchunks, 1, 1u << 16), kBlock, 0, s>>>(d, count, rchunks, rpu, gs);
+  }
+  if (achunks > 0) k_pack_arcs<<<grid_for(achunks, 1, 1u << 16), kBlock, 0, s>>>(d, count, achunks, colu, wu, gs);
+  return hipGetLastError();
+}
+
+hipError_t b_salts(GStat *gs, int32_t slots, uint64_t seed, int32_t lp_iters, int32_t t, bool pre, hipStream_t s) {
+  k_salts<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, seed, lp_iters, t, pre ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t b_gdeg(const long long *deg, int32_t v0, int32_t v1, const int32_t *gv, GStat *gs, bool with_sum,
+                  hipStream_t s) {
+  if (v1 <= v0) return hipSuccess;
+  k_gdeg<<<grid_for(v1 - v0, kBlock, 4096), kBlock, 0, s>>>((const unsigned long long *)deg, v0, v1, gv, gs,
+                                                             with_sum ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t b_gbound0(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap, hipStream_t s) {
+  k_gbound0<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, st, ring, ring_cap);
+  return hipGetLastError();
+}
+
+hipError_t b_step_top(GStat *gs, int32_t slots, int32_t n0, int32_t max_rounds, Status *st, GStat *ring,
+                      int32_t ring_cap, hipStream_t s) {
+  k_step_top<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, n0, max_rounds, st, ring, ring_cap);
+  return hipGetLastError();
+}
+
+hipError_t b_step_end(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap, hipStream_t s) {
+  k_step_end<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, st, ring, ring_cap);
+  return hipGetLastError();
+}
+
+hipError_t b_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, hipStream_t s) {
+  k_gsizes<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, ids, mode);
+  return hipGetLastError();
+}
+
+hipError_t b_gbound(GStat *gs, int32_t slots, const int32_t *rp, int32_t buf, Status *st, GStat *ring,
+                    int32_t ring_cap, hipStream_t s) {
+  k_gbound<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, rp, buf, st, ring, ring_cap);
+  return hipGetLastError();
+}
+
+hipError_t b_gwitness(const int32_t *map, const int32_t *wg, const GStat *gs, int32_t words,
+                      unsigned long long *wit, hipStream_t s) {
+  if (words <= 0) return hipSuccess;
+  k_gwitness<<<grid_for(64ll * words, kBlock, 8192), kBlock, 0, s>>>(map, wg, gs, words, wit);
+  return hipGetLastError();
+}
+
+hipError_t b_compose(int32_t *map, const int32_t *cl, int64_t entries, const int32_t *wg, const GStat *gs,
+                     hipStream_t s) {
+  if (entries <= 0) return hipSuccess;
+  k_compose<<<grid_for(entries), kBlock, 0, s>>>(map, cl, (int32_t)entries, wg, gs);
+  return hipGetLastError();
+}
+
+hipError_t b_gather(const GatherDesc *d, int32_t count, int32_t rchunks, int32_t achunks, int32_t *orp,
+                    int32_t *ocol, int32_t *ow, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_gather<<<grid_for(rchunks + achunks, 1, 1u << 16), kBlock, 0, s>>>(d, count, rchunks, rchunks + achunks, orp,
+                                                                        ocol, ow);
+  return hipGetLastError();
+}
+
+hipError_t b_side(const SideDesc *d, int32_t count, int32_t words, const int32_t *map,
+                  const unsigned long long *wit, const uint8_t *flags, int32_t *wg, hipStream_t s) {
+  if (count <= 0 || words <= 0) return hipSuccess;
+  k_side_batch<<<grid_for(64ll * words, kBlock, 8192), kBlock, 0, s>>>(d, count, words, map, wit, flags, wg);
   return hipGetLastError();
 }
 

@@ -199,6 +199,30 @@ int viecut_session_step(viecut_session *s, int32_t *n_active);
 int viecut_session_poll(viecut_session *s, int64_t *ids, viecut_result *outs, int32_t max);
 void viecut_session_destroy(viecut_session *s);
 
+/* ------------------------------------------------------------ kernel timing */
+/* Optional measurement aid, off by default and process-wide. While enabled,
+ * every launch of the arc-tile label-propagation kernels (first iteration,
+ * first iteration at level 0, iterations >= 2) is timed with a pair of HIP
+ * events on the stream it runs on, and its algorithmic bytes are counted from
+ * the exact row and arc totals of the tiles it sweeps:
+ *   k_first_tile        8 B per arc (col, w) + 8 B per row (row_ptr, label) + 16 B per tile
+ *   k_first_tile_level0 8 B per arc + 16 B per row (also the weighted degree) + 16 B per tile
+ *   k_lp_tile           12 B per arc (col, w, neighbour label) + 12 B per row (row_ptr, own
+ *                       label, new label) + 16 B per tile
+ * Timing adds two event records and a 16-byte copy per timed launch. */
+typedef struct {
+  char name[32];     /* kernel name */
+  int64_t launches;  /* timed launches since viecut_profile_enable(1) */
+  double total_ms;   /* summed event-to-event durations */
+  double bytes;      /* summed algorithmic bytes */
+} viecut_kernel_stat;
+
+/* on != 0: start timing and clear the totals; on == 0: stop. Returns VIECUT_OK or VIECUT_ENOMEM. */
+int viecut_profile_enable(int on);
+/* Copies up to max totals into out (host array); returns how many, or VIECUT_EINVAL. Totals cover
+ * the solves that have returned (batched: the rounds completed). */
+int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
+
 /* Static message for a status code. */
 const char *viecut_strerror(int code);
 

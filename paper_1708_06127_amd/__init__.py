@@ -28,7 +28,7 @@ F_VALIDATE = 1
 EXPORTED = ["viecut_default_params", "viecut_workspace_bytes", "viecut_mincut", "viecut_mincut_trace",
             "viecut_validate", "viecut_batch_workspace_bytes", "viecut_mincut_batch", "viecut_session_create",
             "viecut_session_submit", "viecut_session_step", "viecut_session_poll", "viecut_session_destroy",
-            "viecut_strerror"]
+            "viecut_profile_enable", "viecut_profile_read", "viecut_strerror"]
 
 
 class Csr(ctypes.Structure):
@@ -62,6 +62,11 @@ class Event(ctypes.Structure):
 
 
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(Event))
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 class ViecutError(RuntimeError):
@@ -112,6 +117,10 @@ def load():
         lib.viecut_session_poll.restype = ctypes.c_int
         lib.viecut_session_destroy.argtypes = [vp]
         lib.viecut_session_destroy.restype = None
+    lib.viecut_profile_enable.argtypes = [ctypes.c_int]
+    lib.viecut_profile_enable.restype = ctypes.c_int
+    lib.viecut_profile_read.argtypes = [P(KernelStat), i32]
+    lib.viecut_profile_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -335,3 +344,19 @@ class Session:
             self.close()
         except Exception:
             pass
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing the totals) or stop event timing of the arc-tile
+    label-propagation kernels (see viecut_profile_enable)."""
+    _check(load().viecut_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """Totals per timed kernel: {name: {"launches", "total_ms", "bytes"}}."""
+    out = (KernelStat * 8)()
+    k = load().viecut_profile_read(out, 8)
+    if k < 0:
+        _check(k)
+    return {out[i].name.decode(): {"launches": int(out[i].launches), "total_ms": float(out[i].total_ms),
+                                   "bytes": float(out[i].bytes)} for i in range(k)}

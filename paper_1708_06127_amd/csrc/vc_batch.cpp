@@ -23,6 +23,8 @@
 #include <atomic>
 #include <chrono>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -206,6 +208,10 @@ struct Engine {
   std::deque<ReqRec> pending;
   std::vector<DoneRec> staged, ready;
   unsigned n_threads = 1;
+  // phase times (host clock, ms) for VIECUT_LOG=1 diagnostics
+  bool verbose = false;
+  double t_sync = 0, t_drain_read = 0, t_gather = 0, t_solve = 0, t_side = 0, t_admit = 0;
+  int64_t n_syncs = 0, n_steps = 0, n_solved = 0;
 
   Engine(const Engine &) = delete;
   Engine &operator=(const Engine &) = delete;
@@ -258,6 +264,8 @@ struct Engine {
     for (int32_t i = cap.s - 1; i >= 0; i--) free_slots.push_back(i);
     slot_req.assign(cap.s, ReqRec{});
     n_threads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const char *lg = getenv("VIECUT_LOG");
+    verbose = lg && lg[0] == '1';
     return VIECUT_OK;
   }
 
@@ -276,8 +284,11 @@ struct Engine {
   }
 
   int sync_status() {
+    const double t0 = now_ms();
     VC_TRY(hipMemcpyAsync(hst(), w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
+    t_sync += now_ms() - t0;
+    n_syncs++;
     return VIECUT_OK;
   }
 
@@ -349,11 +360,13 @@ struct Engine {
     if (m > cap.s) return VIECUT_EDEVICE;  // cannot happen: one entry per admitted graph between drains
     const int32_t first = drained % cap.s;
     const int32_t n1 = std::min(m, cap.s - first);
+    double t0 = now_ms();
     GStat *he = h_ring.as<GStat>();
     VC_TRY(hipMemcpyAsync(he, ring + first, sizeof(GStat) * n1, hipMemcpyDeviceToHost, s));
     if (m > n1) VC_TRY(hipMemcpyAsync(he + n1, ring, sizeof(GStat) * (m - n1), hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
     drained = cnt;
+    t_drain_read += now_ms() - t0;
 
     // exact solve on the last level of graphs that left the loop unsolved
     std::vector<int32_t> solve;
@@ -394,6 +407,7 @@ struct Engine {
       if (!h_rp.ensure(4 * (size_t)rows) || !h_col.ensure(4 * (size_t)std::max<int64_t>(arcs, 1)) ||
           !h_w.ensure(4 * (size_t)std::max<int64_t>(arcs, 1)))
         return VIECUT_ENOMEM;
+      t0 = now_ms();
       int32_t *srp = w.cnt, *scol = (int32_t *)w.keys[0], *sw = w.vals[0];  // free at every drain point
       VC_TRY(hipMemcpyAsync(d_gdesc, gd, sizeof(GatherDesc) * cnt_g, hipMemcpyHostToDevice, s));
       VC_TRY(b_gather(d_gdesc, cnt_g, rch, ach, srp, scol, sw, s));
@@ -403,6 +417,8 @@ struct Engine {
         VC_TRY(hipMemcpyAsync(h_w.p, sw, 4 * (size_t)arcs, hipMemcpyDeviceToHost, s));
       }
       VC_TRY(hipStreamSynchronize(s));
+      t_gather += now_ms() - t0;
+      t0 = now_ms();
       // solve the group on host threads
       std::vector<std::vector<uint8_t>> kside(cnt_g);
       std::vector<int64_t> kcut(cnt_g);
@@ -423,6 +439,8 @@ struct Engine {
         for (unsigned t = 0; t < nt; t++) th.emplace_back(work);
         for (auto &t : th) t.join();
       }
+      t_solve += now_ms() - t0;
+      n_solved += cnt_g;
       for (int32_t j = 0; j < cnt_g; j++) {
         const int32_t i = solve[pos + j];
         lk[i] = kcut[j];
@@ -435,6 +453,7 @@ struct Engine {
     }
 
     // sides and results
+    t0 = now_ms();
     if (!flags.empty()) {
       if (flags.size() > (size_t)cap.n + 1) return VIECUT_EDEVICE;  // one level holds them all
       if (!h_flags.ensure(flags.size())) return VIECUT_ENOMEM;
@@ -482,7 +501,17 @@ struct Engine {
     VC_TRY(b_side(d_sdesc, m, wsum, w.map, w.witness, w.flags8, wg, s));
     // the descriptors in pinned memory must not change before the copies ran
     VC_TRY(hipStreamSynchronize(s));
+    t_side += now_ms() - t0;
     return VIECUT_OK;
+  }
+
+  void report(const char *what) const {
+    if (!verbose) return;
+    fprintf(stderr,
+            "[viecut] %s: steps %lld syncs %lld (%.2f ms) ring read %.2f ms, gather %.2f ms, exact solves %lld "
+            "(%.2f ms), sides %.2f ms, admission %.2f ms\n",
+            what, (long long)n_steps, (long long)n_syncs, t_sync, t_drain_read, t_gather, (long long)n_solved,
+            t_solve, t_side, t_admit);
   }
 
   // results whose side kernels have completed become readable; t_ms[5] is
@@ -549,9 +578,12 @@ struct Engine {
   // Admits what fits, then runs one round for every graph in the loop.
   int step() {
     int32_t n_fresh = 0, N0 = 0;
+    const double ta = now_ms();
     int rc = admit(n_fresh, N0);
+    t_admit += now_ms() - ta;
     if (rc) return rc;
     if (n_active == 0 && n_fresh == 0) return VIECUT_OK;
+    n_steps++;
     DGraph G;
     G.n = N;
     G.nnz = A;
@@ -611,6 +643,7 @@ struct Engine {
       known = known_buf;
     }
     publish();
+    prof_collect();
     return VIECUT_OK;
   }
 
@@ -697,6 +730,7 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
     }
   }
   for (const auto &d : eng.ready) outs[d.id] = d.res;
+  eng.report("batch");
   return VIECUT_OK;
 }
 
@@ -748,6 +782,7 @@ int viecut_session_poll(viecut_session *s, int64_t *ids, viecut_result *outs, in
 void viecut_session_destroy(viecut_session *s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->eng.s);
+  s->eng.report("session");
   delete s;
 }
 

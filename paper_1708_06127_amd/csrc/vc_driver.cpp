@@ -26,6 +26,90 @@ uint64_t splitmix64_at(uint64_t seed, uint64_t index) {
   return z ^ (z >> 31);
 }
 
+// ------------------------------------------------------------ kernel timing
+// Process-wide and off by default. While on, each timed launch gets an event
+// pair on its stream and a 16-byte copy of the level's tile totals (rows,
+// arcs) into page-locked memory; prof_collect() folds completed records into
+// per-kernel totals of duration and algorithmic bytes.
+namespace {
+struct ProfRec {
+  int kind;
+  int32_t ntiles;
+  hipEvent_t a, b;
+};
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  int32_t *slots = nullptr;  // 4 int32 per record: tile_rows, pad, tile_arcs (u64)
+  int32_t cap = 0;
+  int64_t launches[PROF_KINDS] = {0};
+  double ms[PROF_KINDS] = {0}, bytes[PROF_KINDS] = {0};
+};
+ProfState &prof() {
+  static ProfState p;
+  return p;
+}
+const char *kProfNames[PROF_KINDS] = {"k_first_tile", "k_first_tile_level0", "k_lp_tile"};
+// algorithmic bytes per arc and per row of each timed kernel
+const double kProfPerArc[PROF_KINDS] = {8, 8, 12};   // col, w (+ the label gather Lin[col])
+const double kProfPerRow[PROF_KINDS] = {8, 16, 12};  // rp + label out (+ degree, + own label)
+hipEvent_t prof_event(ProfState &p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+ProfScope::ProfScope(ProfKind kind, hipStream_t stream, const Status *st_, int32_t ntiles) : s(stream), st(st_) {
+  ProfState &p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (!p.on || !p.slots || (int32_t)p.pending.size() >= p.cap) return;
+  ProfRec r;
+  r.kind = kind;
+  r.ntiles = ntiles;
+  r.a = prof_event(p);
+  r.b = prof_event(p);
+  if (!r.a || !r.b || hipEventRecord(r.a, s) != hipSuccess) return;
+  slot = (int)p.pending.size();
+  p.pending.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+  if (slot < 0) return;
+  ProfState &p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (slot >= (int)p.pending.size()) return;
+  (void)hipEventRecord(p.pending[slot].b, s);
+  (void)hipMemcpyAsync(&p.slots[4 * slot], &st->tile_rows, 16, hipMemcpyDeviceToHost, s);
+}
+
+void prof_collect() {
+  ProfState &p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  for (size_t i = 0; i < p.pending.size(); i++) {
+    ProfRec &r = p.pending[i];
+    float ms = 0;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      const int32_t rows = p.slots[4 * i];
+      uint64_t arcs;
+      std::memcpy(&arcs, &p.slots[4 * i + 2], 8);
+      p.launches[r.kind]++;
+      p.ms[r.kind] += ms;
+      p.bytes[r.kind] += kProfPerArc[r.kind] * (double)arcs + kProfPerRow[r.kind] * rows + 16.0 * r.ntiles;
+    }
+    p.pool.push_back(r.a);
+    p.pool.push_back(r.b);
+  }
+  p.pending.clear();
+}
+
 namespace {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -425,6 +509,7 @@ int solve_one(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_b
   viecut_result res{};
   rc = sv.run(*g, &res, side);
   if (rc != VIECUT_OK) (void)hipStreamSynchronize(s);
+  prof_collect();
   if (own) (void)hipFree(own);
   if (rc == VIECUT_OK) *out = res;
   return rc;
@@ -489,6 +574,44 @@ int viecut_validate(const viecut_csr *g, uint32_t flags, void *stream) {
   if (st.wsum / 2 > (unsigned long long)INT32_MAX) return VIECUT_EOVERFLOW;
   if (st.err & (vc::ERR_NOTSYM | vc::ERR_UNSORTED)) return VIECUT_ENOTSYM;
   return VIECUT_OK;
+}
+
+int viecut_profile_enable(int on) {
+  vc::ProfState &p = vc::prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (on) {
+    if (!p.slots) {
+      const int32_t cap = 1 << 16;
+      if (hipHostMalloc((void **)&p.slots, 16 * (size_t)cap, 0) != hipSuccess) {
+        p.slots = nullptr;
+        return VIECUT_ENOMEM;
+      }
+      p.cap = cap;
+    }
+    for (int k = 0; k < vc::PROF_KINDS; k++) {
+      p.launches[k] = 0;
+      p.ms[k] = 0;
+      p.bytes[k] = 0;
+    }
+  }
+  p.on = on != 0;
+  return VIECUT_OK;
+}
+
+int viecut_profile_read(viecut_kernel_stat *out, int32_t max) {
+  if (max < 0 || (max > 0 && !out)) return VIECUT_EINVAL;
+  vc::prof_collect();
+  vc::ProfState &p = vc::prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  const int32_t k = std::min<int32_t>(max, vc::PROF_KINDS);
+  for (int32_t i = 0; i < k; i++) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::strncpy(out[i].name, vc::kProfNames[i], sizeof(out[i].name) - 1);
+    out[i].launches = p.launches[i];
+    out[i].total_ms = p.ms[i];
+    out[i].bytes = p.bytes[i];
+  }
+  return k;
 }
 
 const char *viecut_strerror(int code) {

@@ -56,7 +56,10 @@ struct Status {
   int32_t bin_cnt[8];          // vertices per degree class
   int32_t ring_cnt;            // (batched) finished graphs pushed to the ring so far
   int32_t active_cnt;          // (batched) graphs still in the round loop
-  int32_t pad1[2];
+  int32_t tile_rows;           // rows covered by the arc tiles of the current level
+  int32_t pad1;
+  unsigned long long tile_arcs;  // arcs covered by the arc tiles of the current level
+  int32_t pr_rows[2];          // rows marked with an LDS table of their row (short / long tables)
 };
 
 // ------------------------------------------------------------ batched solves
@@ -244,6 +247,18 @@ hipError_t b_side(const SideDesc *d, int32_t count, int32_t words, const int32_t
                   const unsigned long long *wit, const uint8_t *flags, int32_t *wg, hipStream_t s);
 constexpr int kPackRows = 2048;  // rows (input index entries) per chunk of the packing and gather work
 constexpr int kPackArcs = 8192;  // arcs per chunk of the packing and gather work
+
+// ---- optional kernel timing (viecut_profile_*): an event pair around a
+// launch plus a copy of the level's tile totals for its algorithmic bytes
+enum ProfKind : int { PROF_FIRST_TILE = 0, PROF_FIRST_TILE_L0 = 1, PROF_LP_TILE = 2, PROF_KINDS = 3 };
+struct ProfScope {
+  int slot = -1;
+  hipStream_t s;
+  const Status *st;
+  ProfScope(ProfKind kind, hipStream_t stream, const Status *st, int32_t ntiles);
+  ~ProfScope();
+};
+void prof_collect();  // after a synchronisation: fold finished records into the totals
 
 // host driver entry points shared by the single, batched and session paths
 int check_args(const viecut_csr *g, const viecut_params *p);

@@ -159,6 +159,8 @@ __global__ void k_status_reset(Status *st) {
     st->huge_slots = 0;
     st->ring_cnt = 0;
     st->active_cnt = 0;
+    st->tile_rows = 0;
+    st->tile_arcs = 0;
   }
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
 }
@@ -186,12 +188,23 @@ __device__ __forceinline__ int32_t tile_start(const int32_t *rp, int32_t n, int6
   }
   return lo;
 }
-__global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta) {
+__global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  unsigned long long rows = 0, arcs = 0;
   for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * kBlock) {
     const int32_t r0 = tile_start(rp, n, t * (int64_t)kTile);
     int32_t r1 = t + 1 == ntiles ? n : tile_start(rp, n, (t + 1) * (int64_t)kTile);
     if (r1 > r0 && rp[r1] - rp[r1 - 1] >= kTile) r1--;
     meta[t] = make_int4(r0, r1 - r0, rp[r0], rp[r1] - rp[r0]);
+    rows += (unsigned long long)(r1 - r0);
+    arcs += (unsigned long long)(rp[r1] - rp[r0]);
+  }
+  // totals over the tiles (the algorithmic size of a tile sweep)
+  rows = block_sum(rows, sh);
+  arcs = block_sum(arcs, sh);
+  if (threadIdx.x == 0) {
+    if (rows) atomicAdd(&st->tile_rows, (int32_t)rows);
+    if (arcs) atomicAdd(&st->tile_arcs, arcs);
   }
 }
 
@@ -1289,36 +1302,51 @@ __global__ void k_seg_heads(const unsigned long long *keys, int64_t count, int32
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
     head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
 }
-// seg = exclusive scan of head; each element adds its weight to its segment
-// (wave-level segmented pre-reduction keeps atomics to one per segment piece)
+// seg = exclusive scan of head; each element adds its weight to its segment.
+// Within a wave, a segmented scan keyed by segment leaves one weight
+// contribution per segment piece, and a second one keyed by row leaves one
+// degree and one column-count contribution per row piece, so the atomics
+// are few and rarely on the same address.
 __global__ void k_seg_write(const unsigned long long *keys, const int32_t *vals, int64_t count, const int32_t *seg,
                             const int32_t *head, int key_bits, int32_t *colo, int32_t *wo, int32_t *rowcnt,
                             unsigned long long *degu) {
   const int lane = threadIdx.x & 63;
   const unsigned long long mask_lo = (1ull << key_bits) - 1;
   for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
-    int64_t i = base + threadIdx.x;
-    bool ok = i < count;
-    unsigned long long k = ok ? keys[i] : ~0ull;
-    int32_t h = ok ? head[i] : 1;
-    int32_t s = ok ? seg[i] + h - 1 : -1;  // segment index of element i
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < count;
+    const unsigned long long k = ok ? keys[i] : ~0ull;
+    const int32_t h = ok ? head[i] : 1;
+    const int32_t s = ok ? seg[i] + h - 1 : -1;  // segment index of element i
     unsigned long long x = ok ? (unsigned long long)(uint32_t)vals[i] : 0;
-    // segmented inclusive scan within the wave (segments keyed by s)
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      unsigned long long y = __shfl_up(x, off, 64);
-      int32_t sy = __shfl_up(s, off, 64);
+      const unsigned long long y = __shfl_up(x, off, 64);
+      const int32_t sy = __shfl_up(s, off, 64);
       if (lane >= off && sy == s) x += y;
     }
-    int32_t s_next = __shfl_down(s, 1, 64);
-    bool last = (lane == 63) || (s_next != s);
-    if (ok && last) {
-      atomicAdd((uint32_t *)&wo[s], (uint32_t)x);
-      atomicAdd(&degu[k >> key_bits], x);
+    const int32_t s_next = __shfl_down(s, 1, 64);
+    const bool last = (lane == 63) || (s_next != s);
+    if (ok && last) atomicAdd((uint32_t *)&wo[s], (uint32_t)x);
+    if (ok && h) colo[s] = (int32_t)(k & mask_lo);
+    // per row piece: degree (sum of the segment pieces) and new columns (heads)
+    const long long row = ok ? (long long)(k >> key_bits) : -1;
+    unsigned long long dsum = (ok && last) ? x : 0;
+    int32_t hsum = (ok && h) ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned long long y = __shfl_up(dsum, off, 64);
+      const int32_t hy = __shfl_up(hsum, off, 64);
+      const long long ry = __shfl_up(row, off, 64);
+      if (lane >= off && ry == row) {
+        dsum += y;
+        hsum += hy;
+      }
     }
-    if (ok && h) {
-      colo[s] = (int32_t)(k & mask_lo);
-      atomicAdd(&rowcnt[k >> key_bits], 1);
+    const long long r_next = __shfl_down(row, 1, 64);
+    if (ok && (lane == 63 || r_next != row)) {
+      if (dsum) atomicAdd(&degu[row], dsum);
+      if (hsum) atomicAdd(&rowcnt[row], hsum);
     }
   }
 }
@@ -1328,7 +1356,11 @@ __global__ void k_set_minkey(Status *st) {
 }
 __global__ void k_reset_bins(Status *st) {
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
-  if (threadIdx.x == 0) st->dmax = 0;
+  if (threadIdx.x == 0) {
+    st->dmax = 0;
+    st->tile_rows = 0;
+    st->tile_arcs = 0;
+  }
 }
 
 __global__ void k_min_degree(const unsigned long long *degu, int32_t n, Status *st) {
@@ -1372,125 +1404,31 @@ __global__ void k_witness(const int32_t *map, int32_t n_in, const Status *st, un
 }
 
 // ------------------------------------------------------------ Padberg-Rinaldi
-// One group of 16 lanes per vertex v; for each arc (v, x) with v < x the
-// group tests conditions 1-4 (2 and 3 strict), intersecting the two sorted
-// rows by binary search of the shorter row's entries in the longer row.
-__global__ __launch_bounds__(kBlock) void k_pr_mark(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                     const int32_t *__restrict__ w,
-                                                     const unsigned long long *__restrict__ degu, int32_t n,
-                                                     uint8_t *__restrict__ mark, Status *st) {
-  constexpr int G = 16;
-  __shared__ unsigned long long sh[kBlock / 64];
-  const int gi = threadIdx.x / G, lane = threadIdx.x % G;
-  const long long lam = st->lam_hat;
-  unsigned long long nm = 0;
-  for (int64_t base = blockIdx.x * (int64_t)(kBlock / G); base < n; base += (int64_t)gridDim.x * (kBlock / G)) {
-    int64_t v = base + gi;
-    if (v >= n) continue;
-    const int32_t vb = rp[v], ve = rp[v + 1];
-    const long long dv = (long long)degu[v];
-    for (int32_t i = vb; i < ve; i++) {
-      const int32_t x = col[i];
-      if (x <= v) {
-        if (lane == 0) mark[i] = 0;
-        continue;
-      }
-      const long long c = w[i];
-      const long long dx = (long long)degu[x];
-      bool m = (c >= lam) || (dv < 2 * c) || (dx < 2 * c);
-      if (!m) {
-        const int32_t xb = rp[x], xe = rp[x + 1];
-        // iterate over the shorter row, search in the longer one
-        const bool v_short = (ve - vb) <= (xe - xb);
-        const int32_t sb = v_short ? vb : xb, se = v_short ? ve : xe;
-        const int32_t lb = v_short ? xb : vb, le = v_short ? xe : ve;
-        long long sum4 = 0;
-        int pr3 = 0;
-        for (int32_t j = sb + lane; j < se; j += G) {
-          const int32_t u = col[j];
-          int32_t lo = lb, hi = le;
-          while (lo < hi) {
-            int32_t mid = (lo + hi) >> 1;
-            if (col[mid] < u) lo = mid + 1; else hi = mid;
-          }
-          if (lo < le && col[lo] == u) {
-            const long long cvu = v_short ? w[j] : w[lo];
-            const long long cxu = v_short ? w[lo] : w[j];
-            if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) pr3 = 1;
-            sum4 += cvu < cxu ? cvu : cxu;
-          }
-        }
-        sum4 = (long long)grp_sum<G>((unsigned long long)sum4);
-        pr3 = grp_or<G>(pr3);
-        m = pr3 || (c + sum4 >= lam);
-      }
-      if (lane == 0) {
-        mark[i] = m ? 1 : 0;
-        nm += m ? 1 : 0;
-      }
-    }
-  }
-  nm = block_sum(nm, sh);
-  if (threadIdx.x == 0 && nm) atomicAdd(&st->nmarked, (int32_t)nm);
-}
-
-// Arc-parallel marking on the tiles: each thread tests its arcs (v, x) with
-// v < x. Conditions 1 and 2 need only the weights and degrees; 3 and 4 need
-// the common neighbourhood, intersected sequentially by the thread when the
-// shorter row has at most kPrSeq entries, otherwise the arc is queued for a
-// wave (k_pr_heavy). `flag` records that some edge was marked.
-constexpr int kPrSeq = 64;
+// Conditions 1-4 of the lemma (2 and 3 strict) on every edge {v, x}. Each
+// edge is decided once, by its OWNER: the endpoint with the longer row (ties:
+// the smaller id). The mark goes on the owner's arc; the other arc gets 0
+// (the union-find takes an edge from either arc). Conditions 1 and 2 need
+// only the weight and the two degrees; 3 and 4 need the common
+// neighbourhood N(v) & N(x), and the scan stops as soon as condition 3 holds
+// or the condition-4 sum reaches lambda-hat, which does not change the
+// decision. Who intersects:
+//  * rows shorter than kPrRow arcs, in the tiles: the owner's thread merges
+//    the two short rows;
+//  * rows of kPrRow..kPrLds arcs: a workgroup per row holds the row in an LDS
+//    hash table (neighbour -> weight); one wave per owned arc scans the other
+//    (not longer) row in 64-wide chunks and probes the table;
+//  * rows longer than kPrLds: owned arcs that the cheap tests leave open are
+//    queued; a wave per arc binary-searches the long row for the other row's
+//    entries, 64 at a time.
+constexpr int kPrRow = 32;
+constexpr int kPrSmallMax = 512;   // rows up to this length use the small table
+constexpr int kPrLds = 4096;
 
 __device__ __forceinline__ bool pr_cheap(long long c, long long dv, long long dx, long long lam) {
   return c >= lam || dv < 2 * c || dx < 2 * c;
 }
-// conditions 3 and 4 by a sequential intersection of sorted rows
-__device__ bool pr_intersect_seq(const int32_t *col, const int32_t *w, int32_t vb, int32_t ve, int32_t xb, int32_t xe,
-                                 long long c, long long dv, long long dx, long long lam) {
-  const bool v_short = (ve - vb) <= (xe - xb);
-  const int32_t sb = v_short ? vb : xb, se = v_short ? ve : xe;
-  const int32_t lb = v_short ? xb : vb, le = v_short ? xe : ve;
-  long long sum4 = c;
-  int32_t lo = lb;
-  for (int32_t j = sb; j < se; j++) {
-    const int32_t u = col[j];
-    int32_t hi = le;  // rows are sorted: the search window only moves right
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (col[mid] < u) lo = mid + 1; else hi = mid;
-    }
-    if (lo < le && col[lo] == u) {
-      const long long cvu = v_short ? w[j] : w[lo];
-      const long long cxu = v_short ? w[lo] : w[j];
-      if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
-      sum4 += cvu < cxu ? cvu : cxu;
-      if (sum4 >= lam) return true;
-    }
-  }
-  return sum4 >= lam;
-}
-
-// Returns whether arc i was marked. lam < 0: the row's graph is out of the
-// round loop (batched), nothing is marked.
-__device__ __forceinline__ bool pr_arc(const int32_t *rp, const int32_t *col, const int32_t *w,
-                                       const unsigned long long *degu, int32_t v, int32_t i, long long lam,
-                                       uint8_t *mark, int32_t *heavy, Status *st) {
-  const int32_t x = col[i];
-  if (x <= v || lam < 0) { mark[i] = 0; return false; }
-  const long long c = w[i];
-  const long long dv = (long long)degu[v], dx = (long long)degu[x];
-  bool m = pr_cheap(c, dv, dx, lam);
-  if (!m) {
-    const int32_t vb = rp[v], ve = rp[v + 1], xb = rp[x], xe = rp[x + 1];
-    if (min(ve - vb, xe - xb) > kPrSeq) {
-      heavy[atomicAdd(&st->huge_items, 1)] = i;  // decided by k_pr_heavy
-      mark[i] = 0;
-      return false;
-    }
-    m = pr_intersect_seq(col, w, vb, ve, xb, xe, c, dv, dx, lam);
-  }
-  mark[i] = m ? 1 : 0;
-  return m;
+__device__ __forceinline__ bool pr_owner(int32_t v, int32_t lv, int32_t x, int32_t lx) {
+  return lv > lx || (lv == lx && v < x);
 }
 // batched: bound of the row's graph, or -1 when it is out of the loop
 __device__ __forceinline__ long long graph_lam(const GStat &g) { return g.state == GS_ACTIVE ? g.lam_hat : -1; }
@@ -1502,12 +1440,36 @@ __device__ __forceinline__ void flag_marked(GStat *gs, int32_t g, int32_t &flagg
     atomicExch(&gs[g].nmarked, 1);
 }
 
+// conditions 3 and 4 by merging two short sorted rows
+__device__ bool pr_merge(const int32_t *col, const int32_t *w, int32_t vb, int32_t ve, int32_t xb, int32_t xe,
+                         long long c, long long dv, long long dx, long long lam) {
+  long long sum4 = c;
+  int32_t i = vb, j = xb;
+  while (i < ve && j < xe) {
+    const int32_t a = col[i], b = col[j];
+    if (a < b) {
+      i++;
+    } else if (b < a) {
+      j++;
+    } else {
+      const long long cvu = w[i], cxu = w[j];
+      if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
+      sum4 += cvu < cxu ? cvu : cxu;
+      if (sum4 >= lam) return true;
+      i++;
+      j++;
+    }
+  }
+  return sum4 >= lam;
+}
+
+// Short rows on the tiles. Rows of kPrRow arcs or more are left to k_pr_rows.
 template <bool B>
 __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w,
                                                      const unsigned long long *__restrict__ degu,
                                                      const int4 *__restrict__ meta, int32_t ntiles,
-                                                     uint8_t *__restrict__ mark, int32_t *heavy, Status *st,
+                                                     uint8_t *__restrict__ mark, Status *st,
                                                      const int32_t *__restrict__ gv, GStat *gs) {
   __shared__ int32_t s_rp[kTile + 1];
   __shared__ int s_any;
@@ -1536,9 +1498,23 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
       const int32_t iend = min(i0 + q, acnt);
       for (int32_t i = i0; i < iend; i++) {
         while (i >= s_rp[j + 1]) j++;
-        const bool mk = pr_arc(rp, col, w, degu, r0 + j, a0 + i, B ? s_lam[j] : lam0, mark, heavy, st);
-        any = any || mk;
-        if (B && mk) flag_marked(gs, s_g[j], flagged);
+        const int32_t lv = s_rp[j + 1] - s_rp[j];
+        if (lv >= kPrRow) continue;  // k_pr_rows
+        const int32_t v = r0 + j, a = a0 + i;
+        const int32_t x = col[a];
+        const int32_t xb = rp[x], xe = rp[x + 1];
+        const long long lam = B ? s_lam[j] : lam0;
+        bool mk = false;
+        if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
+          const long long c = w[a];
+          const long long dv = (long long)degu[v], dx = (long long)degu[x];
+          mk = pr_cheap(c, dv, dx, lam) || pr_merge(col, w, a0 + s_rp[j], a0 + s_rp[j + 1], xb, xe, c, dv, dx, lam);
+        }
+        mark[a] = mk ? 1 : 0;
+        if (mk) {
+          any = true;
+          if constexpr (B) flag_marked(gs, s_g[j], flagged);
+        }
       }
     }
     if (any) s_any = 1;
@@ -1548,6 +1524,122 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
   }
 }
 
+// rows of kPrRow..kPrSmallMax arcs from the front of `list`, longer ones up
+// to kPrLds from the back
+__global__ void k_pr_list(const int32_t *rp, int32_t n, int32_t *list, Status *st) {
+  __shared__ int32_t cnt[2], base[2];
+  for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t v = b0 + threadIdx.x;
+    const int32_t d = v < n ? rp[v + 1] - rp[v] : 0;
+    const int cls = (d >= kPrRow && d <= kPrSmallMax) ? 0 : (d > kPrSmallMax && d <= kPrLds) ? 1 : -1;
+    const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < 2) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&st->pr_rows[threadIdx.x], cnt[threadIdx.x]) : 0;
+    __syncthreads();
+    if (cls == 0) list[base[0] + pos] = (int32_t)v;
+    if (cls == 1) list[n - 1 - (base[1] + pos)] = (int32_t)v;
+    __syncthreads();
+  }
+}
+
+// A workgroup per listed row v: v's row in an LDS hash table of 2 |row|
+// slots; one 16-lane group per owned arc (v, x) scans x's row against it,
+// 16 entries at a time (4 arcs in flight per wave, loads still coalesced).
+// Partial sums are 32-bit: c + sum <= deg(v) <= total weight <= INT32_MAX.
+constexpr int kPrGroup = 16;
+template <int TBL, bool B>
+__global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ w,
+                                                     const unsigned long long *__restrict__ degu,
+                                                     const int32_t *__restrict__ list, int which, int32_t n,
+                                                     uint8_t *__restrict__ mark, Status *st,
+                                                     const int32_t *__restrict__ gv, GStat *gs) {
+  __shared__ int32_t tkey[TBL];
+  __shared__ int32_t tval[TBL];
+  __shared__ int s_any;
+  constexpr int G = kPrGroup;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  const int32_t cnt = st->pr_rows[which];
+  int32_t flagged = -1;
+  for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+    const int32_t v = which == 0 ? list[r] : list[n - 1 - r];
+    const int32_t vb = rp[v], ve = rp[v + 1], lv = ve - vb;
+    const uint32_t size = 2u * (uint32_t)lv;
+    const int32_t g = B ? gv[v] : 0;
+    const long long lam = B ? graph_lam(gs[g]) : st->lam_hat;
+    for (int e = threadIdx.x; e < (int)size; e += kBlock) tkey[e] = -1;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    for (int32_t i = vb + threadIdx.x; i < ve; i += kBlock) {  // distinct keys: one free slot each
+      const int32_t u = col[i];
+      uint32_t h = (uint32_t)(((unsigned long long)slot_hash(u) * size) >> 32);
+      while (atomicCAS(&tkey[h], -1, u) != -1) h = (h + 1 == size) ? 0 : h + 1;
+      tval[h] = w[i];
+    }
+    __syncthreads();
+    const long long dv = (long long)degu[v];
+    bool any = false;
+    for (int32_t i = vb + grp; i < ve; i += kBlock / G) {
+      const int32_t x = col[i];
+      const int32_t xb = rp[x], xe = rp[x + 1];
+      bool mk = false;
+      if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
+        const long long c = w[i];
+        const long long dx = (long long)degu[x];
+        mk = pr_cheap(c, dv, dx, lam);
+        if (!mk) {
+          // condition 3 for a common neighbour u: w(v,u) > dv/2 - c and w(x,u) > dx/2 - c
+          const long long tv = dv / 2 - c, tx = dx / 2 - c;  // dv < 2(c + a) <=> a > floor(dv/2) - c
+          long long sum4 = c;
+          int pr3 = 0;
+          for (int32_t j0 = xb; j0 < xe; j0 += G) {
+            const int32_t j = j0 + lane;
+            uint32_t part = 0;
+            int p3 = 0;
+            if (j < xe) {
+              const int32_t u = col[j];
+              uint32_t h = (uint32_t)(((unsigned long long)slot_hash(u) * size) >> 32);
+              while (true) {
+                const int32_t k = tkey[h];
+                if (k == u) {
+                  const int32_t cvu = tval[h], cxu = w[j];
+                  if (cvu > tv && cxu > tx) p3 = 1;
+                  part = (uint32_t)(cvu < cxu ? cvu : cxu);
+                  break;
+                }
+                if (k == -1) break;
+                h = (h + 1 == size) ? 0 : h + 1;
+              }
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+              part += __shfl_xor(part, off, G);
+              p3 |= __shfl_xor(p3, off, G);
+            }
+            sum4 += part;
+            pr3 |= p3;
+            if (pr3 || sum4 >= lam) break;  // decided
+          }
+          mk = pr3 || sum4 >= lam;
+        }
+      }
+      if (lane == 0) mark[i] = mk ? 1 : 0;
+      if (mk) {
+        any = true;
+        if constexpr (B)
+          if (lane == 0) flag_marked(gs, g, flagged);
+      }
+    }
+    if (any && lane == 0) s_any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_any && st->nmarked == 0) atomicExch(&st->nmarked, 1);
+    __syncthreads();
+  }
+}
+
+// rows longer than kPrLds: cheap tests per owned arc, the rest queued
 __global__ void k_pr_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                           const int32_t *__restrict__ w, const unsigned long long *__restrict__ degu,
                           const int32_t *list, const int32_t *cnt_p, uint8_t *__restrict__ mark, int32_t *heavy,
@@ -1557,15 +1649,26 @@ __global__ void k_pr_long(const int32_t *__restrict__ rp, const int32_t *__restr
   int32_t flagged = -1;
   for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
     const int32_t v = list[r];
+    const int32_t vb = rp[v], ve = rp[v + 1], lv = ve - vb;
     const int32_t g = gv ? gv[v] : 0;
     const long long lam = gv ? graph_lam(gs[g]) : st->lam_hat;
+    const long long dv = (long long)degu[v];
     if (threadIdx.x == 0) s_any = 0;
     __syncthreads();
     bool any = false;
-    for (int32_t i = rp[v] + threadIdx.x; i < rp[v + 1]; i += kBlock) {
-      const bool mk = pr_arc(rp, col, w, degu, v, i, lam, mark, heavy, st);
-      any = any || mk;
-      if (gv && mk) flag_marked(gs, g, flagged);
+    for (int32_t i = vb + threadIdx.x; i < ve; i += kBlock) {
+      const int32_t x = col[i];
+      bool mk = false;
+      if (pr_owner(v, lv, x, rp[x + 1] - rp[x]) && lam >= 0) {
+        const long long c = w[i];
+        mk = pr_cheap(c, dv, (long long)degu[x], lam);
+        if (!mk) heavy[atomicAdd(&st->huge_items, 1)] = i;  // decided by k_pr_heavy
+      }
+      mark[i] = mk ? 1 : 0;
+      if (mk) {
+        any = true;
+        if (gv) flag_marked(gs, g, flagged);
+      }
     }
     if (any) s_any = 1;
     __syncthreads();
@@ -1574,7 +1677,8 @@ __global__ void k_pr_long(const int32_t *__restrict__ rp, const int32_t *__restr
   }
 }
 
-// queued arcs: one wave each, lanes over the shorter row
+// queued arcs (v, x) of rows longer than kPrLds: one wave each; the lanes
+// take 64 entries of x's row at a time and binary-search v's row
 __global__ void k_pr_heavy(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                            const int32_t *__restrict__ w, const unsigned long long *__restrict__ degu, int32_t n,
                            const int32_t *heavy, uint8_t *__restrict__ mark, Status *st,
@@ -1595,28 +1699,30 @@ __global__ void k_pr_heavy(const int32_t *__restrict__ rp, const int32_t *__rest
     const long long c = w[i];
     const long long dv = (long long)degu[v], dx = (long long)degu[x];
     const int32_t vb = rp[v], ve = rp[v + 1], xb = rp[x], xe = rp[x + 1];
-    const bool v_short = (ve - vb) <= (xe - xb);
-    const int32_t sb = v_short ? vb : xb, se = v_short ? ve : xe;
-    const int32_t lb = v_short ? xb : vb, le = v_short ? xe : ve;
-    unsigned long long sum4 = 0;
+    long long sum4 = c;
     int pr3 = 0;
-    for (int32_t j = sb + lane; j < se; j += 64) {
-      const int32_t u = col[j];
-      int32_t a = lb, b = le;
-      while (a < b) {
-        int32_t mid = (a + b) >> 1;
-        if (col[mid] < u) a = mid + 1; else b = mid;
+    for (int32_t j0 = xb; j0 < xe; j0 += 64) {
+      const int32_t j = j0 + lane;
+      unsigned long long part = 0;
+      int p3 = 0;
+      if (j < xe) {
+        const int32_t u = col[j];
+        int32_t a = vb, b = ve;
+        while (a < b) {
+          int32_t mid = (a + b) >> 1;
+          if (col[mid] < u) a = mid + 1; else b = mid;
+        }
+        if (a < ve && col[a] == u) {
+          const long long cvu = w[a], cxu = w[j];
+          if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) p3 = 1;
+          part = (unsigned long long)(cvu < cxu ? cvu : cxu);
+        }
       }
-      if (a < le && col[a] == u) {
-        const long long cvu = v_short ? w[j] : w[a];
-        const long long cxu = v_short ? w[a] : w[j];
-        if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) pr3 = 1;
-        sum4 += (unsigned long long)(cvu < cxu ? cvu : cxu);
-      }
+      sum4 += (long long)grp_sum<64>(part);
+      pr3 |= grp_or<64>(p3);
+      if (pr3 || sum4 >= lam) break;
     }
-    sum4 = grp_sum<64>(sum4);
-    pr3 = grp_or<64>(pr3);
-    const bool m = pr3 || (c + (long long)sum4 >= lam);
+    const bool m = pr3 || sum4 >= lam;
     if (lane == 0) {
       mark[i] = m ? 1 : 0;
       if (m && st->nmarked == 0) atomicExch(&st->nmarked, 1);
@@ -2092,7 +2198,7 @@ hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
 
 hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s) {
   w.ntiles = (int32_t)((g.nnz + g.n + kTile - 1) / kTile);
-  k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta);
+  k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta, w.st);
   k_long_rows<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, w.n_in, w.bins, w.st);
   return hipGetLastError();
 }
@@ -2129,21 +2235,24 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
   const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
-  if (bv) {
-    if (level0)
-      k_first_tile<true, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt,
-                                                     w.st, w.part, gv, gs);
-    else
-      k_first_tile<false, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                      salt, w.st, w.part, gv, gs);
-  } else if (level0) {
-    k_first_tile<true, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg, salt,
-                                                    w.st, w.part, nullptr, nullptr);
-    k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
-  } else {
-    k_first_tile<false, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                     salt, w.st, w.part, nullptr, nullptr);
+  {
+    ProfScope ps(level0 ? PROF_FIRST_TILE_L0 : PROF_FIRST_TILE, s, w.st, w.ntiles);
+    if (bv) {
+      if (level0)
+        k_first_tile<true, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
+                                                       salt, w.st, w.part, gv, gs);
+      else
+        k_first_tile<false, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
+                                                        salt, w.st, w.part, gv, gs);
+    } else if (level0) {
+      k_first_tile<true, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
+                                                      salt, w.st, w.part, nullptr, nullptr);
+    } else {
+      k_first_tile<false, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
+                                                       salt, w.st, w.part, nullptr, nullptr);
+    }
   }
+  if (!bv && level0) k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
   // long rows: a wave per row up to 4096 arcs, chunked beyond
   for (int b = 4; b <= 5; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
@@ -2172,12 +2281,16 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
                    hipStream_t s, const BatchView *bv) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
-  if (bv)
-    k_lp_tile<true><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta,
-                                                                       w.ntiles, salt, w.st, gv, gs);
-  else
-    k_lp_tile<false><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta,
-                                                                        w.ntiles, salt, w.st, nullptr, nullptr);
+  {
+    ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
+    if (bv)
+      k_lp_tile<true><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout,
+                                                                         w.tile_meta, w.ntiles, salt, w.st, gv, gs);
+    else
+      k_lp_tile<false><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout,
+                                                                          w.tile_meta, w.ntiles, salt, w.st, nullptr,
+                                                                          nullptr);
+  }
   launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);
   if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
@@ -2308,23 +2421,36 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   GStat *gs = bv ? bv->gs : nullptr;
   hipError_t e = fill_i32(&w.st->nmarked, 0, 1, s);
   if (e == hipSuccess) e = fill_i32(&w.st->huge_items, 0, 1, s);
+  if (e == hipSuccess) e = fill_i32(w.st->pr_rows, 0, 2, s);
   if (e != hipSuccess) return e;
   const unsigned long long *degu = (const unsigned long long *)w.deg;
   int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
+  int32_t *list = w.parent;               // free until the union-find
+  const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
   if (bv)
-    k_pr_tile<true><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta,
-                                                                       w.ntiles, w.mark, heavy, w.st, gv, gs);
+    k_pr_tile<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv, gs);
   else
-    k_pr_tile<false><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta,
-                                                                        w.ntiles, w.mark, heavy, w.st, nullptr,
-                                                                        nullptr);
-  for (int b = 4; b <= 6; b++) {
-    const int64_t items = known ? known[b] : g.nnz / kTile + 1;
-    if (items <= 0) continue;
-    k_pr_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.bins + (int64_t)b * w.n_in,
-                                                          &w.st->bin_cnt[b], w.mark, heavy, w.st, gv, gs);
+    k_pr_tile<false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, nullptr,
+                                           nullptr);
+  k_pr_list<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, list, w.st);
+  const unsigned rg = grid_for(g.nnz / kPrRow + 1, 1, 4096);
+  if (bv) {
+    k_pr_rows<2 * kPrSmallMax, true><<<rg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, list, 0, g.n, w.mark, w.st,
+                                                            gv, gs);
+    k_pr_rows<2 * kPrLds, true><<<grid_for(g.nnz / kPrSmallMax + 1, 1, 1024), kBlock, 0, s>>>(
+        g.row_ptr, g.col, g.w, degu, list, 1, g.n, w.mark, w.st, gv, gs);
+  } else {
+    k_pr_rows<2 * kPrSmallMax, false><<<rg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, list, 0, g.n, w.mark,
+                                                             w.st, nullptr, nullptr);
+    k_pr_rows<2 * kPrLds, false><<<grid_for(g.nnz / kPrSmallMax + 1, 1, 1024), kBlock, 0, s>>>(
+        g.row_ptr, g.col, g.w, degu, list, 1, g.n, w.mark, w.st, nullptr, nullptr);
   }
-  k_pr_heavy<<<1024, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, g.n, heavy, w.mark, w.st, gv, gs);
+  const int64_t items6 = known ? known[6] : g.nnz / kHugeChunk + 1;
+  if (items6 > 0) {
+    k_pr_long<<<grid_for(items6, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.bins + 6ll * w.n_in,
+                                                          &w.st->bin_cnt[6], w.mark, heavy, w.st, gv, gs);
+    k_pr_heavy<<<1024, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, g.n, heavy, w.mark, w.st, gv, gs);
+  }
   return hipGetLastError();
 }
 

@@ -45,10 +45,29 @@ __device__ __forceinline__ uint32_t fmix32_inv_dev(uint32_t h) {
 __device__ __forceinline__ unsigned long long cand_key(uint32_t S, int32_t x, uint32_t salt) {
   return ((unsigned long long)S << 32) | (unsigned long long)(~fmix32_dev((uint32_t)x ^ salt));
 }
+// Candidate key with the own-label flag between the sum and the prio:
+// (S, own, -prio(x)); S < 2^31.
+__device__ __forceinline__ unsigned long long own_key(uint32_t S, bool own, int32_t x, uint32_t salt) {
+  return ((unsigned long long)S << 33) | ((unsigned long long)own << 32) |
+         (unsigned long long)(~fmix32_dev((uint32_t)x ^ salt));
+}
 __device__ __forceinline__ int32_t key_label(unsigned long long key, uint32_t salt) {
   return (int32_t)(fmix32_inv_dev(~(uint32_t)(key & 0xFFFFFFFFull)) ^ salt);
 }
 __device__ __forceinline__ uint32_t slot_hash(int32_t x) { return (uint32_t)x * 2654435761u; }
+// Slot in [0, size) for size < 2^9, from 24-bit multiplies only (full rate):
+// a 16-bit hash scaled by size. Every product stays below 2^31 (hipcc turns a
+// logical right shift of a 24-bit product into an arithmetic one).
+__device__ __forceinline__ uint32_t region_slot(int32_t x, uint32_t size) {
+  const uint32_t h = (__umul24((uint32_t)x ^ ((uint32_t)x >> 16), 0x9E3779u) >> 8) & 0xFFFFu;
+  return __umul24(h, size) >> 16;
+}
+// Element i of an array addressed with a 32-bit byte offset from its base,
+// so that the base stays in scalar registers; needs i * sizeof(T) < 2^32.
+template <class T>
+__device__ __forceinline__ const T &at32(const T *base, uint32_t i) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + i * (uint32_t)sizeof(T));
+}
 
 __device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
   return a > b ? a : b;
@@ -525,134 +544,287 @@ __global__ void k_reduce_parts(const unsigned long long *part, int32_t count, St
   }
 }
 
-// Iteration t >= 2 on a tile. Row j of the tile owns the hash region
-// [2*s_rp[j], 2*s_rp[j+1]) of the tile's LDS table (twice its arc count, so
-// probing always ends), keyed by neighbour label and summing weights. A
-// thread inserts its q arcs and then scans the 2q table slots of the same
-// rows, so the row of every slot is known without a search.
+// Iteration t >= 2 on a tile. Thread l takes the q = ceil(arcs / 64)
+// consecutive arcs [l*q, l*q + q) of the tile (q <= 8, and q <= 4 on tiles
+// of short rows, which get their own instantiation), so the arcs of a row
+// sit in one thread or a few. Loads use clamped indices instead of branches,
+// so all arc loads, and then all label gathers, are in flight together. The
+// row of each arc comes from a prefix maximum over row-start marks (s_row).
+// Row j owns the hash region [2*s_rp[j], 2*s_rp[j+1]) of the tile's LDS
+// table (twice its arc count, so probing always ends), keyed by neighbour
+// label and summing weights. Runs of equal (row, label) within a thread are
+// folded first; the claims of a thread are all issued before any result is
+// used. Each run then adds its weight with a returning atomic, and the
+// candidate keys (sum, -prio) of a thread's runs are folded per row piece
+// into one maximum update per piece, so no pass over the table is needed.
+// Lanes without work aim their LDS operations at per-lane sink entries.
+__device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8) {
+  static_assert(kTileArcs / 8 == kTB, "one 8-byte word of marks per lane");
+  const int lane = threadIdx.x;
+  const unsigned long long v = s_row8[lane];
+  uint32_t b[8], run = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    run = max(run, (uint32_t)(v >> (8 * k)) & 0xFFu);
+    b[k] = run;
+  }
+  uint32_t incl = run;
+#pragma unroll
+  for (int off = 1; off < kTB; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, kTB);
+    if (lane >= off) incl = max(incl, y);
+  }
+  uint32_t carry = __shfl_up(incl, 1, kTB);
+  if (lane == 0) carry = 0;
+  unsigned long long out = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) out |= (unsigned long long)max(b[k], carry) << (8 * k);
+  s_row8[lane] = out;
+}
+
+struct LpTileShared {
+  int32_t rp[kTile + 1];
+  int32_t own[kTile];
+  unsigned long long best[kTile + kTB];  // + a sink per lane
+  int32_t tkey[2 * kTileArcs + kTB];     // + a sink per lane
+  uint32_t tval[2 * kTileArcs + kTB];
+  unsigned long long row8[kTileArcs / 8];
+};
+
+// Registers of one tile, fetched ahead of its processing: per thread NQ arcs
+// (neighbour, then its label, and weight) and the tile's row data, one entry
+// per 64 rows.
+constexpr int kRowRegs = kTile / kTB;
+template <bool B, int NQ>
+struct LpFetch {
+  int4 m;
+  int32_t xs[NQ], cs[NQ];
+  int32_t rpv[kRowRegs + 1];
+  int32_t ownv[kRowRegs];
+  int32_t basev[B ? kRowRegs : 1];
+  uint32_t saltv[B ? kRowRegs : 1];
+};
+
+template <bool B, int NQ>
+__device__ __forceinline__ void lp_fetch_loads(LpFetch<B, NQ> &f, int4 m, const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ col, const int32_t *__restrict__ w,
+                                               const int32_t *__restrict__ Lin, const int32_t *__restrict__ gv,
+                                               const GStat *gs) {
+  const int lane = threadIdx.x;
+  f.m = m;
+  const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+  const int32_t q = (acnt + kTB - 1) / kTB;
+  const int32_t i0 = (int32_t)__umul24((uint32_t)lane, (uint32_t)q);
+  const int32_t iend = min(i0 + q, acnt);
+  const int32_t ilast = iend > i0 ? iend - 1 : acnt - 1;  // threads past the end repeat the tile's last arc
+#pragma unroll
+  for (int k = 0; k < NQ; k++) f.xs[k] = f.cs[k] = 0;
+  if (acnt > 0) {
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const uint32_t i = (uint32_t)min(i0 + k, ilast);
+      f.xs[k] = at32(col + a0, i);
+      f.cs[k] = at32(w + a0, i);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r <= kRowRegs; r++) f.rpv[r] = at32(rp + r0, (uint32_t)min(lane + kTB * r, rows));
+  if (rows > 0) {
+#pragma unroll
+    for (int r = 0; r < kRowRegs; r++) {
+      const uint32_t j = (uint32_t)min(lane + kTB * r, rows - 1);
+      f.ownv[r] = at32(Lin + r0, j);
+      if constexpr (B) {
+        const GStat &g = gs[at32(gv + r0, j)];
+        f.basev[r] = g.base;
+        f.saltv[r] = g.salt;
+      }
+    }
+  }
+}
+template <bool B, int NQ>
+__device__ __forceinline__ void lp_fetch_gather(LpFetch<B, NQ> &f, const int32_t *__restrict__ Lin) {
+  if (f.m.w > 0) {
+#pragma unroll
+    for (int k = 0; k < NQ; k++) f.xs[k] = at32(Lin, (uint32_t)f.xs[k]);
+  }
+}
+
+// The LDS phases of one tile whose registers were fetched; `hook` runs after
+// the table updates (the caller issues the next tile's gathers there).
+template <bool B, int NQ, class Hook>
+__device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__restrict__ Lout, uint32_t salt,
+                                            LpTileShared &sh, int32_t *s_base, uint32_t *s_salt, Hook hook) {
+  const int lane = threadIdx.x;
+  const int32_t r0 = f.m.x, rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
+  const int32_t q = (acnt + kTB - 1) / kTB;
+  const int32_t i0 = (int32_t)__umul24((uint32_t)lane, (uint32_t)q);
+  const int32_t iend = min(i0 + q, acnt);
+  const int32_t ilast = iend > i0 ? iend - 1 : acnt - 1;
+  const uint8_t *s_row = reinterpret_cast<const uint8_t *>(sh.row8);
+#pragma unroll
+  for (int r = 0; r <= kRowRegs; r++)
+    if (lane + kTB * r <= rows) sh.rp[lane + kTB * r] = f.rpv[r] - a0;
+#pragma unroll
+  for (int r = 0; r < kRowRegs; r++) {
+    const int j = lane + kTB * r;
+    if (j < rows) {
+      sh.own[j] = f.ownv[r];
+      sh.best[j] = 0;
+      if constexpr (B) {
+        s_base[j] = f.basev[r];
+        s_salt[j] = f.saltv[r];
+      }
+    }
+  }
+  for (int e = lane; e < 2 * acnt; e += kTB) {
+    sh.tkey[e] = -1;
+    sh.tval[e] = 0;
+  }
+  sh.row8[lane] = 0;
+  __syncthreads();
+  for (int j = lane; j < rows; j += kTB)
+    if (sh.rp[j + 1] > sh.rp[j]) reinterpret_cast<uint8_t *>(sh.row8)[sh.rp[j]] = (uint8_t)j;
+  __syncthreads();
+  tile_rows_prefix_max(sh.row8);
+  __syncthreads();
+  if (acnt > 0) {
+    int32_t rw[NQ], ow[NQ], bj[NQ], hb[NQ], hsz[NQ], old[NQ];
+    uint32_t sj[NQ], hh[NQ], cc[NQ];
+    bool real[NQ], ok[NQ];
+    // every LDS read first, so that they are in flight together
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      real[k] = i0 + k < iend;
+      rw[k] = s_row[min(i0 + k, ilast)];
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const int32_t lo = sh.rp[rw[k]], hi = sh.rp[rw[k] + 1];
+      hb[k] = 2 * lo;
+      hsz[k] = 2 * (hi - lo);
+      ow[k] = sh.own[rw[k]];
+      bj[k] = 0;
+      sj[k] = salt;
+      if constexpr (B) { bj[k] = s_base[rw[k]]; sj[k] = s_salt[rw[k]]; }
+    }
+    // fold the thread's arcs of equal (row, label) into the first of them
+    // (register work instead of LDS atomics, which bound this kernel)
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      ok[k] = real[k];
+      cc[k] = (uint32_t)f.cs[k];
+    }
+#pragma unroll
+    for (int k = 1; k < NQ; k++) {
+#pragma unroll
+      for (int k1 = 0; k1 < k; k1++)
+        if (ok[k] && ok[k1] && rw[k] == rw[k1] && f.xs[k] == f.xs[k1]) {
+          cc[k1] += cc[k];
+          ok[k] = false;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      hh[k] = region_slot(f.xs[k], (uint32_t)hsz[k]);
+      old[k] = atomicCAS(&sh.tkey[ok[k] ? hb[k] + (int32_t)hh[k] : 2 * kTileArcs + lane], -1, f.xs[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      if (!ok[k]) continue;
+      while (old[k] != -1 && old[k] != f.xs[k]) {  // taken by another label
+        hh[k] = (hh[k] + 1 == (uint32_t)hsz[k]) ? 0 : hh[k] + 1;
+        old[k] = atomicCAS(&sh.tkey[hb[k] + hh[k]], -1, f.xs[k]);
+      }
+    }
+    // add the run weights: the returned partial sum plus the run's weight is
+    // a lower bound of the label's final sum, and the last update of a label
+    // sees the final sum, so the maximum of (partial sum, -prio) over all
+    // updates of a row is the maximum over its labels' final sums
+    // The key (S, own, -prio) orders by sum, then the own label first, then
+    // the smaller prio, so the row maximum decides the update rule at once.
+    unsigned long long key[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; k++)
+      old[k] = (int32_t)atomicAdd(&sh.tval[ok[k] ? hb[k] + (int32_t)hh[k] : 2 * kTileArcs + lane], cc[k]);
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const uint32_t S = (uint32_t)old[k] + cc[k];
+      key[k] = ok[k] ? own_key(S, f.xs[k] == ow[k], f.xs[k] - bj[k], sj[k]) : 0ull;
+    }
+    // fold per row piece of this thread, one update per piece
+    bool head[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; k++) head[k] = real[k];
+#pragma unroll
+    for (int k = NQ - 1; k > 0; k--)
+      if (real[k] && real[k - 1] && rw[k] == rw[k - 1]) {
+        key[k - 1] = umax64(key[k - 1], key[k]);
+        head[k] = false;
+      }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) atomicMax(&sh.best[head[k] ? rw[k] : kTile + lane], key[k]);
+  }
+  hook();
+  __syncthreads();
+  for (int j = lane; j < rows; j += kTB) {
+    const int32_t own = sh.own[j];
+    if (sh.rp[j + 1] == sh.rp[j]) { Lout[r0 + j] = own; continue; }
+    const unsigned long long b = sh.best[j];
+    int32_t bjj = 0;
+    uint32_t sjj = salt;
+    if constexpr (B) { bjj = s_base[j]; sjj = s_salt[j]; }
+    Lout[r0 + j] = ((b >> 32) & 1) ? own : key_label(b, sjj) + bjj;
+  }
+  __syncthreads();
+}
+
+// Persistent: workgroup b takes tiles b, b + G, b + 2G, ... (G = grid size).
+// The next tile's arcs and row data are loaded before this tile's LDS phases
+// and its label gathers are issued after this tile's table updates, so the
+// memory latency of one tile overlaps the LDS work of the previous one.
+// Tiles of more than 4*64 arcs (a long row closing the tile) run unpipelined
+// with 8 arcs per thread.
 template <bool B>
 __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
                                                      int32_t *__restrict__ Lout, const int4 *__restrict__ meta,
                                                      int32_t ntiles, uint32_t salt, const Status *st,
                                                      const int32_t *__restrict__ gv, const GStat *gs) {
-  __shared__ int32_t s_rp[kTile + 1];
-  __shared__ int32_t s_own[kTile];
-  __shared__ uint32_t s_ownS[kTile];
-  __shared__ unsigned long long s_best[kTile];
-  __shared__ int32_t tkey[2 * kTileArcs];
-  __shared__ uint32_t tval[2 * kTileArcs];
+  __shared__ LpTileShared sh;
   __shared__ int32_t s_base[B ? kTile : 1];
   __shared__ uint32_t s_salt[B ? kTile : 1];
   if (!B && st->err) return;
-  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int4 m = meta[t];
-    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-    const int32_t q = (acnt + kTB - 1) / kTB;
-    const int32_t i0 = threadIdx.x * q;
-    int32_t xs[kPerThread], cs[kPerThread];
-#pragma unroll
-    for (int k = 0; k < kPerThread; k++) {
-      const bool ok = k < q && i0 + k < acnt;
-      xs[k] = ok ? col[a0 + i0 + k] : 0;
-      cs[k] = ok ? w[a0 + i0 + k] : 0;
+  int32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  constexpr int32_t kSmall = 4 * kTB;
+  int4 m = meta[t];
+  LpFetch<B, 4> cur;
+  if (m.w <= kSmall) {
+    lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
+    lp_fetch_gather(cur, Lin);
+  }
+  while (true) {
+    const int32_t tn = t + (int32_t)gridDim.x;
+    const int4 mn = tn < ntiles ? meta[tn] : make_int4(0, 0, 0, 0);
+    const bool nsmall = tn < ntiles && mn.w <= kSmall;
+    LpFetch<B, 4> nxt;
+    if (nsmall) lp_fetch_loads(nxt, mn, rp, col, w, Lin, gv, gs);
+    auto hook = [&]() {
+      if (nsmall) lp_fetch_gather(nxt, Lin);
+    };
+    if (m.w <= kSmall) {
+      lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, hook);
+    } else {
+      LpFetch<B, kPerThread> big;
+      lp_fetch_loads(big, m, rp, col, w, Lin, gv, gs);
+      lp_fetch_gather(big, Lin);
+      lp_tile_run<B, kPerThread>(big, Lout, salt, sh, s_base, s_salt, hook);
     }
-    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
-    for (int j = threadIdx.x; j < rows; j += kTB) {
-      s_own[j] = Lin[r0 + j];
-      s_ownS[j] = 0;
-      s_best[j] = 0;
-      if constexpr (B) {
-        const GStat &g = gs[gv[r0 + j]];
-        s_base[j] = g.base;
-        s_salt[j] = g.salt;
-      }
-    }
-    for (int e = threadIdx.x; e < 2 * acnt; e += kTB) {
-      tkey[e] = -1;
-      tval[e] = 0;
-    }
-#pragma unroll
-    for (int k = 0; k < kPerThread; k++)
-      if (k < q && i0 + k < acnt) xs[k] = Lin[xs[k]];
-    __syncthreads();
-    const int32_t iend = min(i0 + q, acnt);
-    const int32_t j0 = i0 < acnt ? row_of(s_rp, rows, i0) : 0;
-    if (i0 < acnt) {
-      int32_t j = j0;
-      int32_t px = -1;
-      uint32_t pc = 0;
-      auto insert = [&](int32_t row, int32_t x, uint32_t c) {
-        const int32_t base = 2 * s_rp[row];
-        const uint32_t size = 2u * (uint32_t)(s_rp[row + 1] - s_rp[row]);
-        uint32_t h = (uint32_t)(((unsigned long long)slot_hash(x) * size) >> 32);
-        while (true) {
-          const int32_t k = tkey[base + h];
-          if (k == x) break;
-          if (k == -1) {
-            const int32_t old = atomicCAS(&tkey[base + h], -1, x);
-            if (old == -1 || old == x) break;
-          }
-          h = (h + 1 == size) ? 0 : h + 1;
-        }
-        atomicAdd(&tval[base + h], c);
-      };
-#pragma unroll
-      for (int k = 0; k < kPerThread; k++) {
-        const int32_t i = i0 + k;
-        if (k < q && i < acnt) {
-          if (i >= s_rp[j + 1]) {
-            if (px >= 0) insert(j, px, pc);
-            px = -1;
-            do { j++; } while (i >= s_rp[j + 1]);
-          }
-          const int32_t x = xs[k];
-          const uint32_t c = (uint32_t)cs[k];
-          if (x == px) {
-            pc += c;  // consecutive arcs with the same label: one insertion
-          } else {
-            if (px >= 0) insert(j, px, pc);
-            px = x;
-            pc = c;
-          }
-        }
-      }
-      if (px >= 0) insert(j, px, pc);
-    }
-    __syncthreads();
-    if (i0 < acnt) {
-      int32_t j = j0;
-      int32_t bj = 0;
-      uint32_t sj = salt;
-      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
-      unsigned long long best = 0;
-      for (int32_t e = 2 * i0; e < 2 * iend; e++) {
-        if (e >= 2 * s_rp[j + 1]) {
-          atomicMax(&s_best[j], best);
-          best = 0;
-          do { j++; } while (e >= 2 * s_rp[j + 1]);
-          if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
-        }
-        const int32_t k = tkey[e];
-        if (k >= 0) {
-          const uint32_t S = tval[e];
-          best = umax64(best, cand_key(S, k - bj, sj));
-          if (k == s_own[j]) s_ownS[j] = S;
-        }
-      }
-      atomicMax(&s_best[j], best);
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < rows; j += kTB) {
-      const int32_t own = s_own[j];
-      if (s_rp[j + 1] == s_rp[j]) { Lout[r0 + j] = own; continue; }
-      const unsigned long long b = s_best[j];
-      int32_t bj = 0;
-      uint32_t sj = salt;
-      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
-      Lout[r0 + j] = ((uint32_t)(b >> 32) == s_ownS[j]) ? own : key_label(b, sj) + bj;
-    }
-    __syncthreads();
+    if (tn >= ntiles) break;
+    t = tn;
+    m = mn;
+    cur = nxt;
   }
 }
 
@@ -1053,103 +1225,141 @@ __device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus
   (void)xs;
 }
 
-// Tile emission with a combiner: the tile's inter-cluster arcs are first
-// summed per (cl(u), cl(v)) pair in an LDS hash table, and only the distinct
-// pairs are written (the sort and the final segmented sum are insensitive to
-// how a pair's weight is split).
+// Tile emission with a combiner: the tile's inter-cluster arcs are summed per
+// (cl(u), cl(v)) pair in an LDS hash table, and only the distinct pairs are
+// written (the sort and the final segmented sum do not depend on how a
+// pair's weight is split). Thread l takes q consecutive arcs as in the LP
+// tile kernel: clamped loads, so loads and cluster gathers are in flight
+// together; rows from the prefix maximum of row-start marks; runs of equal
+// pairs folded in registers; all claims issued before any result is used.
+// The occupied slots are then written in slot order, 64 at a time.
 constexpr int kCombSlots = kTileArcs;  // > arcs of a tile, so probing ends
+constexpr unsigned long long kNoPair = ~0ull;
+struct EmitTileShared {
+  int32_t rp[kTile + 1];
+  int32_t cl[kTile];
+  unsigned long long tkey[kCombSlots + kTB];  // + a sink per lane
+  uint32_t tval[kCombSlots + kTB];
+  unsigned long long row8[kTileArcs / 8];
+};
+
+template <int NQ>
+__device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                              const int32_t *__restrict__ w, const int32_t *__restrict__ cl, int4 m,
+                                              int32_t t, int key_bits, unsigned long long *__restrict__ keys,
+                                              int32_t *__restrict__ vals, int32_t *__restrict__ seg,
+                                              EmitTileShared &sh) {
+  const int lane = threadIdx.x;
+  const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+  const int32_t q = (acnt + kTB - 1) / kTB;
+  const int32_t i0 = lane * q;
+  const int32_t iend = min(i0 + q, acnt);
+  const int32_t ilast = iend > i0 ? iend - 1 : acnt - 1;
+  const uint8_t *s_row = reinterpret_cast<const uint8_t *>(sh.row8);
+  int32_t cus[NQ], cs[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; k++) cus[k] = cs[k] = 0;
+  if (acnt > 0) {
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const int32_t i = a0 + min(i0 + k, ilast);
+      cus[k] = col[i];
+      cs[k] = w[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) cus[k] = cl[cus[k]];
+  }
+  for (int j = lane; j <= rows; j += kTB) sh.rp[j] = rp[r0 + j] - a0;
+  for (int j = lane; j < rows; j += kTB) sh.cl[j] = cl[r0 + j];
+  for (int e = lane; e < kCombSlots; e += kTB) {
+    sh.tkey[e] = kNoPair;
+    sh.tval[e] = 0;
+  }
+  sh.row8[lane] = 0;
+  __syncthreads();
+  for (int j = lane; j < rows; j += kTB)
+    if (sh.rp[j + 1] > sh.rp[j]) reinterpret_cast<uint8_t *>(sh.row8)[sh.rp[j]] = (uint8_t)j;
+  __syncthreads();
+  tile_rows_prefix_max(sh.row8);
+  __syncthreads();
+  if (acnt > 0) {
+    int32_t cv[NQ];
+    bool ok[NQ];
+    uint32_t cc[NQ], hh[NQ];
+    unsigned long long key[NQ], old[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; k++) cv[k] = s_row[min(i0 + k, ilast)];
+#pragma unroll
+    for (int k = 0; k < NQ; k++) cv[k] = sh.cl[cv[k]];
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      ok[k] = i0 + k < iend && cus[k] != cv[k];
+      key[k] = ((unsigned long long)(uint32_t)cv[k] << key_bits) | (uint32_t)cus[k];
+      cc[k] = (uint32_t)cs[k];
+    }
+    // fold runs of equal pairs into their first arc
+#pragma unroll
+    for (int k = NQ - 1; k > 0; k--)
+      if (ok[k] && ok[k - 1] && key[k] == key[k - 1]) {
+        cc[k - 1] += cc[k];
+        ok[k] = false;
+      }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const uint32_t fold = (uint32_t)key[k] ^ (uint32_t)(key[k] >> 32);
+      hh[k] = (fold * 2654435761u) & (kCombSlots - 1);
+      old[k] = atomicCAS(&sh.tkey[ok[k] ? (int32_t)hh[k] : kCombSlots + lane], kNoPair, key[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      if (!ok[k]) continue;
+      while (old[k] != kNoPair && old[k] != key[k]) {  // taken by another pair
+        hh[k] = (hh[k] + 1) & (kCombSlots - 1);
+        old[k] = atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) atomicAdd(&sh.tval[ok[k] ? (int32_t)hh[k] : kCombSlots + lane], cc[k]);
+  }
+  __syncthreads();
+  // write the distinct pairs into the tile's region, in slot order
+  int32_t tot = 0;
+  if (acnt > 0) {
+#pragma unroll
+    for (int k = 0; k < kCombSlots / kTB; k++) {
+      const int e = k * kTB + lane;
+      const unsigned long long kk = sh.tkey[e];
+      const uint32_t vv = sh.tval[e];
+      const bool occ = kk != kNoPair;
+      const unsigned long long bal = __ballot(occ);
+      if (occ) {
+        const int32_t pos = tot + __popcll(bal & ((1ull << lane) - 1));
+        keys[(int64_t)a0 + pos] = kk;
+        vals[(int64_t)a0 + pos] = (int32_t)vv;
+      }
+      tot += __popcll(bal);
+    }
+  }
+  if (lane == 0) {
+    seg[2 * (int64_t)t] = a0;
+    seg[2 * (int64_t)t + 1] = tot;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
                                                        const int4 *__restrict__ meta, int32_t ntiles,
                                                        const Status *st, unsigned long long *__restrict__ keys,
                                                        int32_t *__restrict__ vals, int32_t *__restrict__ seg) {
-  __shared__ int32_t s_rp[kTile + 1];
-  __shared__ int32_t s_cl[kTile];
-  __shared__ unsigned long long tkey[kCombSlots];
-  __shared__ uint32_t tval[kCombSlots];
+  __shared__ EmitTileShared sh;
   const int key_bits = bits_for(st->k);
   for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
-    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-    const int32_t q = (acnt + kTB - 1) / kTB;
-    const int32_t i0 = threadIdx.x * q;
-    int32_t xs[kPerThread], cs[kPerThread];
-#pragma unroll
-    for (int k = 0; k < kPerThread; k++) {
-      const bool ok = k < q && i0 + k < acnt;
-      xs[k] = ok ? col[a0 + i0 + k] : 0;
-      cs[k] = ok ? w[a0 + i0 + k] : 0;
-    }
-    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
-    for (int j = threadIdx.x; j < rows; j += kTB) s_cl[j] = cl[r0 + j];
-    for (int e = threadIdx.x; e < kCombSlots; e += kTB) {
-      tkey[e] = ~0ull;
-      tval[e] = 0;
-    }
-#pragma unroll
-    for (int k = 0; k < kPerThread; k++)
-      if (k < q && i0 + k < acnt) xs[k] = cl[xs[k]];
-    __syncthreads();
-    if (i0 < acnt) {
-      int32_t j = row_of(s_rp, rows, i0);
-      unsigned long long pk = ~0ull;
-      uint32_t pc = 0;
-      auto insert = [&](unsigned long long key, uint32_t c) {
-        const uint32_t fold = (uint32_t)key ^ (uint32_t)(key >> 32);
-        uint32_t h = (fold * 2654435761u) & (kCombSlots - 1);
-        while (true) {
-          const unsigned long long k = tkey[h];
-          if (k == key) break;
-          if (k == ~0ull) {
-            const unsigned long long old = atomicCAS(&tkey[h], ~0ull, key);
-            if (old == ~0ull || old == key) break;
-          }
-          h = (h + 1) & (kCombSlots - 1);
-        }
-        atomicAdd(&tval[h], c);
-      };
-#pragma unroll
-      for (int k = 0; k < kPerThread; k++) {
-        const int32_t i = i0 + k;
-        if (k < q && i < acnt) {
-          while (i >= s_rp[j + 1]) j++;
-          const int32_t cv = s_cl[j], cu = xs[k];
-          if (cu != cv) {
-            const unsigned long long key = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cu;
-            if (key == pk) {
-              pc += (uint32_t)cs[k];
-            } else {
-              if (pk != ~0ull) insert(pk, pc);
-              pk = key;
-              pc = (uint32_t)cs[k];
-            }
-          }
-        }
-      }
-      if (pk != ~0ull) insert(pk, pc);
-    }
-    __syncthreads();
-    // compact the distinct pairs into the tile's region
-    constexpr int kSlotsPerThread = kCombSlots / kTB;
-    uint32_t fl = 0;
-#pragma unroll
-    for (int k = 0; k < kSlotsPerThread; k++)
-      if (tkey[threadIdx.x * kSlotsPerThread + k] != ~0ull) fl |= 1u << k;
-    const int32_t cnt = __popc(fl);
-    const int32_t inc = wave_incl_scan(cnt);
-    const int32_t off = inc - cnt, tot = __shfl(inc, 63, 64);
-#pragma unroll
-    for (int k = 0; k < kSlotsPerThread; k++)
-      if (fl & (1u << k)) {
-        const int64_t o = (int64_t)a0 + off + __popc(fl & ((1u << k) - 1));
-        keys[o] = tkey[threadIdx.x * kSlotsPerThread + k];
-        vals[o] = (int32_t)tval[threadIdx.x * kSlotsPerThread + k];
-      }
-    if (threadIdx.x == 0) {
-      seg[2 * (int64_t)t] = a0;
-      seg[2 * (int64_t)t + 1] = tot;
-    }
-    __syncthreads();
+    if (m.w <= 4 * kTB)
+      emit_tile_one<4>(rp, col, w, cl, m, t, key_bits, keys, vals, seg, sh);
+    else
+      emit_tile_one<kPerThread>(rp, col, w, cl, m, t, key_bits, keys, vals, seg, sh);
   }
 }
 
@@ -2277,6 +2487,19 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   return hipGetLastError();
 }
 
+// Grid of a persistent kernel: as many workgroups as fit on the device at
+// once (at least one), capped by the work items.
+template <class K>
+unsigned resident_grid(K kernel, int block, int64_t items) {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    per_cu = cus = 1;
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)std::max(per_cu, 1) * std::max(cus, 1)));
+  return (unsigned)g;
+}
+
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
                    hipStream_t s, const BatchView *bv) {
   const int32_t *gv = bv ? bv->gv : nullptr;
@@ -2284,12 +2507,11 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
     if (bv)
-      k_lp_tile<true><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout,
-                                                                         w.tile_meta, w.ntiles, salt, w.st, gv, gs);
+      k_lp_tile<true><<<resident_grid(k_lp_tile<true>, kTB, w.ntiles), kTB, 0, s>>>(
+          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs);
     else
-      k_lp_tile<false><<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout,
-                                                                          w.tile_meta, w.ntiles, salt, w.st, nullptr,
-                                                                          nullptr);
+      k_lp_tile<false><<<resident_grid(k_lp_tile<false>, kTB, w.ntiles), kTB, 0, s>>>(
+          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr);
   }
   launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);

@@ -106,6 +106,47 @@ def traffic_for(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 256 << 20  # the --copy-probe device copy: 64 Mi int32 read and written
+
+
+def record_traffic(fetch_csv, write_csv, kernel, workload, command):
+    """Turn two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, in KiB
+    per dispatch) of `bench.py --copy-probe` into HBM bytes per launch of
+    `kernel`: each counter is scaled by known bytes / reading for the plain
+    256 MiB device copy of the same run. Writes
+    profiles/traffic_<kernel>_<workload>.json stamped with the kernel source
+    hash, which is how the roofline's "traffic" knows it is still current."""
+    import csv
+
+    def per_kernel(path, counter):
+        copy_best, vals = 0.0, []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"]) * 1024.0
+                name = r["Kernel_Name"]
+                if "copyBuffer" in name:
+                    copy_best = max(copy_best, v)
+                elif "%s(" % kernel in name or "%s<" % kernel in name:
+                    vals.append(v)
+        if not copy_best or not vals:
+            raise SystemExit("%s: no copy probe or no %s dispatch with %s" % (path, kernel, counter))
+        return sum(vals) / len(vals), COPY_PROBE_BYTES / copy_best, len(vals)
+
+    fetch, f_scale, nf = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, w_scale, nw = per_kernel(write_csv, "WRITE_SIZE")
+    rec = {"kernel": kernel, "workload": workload, "source_sha": kernel_source_hash(),
+           "bytes_per_launch": round(fetch * f_scale + write * w_scale),
+           "fetch_bytes_per_launch": round(fetch * f_scale), "write_bytes_per_launch": round(write * w_scale),
+           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4), "dispatches": [nf, nw],
+           "command": command}
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def roofline(prof, workload):
     timed = {k: v for k, v in prof.items() if v["launches"] > 0 and v["total_ms"] > 0}
     if not timed:
@@ -276,7 +317,16 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256, help="requests in the stream (drawn from the pool)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<kernel>_<workload>.json from two rocprofv3 --pmc passes "
+                         "(FETCH_SIZE, WRITE_SIZE) of this benchmark run with --copy-probe, then exit")
+    ap.add_argument("--traffic-kernel", default="k_lp_tile")
+    ap.add_argument("--traffic-command", default="", help="the profiled command, stored with the record")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic[0], args.record_traffic[1], args.traffic_kernel, args.workload,
+                       args.traffic_command)
+        return
     if args.gpus != 1:
         print("this benchmark runs on one GPU only: the graphs are solved on a single device "
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)

@@ -210,7 +210,7 @@ struct Engine {
   unsigned n_threads = 1;
   // phase times (host clock, ms) for VIECUT_LOG=1 diagnostics
   bool verbose = false;
-  double t_sync = 0, t_drain_read = 0, t_gather = 0, t_solve = 0, t_side = 0, t_admit = 0;
+  double t_sync = 0, t_drain_read = 0, t_gather = 0, t_solve = 0, t_side = 0, t_admit = 0, t_init = 0;
   int64_t n_syncs = 0, n_steps = 0, n_solved = 0;
 
   Engine(const Engine &) = delete;
@@ -508,9 +508,9 @@ struct Engine {
   void report(const char *what) const {
     if (!verbose) return;
     fprintf(stderr,
-            "[viecut] %s: steps %lld syncs %lld (%.2f ms) ring read %.2f ms, gather %.2f ms, exact solves %lld "
-            "(%.2f ms), sides %.2f ms, admission %.2f ms\n",
-            what, (long long)n_steps, (long long)n_syncs, t_sync, t_drain_read, t_gather, (long long)n_solved,
+            "[viecut] %s: init %.2f ms, steps %lld syncs %lld (%.2f ms) ring read %.2f ms, gather %.2f ms, exact "
+            "solves %lld (%.2f ms), sides %.2f ms, admission %.2f ms\n",
+            what, t_init, (long long)n_steps, (long long)n_syncs, t_sync, t_drain_read, t_gather, (long long)n_solved,
             t_solve, t_side, t_admit);
   }
 
@@ -717,7 +717,9 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
   if (c.s == 0) return VIECUT_OK;
   if (c.a >= INT32_MAX || (int64_t)c.n + c.s >= INT32_MAX) return VIECUT_EOVERFLOW;
   vc::Engine eng;
+  const double ti = vc::now_ms();
   int rc = eng.init(c, q, (hipStream_t)stream, ws, ws_bytes);
+  eng.t_init = vc::now_ms() - ti;
   if (rc) return rc;
   const double t0 = vc::now_ms();
   for (int32_t i = 0; i < count; i++)

@@ -177,6 +177,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   L.add(24 * (size_t)ntiles);                  // 30 part
   L.add(8 * (size_t)nseg);                     // 31 seg
   L.add(4 * (size_t)nseg + 4);                 // 32 seg_cnt
+  L.add(4 * (size_t)ntiles);                   // 33 big_tiles
   return L;
 }
 
@@ -229,6 +230,7 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
   w.part = (unsigned long long *)at(30);
   w.seg = (int32_t *)at(31);
   w.seg_cnt = (int32_t *)at(32);
+  w.big_tiles = (int32_t *)at(33);
   return true;
 }
 

@@ -57,7 +57,7 @@ struct Status {
   int32_t ring_cnt;            // (batched) finished graphs pushed to the ring so far
   int32_t active_cnt;          // (batched) graphs still in the round loop
   int32_t tile_rows;           // rows covered by the arc tiles of the current level
-  int32_t pad1;
+  int32_t big_tiles;           // tiles of more than 256 arcs (listed in Work::big_tiles)
   unsigned long long tile_arcs;  // arcs covered by the arc tiles of the current level
   int32_t pr_rows[2];          // rows marked with an LDS table of their row (short / long tables)
 };
@@ -173,6 +173,7 @@ struct Work {
   int64_t huge_cap = 0;          // table slots available
   uint8_t *flags8 = nullptr;     // side flags of the kernel graph (n)
   int4 *tile_meta = nullptr;     // per arc tile: first row, short rows, first arc, arcs
+  int32_t *big_tiles = nullptr;  // ids of the tiles of more than 256 arcs (any order)
   int32_t ntiles = 0;            // tiles of the current level
   unsigned long long *part = nullptr;  // per-block partial results (3 per tile)
   int32_t *seg = nullptr;        // emission segments: (first arc, count) pairs

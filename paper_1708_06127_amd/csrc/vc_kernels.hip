@@ -180,6 +180,7 @@ __global__ void k_status_reset(Status *st) {
     st->active_cnt = 0;
     st->tile_rows = 0;
     st->tile_arcs = 0;
+    st->big_tiles = 0;
   }
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
 }
@@ -207,16 +208,30 @@ __device__ __forceinline__ int32_t tile_start(const int32_t *rp, int32_t n, int6
   }
   return lo;
 }
-__global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st) {
+// Tiles of more than 4 * 64 arcs (a long row closes them) are also listed in
+// `big`, in any order, for the LP kernel that runs them with 8 arcs per thread.
+__global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st, int32_t *big) {
   __shared__ unsigned long long sh[kBlock / 64];
+  const int lane = threadIdx.x & 63;
   unsigned long long rows = 0, arcs = 0;
-  for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * kBlock) {
-    const int32_t r0 = tile_start(rp, n, t * (int64_t)kTile);
-    int32_t r1 = t + 1 == ntiles ? n : tile_start(rp, n, (t + 1) * (int64_t)kTile);
-    if (r1 > r0 && rp[r1] - rp[r1 - 1] >= kTile) r1--;
-    meta[t] = make_int4(r0, r1 - r0, rp[r0], rp[r1] - rp[r0]);
-    rows += (unsigned long long)(r1 - r0);
-    arcs += (unsigned long long)(rp[r1] - rp[r0]);
+  for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < ntiles; t0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t t = t0 + threadIdx.x;
+    bool is_big = false;
+    if (t < ntiles) {
+      const int32_t r0 = tile_start(rp, n, t * (int64_t)kTile);
+      int32_t r1 = t + 1 == ntiles ? n : tile_start(rp, n, (t + 1) * (int64_t)kTile);
+      if (r1 > r0 && rp[r1] - rp[r1 - 1] >= kTile) r1--;
+      const int32_t acnt = rp[r1] - rp[r0];
+      meta[t] = make_int4(r0, r1 - r0, rp[r0], acnt);
+      rows += (unsigned long long)(r1 - r0);
+      arcs += (unsigned long long)acnt;
+      is_big = acnt > 4 * kTB;
+    }
+    const unsigned long long bal = __ballot(is_big);
+    int32_t base = 0;
+    if (lane == 0 && bal) base = atomicAdd(&st->big_tiles, (int32_t)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (is_big) big[base + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)t;
   }
   // totals over the tiles (the algorithmic size of a tile sweep)
   rows = block_sum(rows, sh);
@@ -582,12 +597,16 @@ __device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8)
   s_row8[lane] = out;
 }
 
+// LDS of one tile whose threads take NQ arcs each: the hash table holds two
+// slots per arc of the tile, plus a sink slot per lane.
+template <int NQ>
 struct LpTileShared {
+  static constexpr int kSlots = 2 * NQ * kTB;
   int32_t rp[kTile + 1];
   int32_t own[kTile];
   unsigned long long best[kTile + kTB];  // + a sink per lane
-  int32_t tkey[2 * kTileArcs + kTB];     // + a sink per lane
-  uint32_t tval[2 * kTileArcs + kTB];
+  int32_t tkey[kSlots + kTB];
+  uint32_t tval[kSlots + kTB];
   unsigned long long row8[kTileArcs / 8];
 };
 
@@ -654,7 +673,8 @@ __device__ __forceinline__ void lp_fetch_gather(LpFetch<B, NQ> &f, const int32_t
 // the table updates (the caller issues the next tile's gathers there).
 template <bool B, int NQ, class Hook>
 __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__restrict__ Lout, uint32_t salt,
-                                            LpTileShared &sh, int32_t *s_base, uint32_t *s_salt, Hook hook) {
+                                            LpTileShared<NQ> &sh, int32_t *s_base, uint32_t *s_salt, Hook hook) {
+  constexpr int kSink = LpTileShared<NQ>::kSlots;
   const int lane = threadIdx.x;
   const int32_t r0 = f.m.x, rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
   const int32_t q = (acnt + kTB - 1) / kTB;
@@ -727,7 +747,7 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       hh[k] = region_slot(f.xs[k], (uint32_t)hsz[k]);
-      old[k] = atomicCAS(&sh.tkey[ok[k] ? hb[k] + (int32_t)hh[k] : 2 * kTileArcs + lane], -1, f.xs[k]);
+      old[k] = atomicCAS(&sh.tkey[ok[k] ? hb[k] + (int32_t)hh[k] : kSink + lane], -1, f.xs[k]);
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
@@ -746,7 +766,7 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
     unsigned long long key[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; k++)
-      old[k] = (int32_t)atomicAdd(&sh.tval[ok[k] ? hb[k] + (int32_t)hh[k] : 2 * kTileArcs + lane], cc[k]);
+      old[k] = (int32_t)atomicAdd(&sh.tval[ok[k] ? hb[k] + (int32_t)hh[k] : kSink + lane], cc[k]);
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       const uint32_t S = (uint32_t)old[k] + cc[k];
@@ -779,51 +799,85 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
   __syncthreads();
 }
 
-// Persistent: workgroup b takes tiles b, b + G, b + 2G, ... (G = grid size).
-// The next tile's arcs and row data are loaded before this tile's LDS phases
-// and its label gathers are issued after this tile's table updates, so the
-// memory latency of one tile overlaps the LDS work of the previous one.
-// Tiles of more than 4*64 arcs (a long row closing the tile) run unpipelined
-// with 8 arcs per thread.
+// Persistent: workgroup b takes the tiles b, b + G, b + 2G, ... (G = grid
+// size) of at most 4 * 64 arcs, 4 arcs per thread. The next tile's arcs and
+// row data are loaded before this tile's LDS phases and its label gathers are
+// issued after this tile's table updates, so the memory latency of one tile
+// overlaps the LDS work of the previous one. The tiles of more than 256 arcs
+// are left to k_lp_tile_big.
 template <bool B>
 __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
                                                      int32_t *__restrict__ Lout, const int4 *__restrict__ meta,
                                                      int32_t ntiles, uint32_t salt, const Status *st,
                                                      const int32_t *__restrict__ gv, const GStat *gs) {
-  __shared__ LpTileShared sh;
+  __shared__ LpTileShared<4> sh;
   __shared__ int32_t s_base[B ? kTile : 1];
   __shared__ uint32_t s_salt[B ? kTile : 1];
   if (!B && st->err) return;
-  int32_t t = blockIdx.x;
-  if (t >= ntiles) return;
   constexpr int32_t kSmall = 4 * kTB;
-  int4 m = meta[t];
-  LpFetch<B, 4> cur;
-  if (m.w <= kSmall) {
-    lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
-    lp_fetch_gather(cur, Lin);
-  }
-  while (true) {
-    const int32_t tn = t + (int32_t)gridDim.x;
-    const int4 mn = tn < ntiles ? meta[tn] : make_int4(0, 0, 0, 0);
-    const bool nsmall = tn < ntiles && mn.w <= kSmall;
-    LpFetch<B, 4> nxt;
-    if (nsmall) lp_fetch_loads(nxt, mn, rp, col, w, Lin, gv, gs);
-    auto hook = [&]() {
-      if (nsmall) lp_fetch_gather(nxt, Lin);
-    };
-    if (m.w <= kSmall) {
-      lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, hook);
-    } else {
-      LpFetch<B, kPerThread> big;
-      lp_fetch_loads(big, m, rp, col, w, Lin, gv, gs);
-      lp_fetch_gather(big, Lin);
-      lp_tile_run<B, kPerThread>(big, Lout, salt, sh, s_base, s_salt, hook);
+  const int32_t G = (int32_t)gridDim.x;
+  // this workgroup's next small tile at or after t
+  auto next_small = [&](int32_t t, int4 &m) {
+    for (; t < ntiles; t += G) {
+      m = meta[t];
+      if (m.w <= kSmall) break;
     }
-    if (tn >= ntiles) break;
+    return t;
+  };
+  int4 m;
+  int32_t t = next_small((int32_t)blockIdx.x, m);
+  if (t >= ntiles) return;
+  LpFetch<B, 4> cur;
+  lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
+  lp_fetch_gather(cur, Lin);
+  while (true) {
+    int4 mn = make_int4(0, 0, 0, 0);
+    const int32_t tn = next_small(t + G, mn);
+    const bool more = tn < ntiles;
+    LpFetch<B, 4> nxt;
+    if (more) lp_fetch_loads(nxt, mn, rp, col, w, Lin, gv, gs);
+    lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, [&]() {
+      if (more) lp_fetch_gather(nxt, Lin);
+    });
+    if (!more) break;
     t = tn;
-    m = mn;
+    cur = nxt;
+  }
+}
+
+// The listed tiles of more than 256 arcs, 8 arcs per thread, pipelined the
+// same way over the list.
+template <bool B>
+__global__ __launch_bounds__(kTB) void k_lp_tile_big(const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         const int32_t *__restrict__ w,
+                                                         const int32_t *__restrict__ Lin, int32_t *__restrict__ Lout,
+                                                         const int4 *__restrict__ meta,
+                                                         const int32_t *__restrict__ big, uint32_t salt,
+                                                         const Status *st, const int32_t *__restrict__ gv,
+                                                         const GStat *gs) {
+  __shared__ LpTileShared<kPerThread> sh;
+  __shared__ int32_t s_base[B ? kTile : 1];
+  __shared__ uint32_t s_salt[B ? kTile : 1];
+  if (!B && st->err) return;
+  const int32_t cnt = st->big_tiles;
+  const int32_t G = (int32_t)gridDim.x;
+  int32_t i = (int32_t)blockIdx.x;
+  if (i >= cnt) return;
+  LpFetch<B, kPerThread> cur;
+  lp_fetch_loads(cur, meta[big[i]], rp, col, w, Lin, gv, gs);
+  lp_fetch_gather(cur, Lin);
+  while (true) {
+    const int32_t in = i + G;
+    const bool more = in < cnt;
+    LpFetch<B, kPerThread> nxt;
+    if (more) lp_fetch_loads(nxt, meta[big[in]], rp, col, w, Lin, gv, gs);
+    lp_tile_run<B, kPerThread>(cur, Lout, salt, sh, s_base, s_salt, [&]() {
+      if (more) lp_fetch_gather(nxt, Lin);
+    });
+    if (!more) break;
+    i = in;
     cur = nxt;
   }
 }
@@ -1454,56 +1508,79 @@ __global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shi
   hist[threadIdx.x * (int64_t)tiles + blockIdx.x] = h[threadIdx.x];
 }
 
+// The block ranks its elements per digit (wave match by ballots), stages them
+// in LDS in digit order, and then writes each digit's run to its global
+// position with consecutive threads on consecutive elements, so that the
+// writes of a run are coalesced instead of one scattered line per element.
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long *__restrict__ kin,
                                                         const int32_t *__restrict__ vin,
                                                         unsigned long long *__restrict__ kout,
                                                         int32_t *__restrict__ vout, int64_t count, int shift,
                                                         const int32_t *__restrict__ offs, int32_t tiles) {
   __shared__ int32_t wcnt[kBlock / 64][256];
+  __shared__ int32_t dstart[256];  // block-local start of each digit's run
+  __shared__ int32_t goff[256];    // global position of a run minus its block-local start
+  __shared__ int32_t sh[kBlock / 64];
+  __shared__ unsigned long long skey[kRsTile];
+  __shared__ int32_t sval[kRsTile];
+  static_assert(kBlock == 256, "one thread per digit");
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int d = threadIdx.x; d < 256 * (kBlock / 64); d += kBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
-  const int64_t base = blockIdx.x * (int64_t)kRsTile + (int64_t)wid * 64 * kRsItems;
+  const int64_t blk0 = blockIdx.x * (int64_t)kRsTile;
+  const int64_t base = blk0 + (int64_t)wid * 64 * kRsItems;
   unsigned long long key[kRsItems];
   int32_t val[kRsItems], rank[kRsItems], dig[kRsItems];
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   for (int j = 0; j < kRsItems; j++) {
-    int64_t i = base + j * 64 + lane;
-    bool ok = i < count;
+    const int64_t i = base + j * 64 + lane;
+    const bool ok = i < count;
     key[j] = ok ? kin[i] : 0;
     val[j] = ok ? vin[i] : 0;
-    int d = ok ? (int)((key[j] >> shift) & 255) : 0;
+    const int d = ok ? (int)((key[j] >> shift) & 255) : 0;
     dig[j] = ok ? d : -1;
     unsigned long long peers = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
-      unsigned long long bb = __ballot((d >> b) & 1);
+      const unsigned long long bb = __ballot((d >> b) & 1);
       peers &= ((d >> b) & 1) ? bb : ~bb;
     }
-    int r = __popcll(peers & lt);
-    int old = ok ? wcnt[wid][d] : 0;
+    const int r = __popcll(peers & lt);
+    const int old = ok ? wcnt[wid][d] : 0;
     __builtin_amdgcn_wave_barrier();
     if (ok && r == 0) wcnt[wid][d] = old + __popcll(peers);
     __builtin_amdgcn_wave_barrier();
     rank[j] = old + r;
   }
   __syncthreads();
-  {  // per digit: exclusive offsets across the block's waves
-    int d = threadIdx.x;
+  {  // thread d: offsets of digit d across the block's waves, then the digit's run start
+    const int d = threadIdx.x;
     int acc = 0;
     for (int q = 0; q < kBlock / 64; q++) {
-      int t = wcnt[q][d];
+      const int t = wcnt[q][d];
       wcnt[q][d] = acc;
       acc += t;
     }
+    int32_t total;
+    const int32_t start = block_excl_scan(acc, total, sh);
+    dstart[d] = start;
+    goff[d] = offs[d * (int64_t)tiles + blockIdx.x] - start;
   }
   __syncthreads();
   for (int j = 0; j < kRsItems; j++) {
     if (dig[j] < 0) continue;
-    int d = dig[j];
-    int64_t pos = (int64_t)offs[d * (int64_t)tiles + blockIdx.x] + wcnt[wid][d] + rank[j];
-    kout[pos] = key[j];
-    vout[pos] = val[j];
+    const int d = dig[j];
+    const int32_t l = dstart[d] + wcnt[wid][d] + rank[j];
+    skey[l] = key[j];
+    sval[l] = val[j];
+  }
+  __syncthreads();
+  const int32_t nvalid = (int32_t)min<int64_t>(kRsTile, count - blk0);
+  for (int e = threadIdx.x; e < nvalid; e += kBlock) {
+    const unsigned long long k = skey[e];
+    const int64_t pos = (int64_t)goff[(int)((k >> shift) & 255)] + e;
+    kout[pos] = k;
+    vout[pos] = sval[e];
   }
 }
 
@@ -1570,6 +1647,7 @@ __global__ void k_reset_bins(Status *st) {
     st->dmax = 0;
     st->tile_rows = 0;
     st->tile_arcs = 0;
+    st->big_tiles = 0;
   }
 }
 
@@ -1802,25 +1880,40 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
         if (!mk) {
           // condition 3 for a common neighbour u: w(v,u) > dv/2 - c and w(x,u) > dx/2 - c
           const long long tv = dv / 2 - c, tx = dx / 2 - c;  // dv < 2(c + a) <=> a > floor(dv/2) - c
+          // x's row in blocks of U chunks of G entries: all loads of a block
+          // first, then the first probes, then the rare longer probes; one
+          // reduction per block. The decision is the same as entry by
+          // entry: the sums only grow.
+          constexpr int U = 4;
           long long sum4 = c;
           int pr3 = 0;
-          for (int32_t j0 = xb; j0 < xe; j0 += G) {
-            const int32_t j = j0 + lane;
+          for (int32_t j0 = xb; j0 < xe; j0 += U * G) {
+            int32_t uu[U], wx[U], kk[U];
+            uint32_t hh[U];
+#pragma unroll
+            for (int q = 0; q < U; q++) {
+              const int32_t j = min(j0 + q * G + lane, xe - 1);
+              uu[q] = col[j];
+              wx[q] = w[j];
+            }
+#pragma unroll
+            for (int q = 0; q < U; q++) {
+              hh[q] = (uint32_t)(((unsigned long long)slot_hash(uu[q]) * size) >> 32);
+              kk[q] = tkey[hh[q]];
+            }
             uint32_t part = 0;
             int p3 = 0;
-            if (j < xe) {
-              const int32_t u = col[j];
-              uint32_t h = (uint32_t)(((unsigned long long)slot_hash(u) * size) >> 32);
-              while (true) {
-                const int32_t k = tkey[h];
-                if (k == u) {
-                  const int32_t cvu = tval[h], cxu = w[j];
-                  if (cvu > tv && cxu > tx) p3 = 1;
-                  part = (uint32_t)(cvu < cxu ? cvu : cxu);
-                  break;
-                }
-                if (k == -1) break;
-                h = (h + 1 == size) ? 0 : h + 1;
+#pragma unroll
+            for (int q = 0; q < U; q++) {
+              if (j0 + q * G + lane >= xe) continue;
+              while (kk[q] != uu[q] && kk[q] != -1) {
+                hh[q] = (hh[q] + 1 == size) ? 0 : hh[q] + 1;
+                kk[q] = tkey[hh[q]];
+              }
+              if (kk[q] == uu[q]) {
+                const int32_t cvu = tval[hh[q]], cxu = wx[q];
+                if (cvu > tv && cxu > tx) p3 = 1;
+                part += (uint32_t)(cvu < cxu ? cvu : cxu);
               }
             }
 #pragma unroll
@@ -2408,7 +2501,7 @@ hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
 
 hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s) {
   w.ntiles = (int32_t)((g.nnz + g.n + kTile - 1) / kTile);
-  k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta, w.st);
+  k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta, w.st, w.big_tiles);
   k_long_rows<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, w.n_in, w.bins, w.st);
   return hipGetLastError();
 }
@@ -2506,12 +2599,17 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   GStat *gs = bv ? bv->gs : nullptr;
   {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
-    if (bv)
+    if (bv) {
       k_lp_tile<true><<<resident_grid(k_lp_tile<true>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs);
-    else
+      k_lp_tile_big<true><<<resident_grid(k_lp_tile_big<true>, kTB, w.ntiles), kTB, 0, s>>>(
+          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, gv, gs);
+    } else {
       k_lp_tile<false><<<resident_grid(k_lp_tile<false>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr);
+      k_lp_tile_big<false><<<resident_grid(k_lp_tile_big<false>, kTB, w.ntiles), kTB, 0, s>>>(
+          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);
+    }
   }
   launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);

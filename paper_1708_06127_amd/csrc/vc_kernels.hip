@@ -1836,6 +1836,13 @@ __global__ void k_pr_list(const int32_t *rp, int32_t n, int32_t *list, Status *s
 // slots; one 16-lane group per owned arc (v, x) scans x's row against it,
 // 16 entries at a time (4 arcs in flight per wave, loads still coalesced).
 // Partial sums are 32-bit: c + sum <= deg(v) <= total weight <= INT32_MAX.
+// Slot of key u in a power-of-two table (24-bit multiplies: full rate).
+__device__ __forceinline__ uint32_t pr_slot(int32_t u, uint32_t mask) {
+  return (__umul24((uint32_t)u ^ ((uint32_t)u >> 16), 0x9E3779u) >> 8) & mask;
+}
+__device__ __forceinline__ int32_t clamp_i32(long long x) {
+  return x > INT32_MAX ? INT32_MAX : x < -1 ? -1 : (int32_t)x;
+}
 constexpr int kPrGroup = 16;
 template <int TBL, bool B>
 __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -1854,7 +1861,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
   for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
     const int32_t v = which == 0 ? list[r] : list[n - 1 - r];
     const int32_t vb = rp[v], ve = rp[v + 1], lv = ve - vb;
-    const uint32_t size = 2u * (uint32_t)lv;
+    // power-of-two table of at least 2 |row| slots (TBL is a power of two >= 2 |row|)
+    uint32_t size = 64;
+    while (size < 2u * (uint32_t)lv) size <<= 1;
+    const uint32_t mask = size - 1;
     const int32_t g = B ? gv[v] : 0;
     const long long lam = B ? graph_lam(gs[g]) : st->lam_hat;
     for (int e = threadIdx.x; e < (int)size; e += kBlock) tkey[e] = -1;
@@ -1862,8 +1872,8 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
     __syncthreads();
     for (int32_t i = vb + threadIdx.x; i < ve; i += kBlock) {  // distinct keys: one free slot each
       const int32_t u = col[i];
-      uint32_t h = (uint32_t)(((unsigned long long)slot_hash(u) * size) >> 32);
-      while (atomicCAS(&tkey[h], -1, u) != -1) h = (h + 1 == size) ? 0 : h + 1;
+      uint32_t h = pr_slot(u, mask);
+      while (atomicCAS(&tkey[h], -1, u) != -1) h = (h + 1) & mask;
       tval[h] = w[i];
     }
     __syncthreads();
@@ -1879,7 +1889,9 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
         mk = pr_cheap(c, dv, dx, lam);
         if (!mk) {
           // condition 3 for a common neighbour u: w(v,u) > dv/2 - c and w(x,u) > dx/2 - c
-          const long long tv = dv / 2 - c, tx = dx / 2 - c;  // dv < 2(c + a) <=> a > floor(dv/2) - c
+          // (dv < 2(c + a) <=> a > floor(dv/2) - c); the thresholds are clamped to
+          // int32 (weights are positive int32), so the comparisons stay 32-bit
+          const int32_t tv = clamp_i32(dv / 2 - c), tx = clamp_i32(dx / 2 - c);
           // x's row in blocks of U chunks of G entries: all loads of a block
           // first, then the first probes, then the rare longer probes; one
           // reduction per block. The decision is the same as entry by
@@ -1898,7 +1910,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
             }
 #pragma unroll
             for (int q = 0; q < U; q++) {
-              hh[q] = (uint32_t)(((unsigned long long)slot_hash(uu[q]) * size) >> 32);
+              hh[q] = pr_slot(uu[q], mask);
               kk[q] = tkey[hh[q]];
             }
             uint32_t part = 0;
@@ -1907,7 +1919,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
             for (int q = 0; q < U; q++) {
               if (j0 + q * G + lane >= xe) continue;
               while (kk[q] != uu[q] && kk[q] != -1) {
-                hh[q] = (hh[q] + 1 == size) ? 0 : hh[q] + 1;
+                hh[q] = (hh[q] + 1) & mask;
                 kk[q] = tkey[hh[q]];
               }
               if (kk[q] == uu[q]) {

@@ -107,6 +107,11 @@ def traffic_for(kernel, workload):
 
 
 COPY_PROBE_BYTES = 256 << 20  # the --copy-probe device copy: 64 Mi int32 read and written
+# a timed unit of the library's kernel timer and the device kernels it covers
+# (the LP iteration t >= 2 runs the tiles of at most 256 arcs and the larger
+# tiles in two launches, timed together)
+TIMED_UNITS = {"k_lp_tile": ["k_lp_tile", "k_lp_tile_big"], "k_first_tile": ["k_first_tile"],
+               "k_first_tile_level0": ["k_first_tile"]}
 
 
 def record_traffic(fetch_csv, write_csv, kernel, workload, command):
@@ -119,7 +124,7 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, command):
     import csv
 
     def per_kernel(path, counter):
-        copy_best, vals = 0.0, []
+        copy_best, vals = 0.0, {k: [] for k in TIMED_UNITS.get(kernel, [kernel])}
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
@@ -128,11 +133,14 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, command):
                 name = r["Kernel_Name"]
                 if "copyBuffer" in name:
                     copy_best = max(copy_best, v)
-                elif "%s(" % kernel in name or "%s<" % kernel in name:
-                    vals.append(v)
-        if not copy_best or not vals:
+                for k in vals:
+                    if "::%s(" % k in name or "::%s<" % k in name:
+                        vals[k].append(v)
+        if not copy_best or not all(vals.values()):
             raise SystemExit("%s: no copy probe or no %s dispatch with %s" % (path, kernel, counter))
-        return sum(vals) / len(vals), COPY_PROBE_BYTES / copy_best, len(vals)
+        # per timed unit: the sum over its kernels of the mean per dispatch
+        return sum(sum(v) / len(v) for v in vals.values()), COPY_PROBE_BYTES / copy_best, \
+            [len(v) for v in vals.values()]
 
     fetch, f_scale, nf = per_kernel(fetch_csv, "FETCH_SIZE")
     write, w_scale, nw = per_kernel(write_csv, "WRITE_SIZE")

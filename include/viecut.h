@@ -104,9 +104,10 @@ typedef struct {
  *                   exact solve on the remaining graph gave it
  *   status_bits   - VIECUT_ST_* bits
  *   levels        - contractions performed
- *   t_ms          - host-measured phase times: [0] validate+first LP iteration, [1] remaining LP
- *                   iterations, [2] cluster contraction, [3] PR marking+union-find+contraction,
- *                   [4] exact solve + transfer, [5] total; [6],[7] unused. */
+ *   t_ms          - host-measured phase times: [0] validate+first LP iteration, [1] enqueueing the
+ *                   remaining LP iterations (their kernels finish within [2]), [2] cluster
+ *                   contraction, [3] PR marking+union-find+contraction, [4] exact solve + transfer,
+ *                   [5] total; [6],[7] unused. */
 typedef struct {
   int64_t cut;
   int32_t rounds;

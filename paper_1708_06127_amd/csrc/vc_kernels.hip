@@ -212,6 +212,7 @@ __device__ __forceinline__ int32_t tile_start(const int32_t *rp, int32_t n, int6
 // `big`, in any order, for the LP kernel that runs them with 8 arcs per thread.
 __global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st, int32_t *big) {
   __shared__ unsigned long long sh[kBlock / 64];
+  __shared__ int32_t s_cnt, s_base;
   const int lane = threadIdx.x & 63;
   unsigned long long rows = 0, arcs = 0;
   for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < ntiles; t0 += (int64_t)gridDim.x * kBlock) {
@@ -227,11 +228,18 @@ __global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta
       arcs += (unsigned long long)acnt;
       is_big = acnt > 4 * kTB;
     }
+    // big tiles: a wave count in LDS, then one global reservation per block
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
     const unsigned long long bal = __ballot(is_big);
-    int32_t base = 0;
-    if (lane == 0 && bal) base = atomicAdd(&st->big_tiles, (int32_t)__popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (is_big) big[base + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)t;
+    int32_t wbase = 0;
+    if (lane == 0 && bal) wbase = atomicAdd(&s_cnt, (int32_t)__popcll(bal));
+    wbase = __shfl(wbase, 0, 64);
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&st->big_tiles, s_cnt) : 0;
+    __syncthreads();
+    if (is_big) big[s_base + wbase + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)t;
+    __syncthreads();
   }
   // totals over the tiles (the algorithmic size of a tile sweep)
   rows = block_sum(rows, sh);
@@ -1836,6 +1844,27 @@ __global__ void k_pr_list(const int32_t *rp, int32_t n, int32_t *list, Status *s
 // slots; one 16-lane group per owned arc (v, x) scans x's row against it,
 // 16 entries at a time (4 arcs in flight per wave, loads still coalesced).
 // Partial sums are 32-bit: c + sum <= deg(v) <= total weight <= INT32_MAX.
+constexpr int kPrGroup = 16;  // lanes per owned arc in k_pr_rows
+
+// Sum / or over each aligned row of 16 lanes with DPP moves (no LDS): after
+// the two quad permutations a lane holds its quad's value, row_half_mirror
+// pairs the quads of each half row, row_mirror the two halves. Every lane of
+// a row must be active.
+__device__ __forceinline__ uint32_t row16_sum(uint32_t v) {
+  static_assert(kPrGroup == 16, "PR groups are DPP rows");
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return v;
+}
+__device__ __forceinline__ int row16_or(int v) {
+  v |= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
+  return v;
+}
 // Slot of key u in a power-of-two table (24-bit multiplies: full rate).
 __device__ __forceinline__ uint32_t pr_slot(int32_t u, uint32_t mask) {
   return (__umul24((uint32_t)u ^ ((uint32_t)u >> 16), 0x9E3779u) >> 8) & mask;
@@ -1843,7 +1872,6 @@ __device__ __forceinline__ uint32_t pr_slot(int32_t u, uint32_t mask) {
 __device__ __forceinline__ int32_t clamp_i32(long long x) {
   return x > INT32_MAX ? INT32_MAX : x < -1 ? -1 : (int32_t)x;
 }
-constexpr int kPrGroup = 16;
 template <int TBL, bool B>
 __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w,
@@ -1854,6 +1882,10 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
   __shared__ int32_t tkey[TBL];
   __shared__ int32_t tval[TBL];
   __shared__ int s_any;
+  // owned arcs of the current chunk that need the common neighbourhood
+  __shared__ int32_t s_nwork;
+  __shared__ int32_t s_wi[kBlock], s_wb[kBlock], s_we[kBlock], s_wc[kBlock];
+  __shared__ long long s_wd[kBlock];
   constexpr int G = kPrGroup;
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int32_t cnt = st->pr_rows[which];
@@ -1879,15 +1911,43 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
     __syncthreads();
     const long long dv = (long long)degu[v];
     bool any = false;
-    for (int32_t i = vb + grp; i < ve; i += kBlock / G) {
-      const int32_t x = col[i];
-      const int32_t xb = rp[x], xe = rp[x + 1];
-      bool mk = false;
-      if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
-        const long long c = w[i];
-        const long long dx = (long long)degu[x];
-        mk = pr_cheap(c, dv, dx, lam);
-        if (!mk) {
+    // The row's arcs in chunks of kBlock: every thread decides the cheap
+    // cases of one arc and lists the owned arcs that need the common
+    // neighbourhood; the groups then share that list evenly.
+    for (int32_t c0 = vb; c0 < ve; c0 += kBlock) {
+      if (threadIdx.x == 0) s_nwork = 0;
+      __syncthreads();
+      const int32_t i = c0 + (int32_t)threadIdx.x;
+      if (i < ve) {
+        const int32_t x = col[i];
+        const int32_t xb = rp[x], xe = rp[x + 1];
+        bool mk = false;
+        if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
+          const int32_t c = w[i];
+          const long long dx = (long long)degu[x];
+          mk = pr_cheap(c, dv, dx, lam);
+          if (!mk) {
+            const int32_t k = atomicAdd(&s_nwork, 1);
+            s_wi[k] = i;
+            s_wb[k] = xb;
+            s_we[k] = xe;
+            s_wc[k] = c;
+            s_wd[k] = dx;
+          }
+        }
+        mark[i] = mk ? 1 : 0;
+        if (mk) {
+          any = true;
+          if constexpr (B) flag_marked(gs, g, flagged);
+        }
+      }
+      __syncthreads();
+      const int32_t nwork = s_nwork;
+      for (int32_t wi = grp; wi < nwork; wi += kBlock / G) {
+        const int32_t ia = s_wi[wi], xb = s_wb[wi], xe = s_we[wi];
+        const long long c = s_wc[wi], dx = s_wd[wi];
+        bool mk;
+        {
           // condition 3 for a common neighbour u: w(v,u) > dv/2 - c and w(x,u) > dx/2 - c
           // (dv < 2(c + a) <=> a > floor(dv/2) - c); the thresholds are clamped to
           // int32 (weights are positive int32), so the comparisons stay 32-bit
@@ -1928,24 +1988,22 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
                 part += (uint32_t)(cvu < cxu ? cvu : cxu);
               }
             }
-#pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) {
-              part += __shfl_xor(part, off, G);
-              p3 |= __shfl_xor(p3, off, G);
-            }
+            part = row16_sum(part);  // the groups are the 16-lane DPP rows
+            p3 = row16_or(p3);
             sum4 += part;
             pr3 |= p3;
             if (pr3 || sum4 >= lam) break;  // decided
           }
           mk = pr3 || sum4 >= lam;
         }
+        if (lane == 0) mark[ia] = mk ? 1 : 0;
+        if (mk) {
+          any = true;
+          if constexpr (B)
+            if (lane == 0) flag_marked(gs, g, flagged);
+        }
       }
-      if (lane == 0) mark[i] = mk ? 1 : 0;
-      if (mk) {
-        any = true;
-        if constexpr (B)
-          if (lane == 0) flag_marked(gs, g, flagged);
-      }
+      __syncthreads();
     }
     if (any && lane == 0) s_any = 1;
     __syncthreads();

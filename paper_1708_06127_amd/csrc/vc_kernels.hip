@@ -957,8 +957,8 @@ __global__ void k_huge_clear(int32_t *tk, uint32_t *tv, const Status *st) {
   }
 }
 
-// one chunk per block iteration: level-0 validation/degree, first-iteration
-// argmax (no table), or table insertion of neighbour labels
+// one chunk per block iteration: the first-iteration argmax of (w, -prio),
+// at level 0 (mode 2) also validation and degree
 __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ w, int32_t n,
                                                         const int32_t *list, const int32_t *cnt_p,
@@ -966,8 +966,6 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
                                                         int32_t *tk, uint32_t *tv, unsigned long long *best,
                                                         long long *deg, uint32_t salt, int mode, Status *st,
                                                         const int32_t *__restrict__ gv, GStat *gs) {
-  // mode 0: first iteration (argmax of (w,-prio)) + optional level-0 degree (mode 2)
-  // mode 1: table insertion
   __shared__ unsigned long long sh[kBlock / 64];
   if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
@@ -977,74 +975,129 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
     int32_t v = list[i];
     int32_t beg = rp[v] + (p - meta[3 * (int64_t)i]) * kHugeChunk;
     int32_t end = min(rp[v + 1], beg + kHugeChunk);
-    if (mode == 1) {
-      int32_t *K = tk + meta[3 * (int64_t)i + 1];
-      uint32_t *V = tv + meta[3 * (int64_t)i + 1];
-      const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
-      for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
-        int32_t x = Lin[col[a]];
-        uint32_t h = slot_hash(x) & mask;
-        while (true) {
-          int32_t k = __hip_atomic_load(&K[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (k == x) break;
-          if (k == -1) {
-            int32_t old = atomicCAS(&K[h], -1, x);
-            if (old == -1 || old == x) break;
-          }
-          h = (h + 1) & mask;
-        }
-        atomicAdd(&V[h], (uint32_t)w[a]);
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
+    }
+    unsigned long long b = 0, sum = 0;
+    int err = 0;
+    for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
+      int32_t x = col[a], c = w[a];
+      if (mode == 2) {
+        if (x < 0 || x >= n) err |= ERR_COL;
+        if (x == v) err |= ERR_SELF;
+        if (c < 1) err |= ERR_WEIGHT;
       }
-    } else {
-      int32_t b0 = 0;
-      uint32_t sl = salt;
-      if (gv) {
-        const GStat &g = gs[gv[v]];
-        b0 = g.base;
-        sl = g.salt;
-      }
-      unsigned long long b = 0, sum = 0;
-      int err = 0;
-      for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
-        int32_t x = col[a], c = w[a];
-        if (mode == 2) {
-          if (x < 0 || x >= n) err |= ERR_COL;
-          if (x == v) err |= ERR_SELF;
-          if (c < 1) err |= ERR_WEIGHT;
-        }
-        sum += (unsigned long long)(uint32_t)c;
-        b = umax64(b, cand_key((uint32_t)c, x - b0, sl));
-      }
-      b = block_max(b, sh);
-      sum = block_sum(sum, sh);
-      err = (int)block_max((unsigned long long)err, sh);
-      if (threadIdx.x == 0) {
-        atomicMax(&best[i], b);
-        if (mode == 2) {
-          atomicAdd((unsigned long long *)&deg[v], sum);
-          if (gv) {
-            if (err) atomicOr(&gs[gv[v]].err, err);
-          } else {
-            atomicAdd(&st->wsum, sum);
-            if (err) atomicOr(&st->err, err);
-          }
+      sum += (unsigned long long)(uint32_t)c;
+      b = umax64(b, cand_key((uint32_t)c, x - b0, sl));
+    }
+    b = block_max(b, sh);
+    sum = block_sum(sum, sh);
+    err = (int)block_max((unsigned long long)err, sh);
+    if (threadIdx.x == 0) {
+      atomicMax(&best[i], b);
+      if (mode == 2) {
+        atomicAdd((unsigned long long *)&deg[v], sum);
+        if (gv) {
+          if (err) atomicOr(&gs[gv[v]].err, err);
+        } else {
+          atomicAdd(&st->wsum, sum);
+          if (err) atomicOr(&st->err, err);
         }
       }
     }
   }
 }
 
-// table scan: per slot, contribute its candidate key to the row's maximum
+// Table insertion for LP iterations t >= 2 on huge rows, one chunk of
+// kHugeChunk arcs per block iteration: the chunk's (label, weight) pairs are
+// first summed in an LDS table, then each distinct label of the chunk makes
+// one insertion into the row's global table (neighbour labels of a huge row
+// repeat a lot, so this removes most global atomics).
+constexpr int kHugeLocal = 2 * kHugeChunk;  // LDS slots: load <= 1/2
+__global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ w, const int32_t *list,
+                                                        const int32_t *cnt_p, const int32_t *meta,
+                                                        const int32_t *__restrict__ Lin, int32_t *tk, uint32_t *tv,
+                                                        const Status *st, const int32_t *__restrict__ gv) {
+  __shared__ int32_t lk[kHugeLocal];
+  __shared__ uint32_t lv[kHugeLocal];
+  if (!gv && st->err) return;
+  const int32_t cnt = *cnt_p;
+  const int32_t items = st->huge_items;
+  constexpr uint32_t lmask = kHugeLocal - 1;
+  for (int32_t p = blockIdx.x; p < items; p += gridDim.x) {
+    const int32_t i = huge_find(meta, cnt, p, 0);
+    const int32_t v = list[i];
+    const int32_t beg = rp[v] + (p - meta[3 * (int64_t)i]) * kHugeChunk;
+    const int32_t end = min(rp[v + 1], beg + kHugeChunk);
+    for (int e = threadIdx.x; e < kHugeLocal; e += kBlock) {
+      lk[e] = -1;
+      lv[e] = 0;
+    }
+    __syncthreads();
+    for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
+      const int32_t x = Lin[col[a]];
+      uint32_t h = slot_hash(x) & lmask;
+      while (true) {
+        const int32_t old = atomicCAS(&lk[h], -1, x);
+        if (old == -1 || old == x) break;
+        h = (h + 1) & lmask;
+      }
+      atomicAdd(&lv[h], (uint32_t)w[a]);
+    }
+    __syncthreads();
+    int32_t *K = tk + meta[3 * (int64_t)i + 1];
+    uint32_t *V = tv + meta[3 * (int64_t)i + 1];
+    const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
+    for (int e = threadIdx.x; e < kHugeLocal; e += kBlock) {
+      const int32_t x = lk[e];
+      if (x < 0) continue;
+      uint32_t h = slot_hash(x) & mask;
+      while (true) {
+        const int32_t k = __hip_atomic_load(&K[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == x) break;
+        if (k == -1) {
+          const int32_t old = atomicCAS(&K[h], -1, x);
+          if (old == -1 || old == x) break;
+        }
+        h = (h + 1) & mask;
+      }
+      atomicAdd(&V[h], lv[e]);
+    }
+    __syncthreads();
+  }
+}
+
+// table scan: each wave takes one contiguous range of slots, 64 at a time.
+// Every table is a power of two of at least 2 * 4096 slots, so the tables
+// start at multiples of 8192 and 64 aligned slots lie in one table; the wave
+// finds the table of its first slot once and then steps through the table
+// ends. Per 64 slots the candidate keys are reduced and the row's best key
+// gets one maximum update.
 __global__ void k_huge_scan(const int32_t *meta, const int32_t *cnt_p, const int32_t *tk, const uint32_t *tv,
                             unsigned long long *best, uint32_t salt, const Status *st, const int32_t *list,
                             const int32_t *__restrict__ gv, const GStat *gs) {
   if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
   const int64_t slots = st->huge_slots;
-  for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < slots; s += (int64_t)gridDim.x * kBlock) {
-    int32_t k = tk[s];
-    if (k < 0) continue;
-    int32_t i = huge_find(meta, cnt, (int32_t)s, 1);
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  const int64_t span = ((slots + nwaves - 1) / nwaves + 63) & ~(int64_t)63;
+  const int64_t lo = wave * span, hi = min<int64_t>(slots, lo + span);
+  if (lo >= hi) return;
+  int32_t i = huge_find(meta, cnt, (int32_t)lo, 1);
+  int64_t row_end = i + 1 < cnt ? meta[3 * (int64_t)(i + 1) + 1] : slots;
+  for (int64_t s0 = lo; s0 < hi; s0 += 64) {
+    while (s0 >= row_end) {  // next table (uniform across the wave)
+      i++;
+      row_end = i + 1 < cnt ? meta[3 * (int64_t)(i + 1) + 1] : slots;
+    }
     int32_t b0 = 0;
     uint32_t sl = salt;
     if (gv) {
@@ -1052,7 +1105,11 @@ __global__ void k_huge_scan(const int32_t *meta, const int32_t *cnt_p, const int
       b0 = g.base;
       sl = g.salt;
     }
-    atomicMax(&best[i], cand_key(tv[s], k - b0, sl));
+    const int64_t s = s0 + lane;
+    const int32_t k = s < slots ? tk[s] : -1;
+    unsigned long long key = k >= 0 ? cand_key(tv[s], k - b0, sl) : 0ull;
+    key = grp_max<64>(key);
+    if (lane == 0 && key) atomicMax(&best[i], key);
   }
 }
 
@@ -2688,10 +2745,9 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   const int32_t *cnt6 = &w.st->bin_cnt[6];
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st);
   k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);
-  k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list6, cnt6,
+  k_huge_insert<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, list6, cnt6,
                                                                      w.huge_meta, Lin, w.huge_tab_key,
-                                                                     w.huge_tab_val, w.huge_best, nullptr, salt, 1,
-                                                                     w.st, gv, gs);
+                                                                     w.huge_tab_val, w.st, gv);
   k_huge_scan<<<2048, kBlock, 0, s>>>(w.huge_meta, cnt6, w.huge_tab_key, w.huge_tab_val, w.huge_best, salt, w.st,
                                       list6, gv, gs);
   k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, Lin, w.huge_tab_key,

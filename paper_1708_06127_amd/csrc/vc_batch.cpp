@@ -289,6 +289,7 @@ struct Engine {
     VC_TRY(hipStreamSynchronize(s));
     t_sync += now_ms() - t0;
     n_syncs++;
+    if (hst()->err & ERR_DEVICE) return VIECUT_EDEVICE;
     return VIECUT_OK;
   }
 

@@ -125,15 +125,8 @@ struct Layout {
   }
 };
 
-int64_t scan_tmp_need(int64_t count) {
-  int64_t need = 0;
-  int64_t c = count;
-  while (c > 2048) {
-    c = (c + 2047) / 2048;
-    need += c;
-  }
-  return need + 64;
-}
+// state words of the single-pass scan: one per 2048-element tile
+int64_t scan_tiles_max(int64_t count) { return (count + 2047) / 2048 + 1; }
 
 // map_n: entries of the input -> current vertex map (n for a single solve,
 // 64 per word of the padded input index space for a batched one); extra:
@@ -165,7 +158,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // 18 vals0
   L.add(4 * (size_t)std::max<int64_t>(nnz, 1));  // 19 vals1
   L.add(4 * 256 * (size_t)tiles);              // 20 hist
-  L.add(4 * (size_t)scan_tmp_need(maxscan));   // 21 scan_tmp
+  L.add(8 * (size_t)scan_tiles_max(maxscan) + 64);  // 21 scan state words + ticket
   L.add((size_t)std::max<int64_t>(nnz, 1));    // 22 mark
   L.add(4 * (size_t)n + 4);                    // 23 parent
   L.add(4 * 4 * (size_t)std::max<int64_t>(nnz, 1));  // 24 huge keys (4 slots per arc)
@@ -214,10 +207,14 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
   w.vals[0] = (int32_t *)at(18);
   w.vals[1] = (int32_t *)at(19);
   w.hist = (int32_t *)at(20);
-  w.scan_tmp = (int32_t *)at(21);
-  const int64_t tiles = (nnz + 4095) / 4096 + 1;
-  const int64_t nseg = (nnz + n) / kTile + 2 + 3 * (nnz / kTile + 1) + 2;
-  w.scan_tmp_elems = (size_t)scan_tmp_need(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg}));
+  {
+    const int64_t tiles = (nnz + 4095) / 4096 + 1;
+    const int64_t nseg = (nnz + n) / kTile + 2 + 3 * (nnz / kTile + 1) + 2;
+    w.lb_tiles = scan_tiles_max(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg}));
+    w.lb_state = (unsigned long long *)at(21);
+    w.lb_ticket = (uint32_t *)(w.lb_state + w.lb_tiles);
+    w.lb_epoch = 0;
+  }
   w.mark = (uint8_t *)at(22);
   w.parent = (int32_t *)at(23);
   w.huge_tab_key = (int32_t *)at(24);
@@ -265,6 +262,7 @@ struct Solver {
   int sync_status() {
     VC_TRY(hipMemcpyAsync(&st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
+    if (st.err & ERR_DEVICE) return VIECUT_EDEVICE;
     return VIECUT_OK;
   }
 
@@ -332,7 +330,6 @@ struct Solver {
   // is invalidated for the new graph.
   int contract(const int32_t *L, DGraph &G, int &cur, int32_t &level, const int32_t *&known) {
     VC_TRY(relabel(L, G.n, w, s));
-    VC_TRY(compose_map(w, s));
     VC_TRY(contract_emit(G, w, known, s));
     int rc = sync_status();
     if (rc) return rc;

@@ -32,7 +32,8 @@ __host__ __device__ inline int degree_bin(int32_t d) {
 }
 
 enum : int32_t {
-  ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELF = 4, ERR_WEIGHT = 8, ERR_NOTSYM = 16, ERR_UNSORTED = 32
+  ERR_ROWPTR = 1, ERR_COL = 2, ERR_SELF = 4, ERR_WEIGHT = 8, ERR_NOTSYM = 16, ERR_UNSORTED = 32,
+  ERR_DEVICE = 64  // a bounded wait between workgroups expired (results of the call are void)
 };
 enum : int32_t { ST_COLLAPSED = 1, ST_DISCONNECTED = 2, ST_NO_PROGRESS = 4, ST_MAX_ROUNDS = 8 };
 
@@ -162,8 +163,12 @@ struct Work {
   unsigned long long *keys[2] = {nullptr, nullptr};  // sort keys (nnz each)
   int32_t *vals[2] = {nullptr, nullptr};             // sort values
   int32_t *hist = nullptr;       // radix histogram, 256 * tiles
-  int32_t *scan_tmp = nullptr;   // scan block sums
-  size_t scan_tmp_elems = 0;
+  // single-pass scans: one state word per tile (epoch, flag, value) and the
+  // tile ticket; lb_epoch == 0 means the words have not been cleared yet
+  unsigned long long *lb_state = nullptr;
+  uint32_t *lb_ticket = nullptr;
+  int64_t lb_tiles = 0;          // state words available
+  uint32_t lb_epoch = 0;         // host-side: epoch of the last scan launched
   uint8_t *mark = nullptr;       // PR mark per arc
   int32_t *parent = nullptr;     // union-find
   int32_t *huge_tab_key = nullptr;  // global hash tables of the huge bin
@@ -176,7 +181,7 @@ struct Work {
   int32_t *big_tiles = nullptr;  // ids of the tiles of more than 256 arcs (any order)
   int32_t ntiles = 0;            // tiles of the current level
   unsigned long long *part = nullptr;  // per-block partial results (3 per tile)
-  int32_t *seg = nullptr;        // emission segments: (first arc, count) pairs
+  int32_t *seg = nullptr;        // emission segments: first arc of each
   int32_t *seg_cnt = nullptr;    // their counts, then exclusive offsets
 };
 
@@ -187,8 +192,8 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
 // All launchers enqueue on `s` and return hipSuccess or the launch error.
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
 hipError_t status_reset(Status *st, hipStream_t s);
-hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t count, int32_t *total, int32_t *tmp,
-                          size_t tmp_elems, hipStream_t s);
+// exclusive scan of int32 counts (in-place capable); *total (optional) gets the sum
+hipError_t scan_exclusive(Work &w, const int32_t *in, int32_t *out, int64_t count, int32_t *total, hipStream_t s);
 
 hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s);
 hipError_t reset_bins(Work &w, hipStream_t s);
@@ -203,12 +208,12 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
                    hipStream_t s, const BatchView *bv = nullptr);
 hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchView *bv = nullptr);
-// relabel: ids = prefix sum of used label values, cl[v] = ids[L[v]], k -> st->k
+// relabel: ids = prefix sum of used label values, cl[v] = ids[L[v]], k -> st->k;
+// a single solve also composes map[u] <- cl[map[u]] in the same pass
 // (batched: only graphs in the round loop keep their vertices; gv_new receives
-// the graph index of every new vertex)
+// the graph index of every new vertex; the map is composed separately)
 hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const BatchView *bv = nullptr,
                    int32_t *gv_new = nullptr);
-hipError_t compose_map(Work &w, hipStream_t s);
 hipError_t init_map(Work &w, hipStream_t s);
 // contraction: inter-cluster triples packed into buffer 1 (count -> st->ax, key bits from st->k)
 hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);

@@ -431,10 +431,11 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
 }
 
 // ------------------------------------------------------------ tiled LP (short rows)
-// A tile's arcs are split into 256 runs of q = ceil(arcs/256) <= 8
-// consecutive arcs, one per thread. Every global load of a thread's run is
-// issued before the barrier that publishes the tile's row offsets in LDS;
-// the row of each arc is then found by one binary search and a forward walk.
+// A tile's arcs are split into 64 runs of q = ceil(arcs/64) <= 8 consecutive
+// arcs, one per lane of the tile's single wave. Every global load of a lane's
+// run is issued before the barrier that publishes the tile's row offsets in
+// LDS; the row of each arc is then found by one binary search and a forward
+// walk.
 
 // Iteration 1 on a tile: running (w, -prio) maximum and weight sum per row
 // run, flushed to per-row LDS slots; one thread per row writes the label. At
@@ -621,7 +622,8 @@ struct LpTileShared {
 // Registers of one tile, fetched ahead of its processing: per thread NQ arcs
 // (neighbour, then its label, and weight) and the tile's row data, one entry
 // per 64 rows.
-constexpr int kRowRegs = kTile / kTB;
+constexpr int kRowRegs = kTile / kTB;  // row-offset registers per lane (rows <= kTile)
+
 template <bool B, int NQ>
 struct LpFetch {
   int4 m;
@@ -1219,44 +1221,164 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t &total, in
   return off + inc - x;
 }
 
-__global__ void k_scan_reduce(const int32_t *in, int64_t count, int32_t *bsum) {
-  __shared__ unsigned long long sh[kBlock / 64];
-  int64_t base = blockIdx.x * (int64_t)kScanTile;
-  unsigned long long s = 0;
-  for (int j = 0; j < kScanItems; j++) {
-    int64_t i = base + j * kBlock + threadIdx.x;
-    if (i < count) s += (uint32_t)in[i];
-  }
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)s;
+// ---- single-pass scan with decoupled look-back (Merrill & Garland 2016)
+// Workgroups take tiles in ticket order, so every predecessor of a tile has
+// started. A tile publishes its aggregate, then wave 0 reads the state words
+// of up to 64 predecessors at once, newest first, and adds them up to the
+// first one holding an inclusive prefix. Each state word packs (epoch, flag,
+// value) into one 64-bit atomic, so a value is never seen without its flag,
+// and words of earlier launches (older epochs) read as "not ready": the array
+// is cleared once, not per launch. The wait is bounded by the wall clock: on
+// expiry the status gets ERR_DEVICE and missing aggregates count as 0, which
+// keeps every offset at or below its true value (in bounds for consumers).
+constexpr uint32_t kLbAgg = 1, kLbInc = 2;
+constexpr uint64_t kLbWaitTicks = 1ull << 26;  // ~0.67 s of the 100 MHz wall clock
+
+__device__ __forceinline__ unsigned long long lb_word(uint32_t epoch, uint32_t flag, uint32_t v) {
+  return ((unsigned long long)((epoch << 2) | flag) << 32) | v;
 }
 
-// in-place capable: out may equal in. offsets (optional) adds per-tile bases.
-__global__ void k_scan_tile(const int32_t *in, int32_t *out, int64_t count, const int32_t *offsets, int32_t *total) {
-  __shared__ int32_t tile[kScanTile];
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// wave-uniform; call from one whole wave. Returns the sum of the values of
+// tiles [0, t) published under `epoch`.
+__device__ unsigned long long lb_lookback(const unsigned long long *state, int64_t t, uint32_t epoch, Status *st) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long excl = 0;
+  int64_t j = t - 1;  // newest predecessor not yet accounted for
+  const uint64_t t0 = wall_clock64();
+  while (j >= 0) {
+    const int64_t idx = j - lane;
+    unsigned long long wd, need, ib;
+    bool ready;
+    while (true) {
+      wd = idx >= 0 ? __hip_atomic_load(&state[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : lb_word(epoch, kLbInc, 0u);
+      const uint32_t hi = (uint32_t)(wd >> 32);
+      ready = (hi >> 2) == epoch && (hi & 3u) != 0;
+      ib = __ballot(ready && (hi & 3u) == kLbInc);
+      const unsigned long long nr = __ballot(!ready);
+      need = ib ? (((ib & (~ib + 1)) << 1) - 1) : ~0ull;  // lanes up to the first inclusive one
+      if ((nr & need) == 0) break;
+      if (wall_clock64() - t0 > kLbWaitTicks) {
+        if (lane == 0) atomicOr(&st->err, ERR_DEVICE);
+        ib = ~0ull;  // stop after this window
+        break;
+      }
+    }
+    const bool take = ((need >> lane) & 1ull) && ready;
+    excl += wave_sum_u64(take ? (unsigned long long)(uint32_t)wd : 0ull);
+    if (ib) break;
+    j -= 64;
+  }
+  return excl;
+}
+
+__device__ __forceinline__ int lb_pad(int e) { return e + (e >> 5); }
+
+// ITEMS elements per thread; all global loads are issued before any is used
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_scan_lb(const int32_t *in, int32_t *out, int64_t count, int32_t *total,
+                                                     unsigned long long *state, uint32_t *ticket, uint32_t epoch,
+                                                     int32_t ntiles, Status *st) {
+  constexpr int TILE = kBlock * ITEMS;
+  __shared__ int32_t tile[TILE + TILE / 32];  // one pad word per 32: conflict-free rows
   __shared__ int32_t sh[kBlock / 64];
-  int64_t base = blockIdx.x * (int64_t)kScanTile;
-  for (int j = 0; j < kScanItems; j++) {
-    int64_t i = base + j * kBlock + threadIdx.x;
-    tile[j * kBlock + threadIdx.x] = i < count ? in[i] : 0;
+  __shared__ int32_t s_t, s_excl;
+  if (threadIdx.x == 0) {
+    const int32_t t = (int32_t)atomicAdd(ticket, 1u);
+    if (t == ntiles - 1) atomicExch(ticket, 0u);  // the last ticket of the launch: rearm
+    s_t = t;
   }
   __syncthreads();
-  int32_t loc[kScanItems];
+  const int32_t t = s_t;
+  const int64_t base = t * (int64_t)TILE;
+  int32_t v[ITEMS];
+#pragma unroll
+  for (int j = 0; j < ITEMS; j++) {
+    const int64_t i = base + j * kBlock + threadIdx.x;
+    v[j] = in[i < count ? i : count - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; j++) {
+    const int64_t i = base + j * kBlock + threadIdx.x;
+    tile[lb_pad(j * kBlock + threadIdx.x)] = i < count ? v[j] : 0;
+  }
+  __syncthreads();
   int32_t acc = 0;
-  for (int j = 0; j < kScanItems; j++) {
-    loc[j] = acc;
-    acc += tile[threadIdx.x * kScanItems + j];
+#pragma unroll
+  for (int j = 0; j < ITEMS; j++) {
+    v[j] = acc;
+    acc += tile[lb_pad(threadIdx.x * ITEMS + j)];
   }
   int32_t tot;
-  int32_t off = block_excl_scan(acc, tot, sh);
-  int32_t add = offsets ? offsets[blockIdx.x] : 0;
-  for (int j = 0; j < kScanItems; j++) tile[threadIdx.x * kScanItems + j] = add + off + loc[j];
-  __syncthreads();
-  for (int j = 0; j < kScanItems; j++) {
-    int64_t i = base + j * kBlock + threadIdx.x;
-    if (i < count) out[i] = tile[j * kBlock + threadIdx.x];
+  const int32_t off = block_excl_scan(acc, tot, sh);
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&state[t], lb_word(epoch, t == 0 ? kLbInc : kLbAgg, (uint32_t)tot), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long ex = t > 0 ? lb_lookback(state, t, epoch, st) : 0ull;
+    if (threadIdx.x == 0) {
+      if (t > 0)
+        __hip_atomic_store(&state[t], lb_word(epoch, kLbInc, (uint32_t)(ex + (uint32_t)tot)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = (int32_t)ex;
+    }
   }
-  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = add + tot;
+  __syncthreads();
+  const int32_t add = s_excl;
+#pragma unroll
+  for (int j = 0; j < ITEMS; j++) tile[lb_pad(threadIdx.x * ITEMS + j)] = add + off + v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; j++) {
+    const int64_t i = base + j * kBlock + threadIdx.x;
+    if (i < count) out[i] = tile[lb_pad(j * kBlock + threadIdx.x)];
+  }
+  if (total && threadIdx.x == 0 && t == ntiles - 1) *total = add + tot;
+}
+
+__global__ void k_lb_clear(unsigned long long *state, int64_t words, uint32_t *ticket) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < words; i += (int64_t)gridDim.x * kBlock)
+    state[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
+}
+
+// one tile (count <= kScanTile), one workgroup; in-place capable
+__global__ void k_scan_tile(const int32_t *in, int32_t *out, int64_t count, int32_t *total) {
+  __shared__ int32_t tile[kScanTile + kScanTile / 32];
+  __shared__ int32_t sh[kBlock / 64];
+  int32_t v[kScanItems];
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    const int64_t i = j * kBlock + threadIdx.x;
+    v[j] = in[i < count ? i : count - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++)
+    tile[lb_pad(j * kBlock + threadIdx.x)] = j * kBlock + threadIdx.x < count ? v[j] : 0;
+  __syncthreads();
+  int32_t acc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    v[j] = acc;
+    acc += tile[lb_pad(threadIdx.x * kScanItems + j)];
+  }
+  int32_t tot;
+  const int32_t off = block_excl_scan(acc, tot, sh);
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) tile[lb_pad(threadIdx.x * kScanItems + j)] = off + v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    const int64_t i = j * kBlock + threadIdx.x;
+    if (i < count) out[i] = tile[lb_pad(j * kBlock + threadIdx.x)];
+  }
+  if (total && threadIdx.x == 0) *total = tot;
 }
 
 // ------------------------------------------------------------ relabel / map
@@ -1284,6 +1406,16 @@ __global__ void k_apply_ids(const int32_t *L, const int32_t *ids, int32_t n, int
     }
   }
 }
+// single solve: cl[v] = ids[L[v]] and, in the same pass, map[u] <- ids[L[map[u]]]
+// (the composed map reads the ids directly, so it need not wait for cl)
+__global__ void k_apply_compose(const int32_t *L, const int32_t *ids, int32_t n, int32_t *cl, int32_t *map,
+                                int32_t n_in) {
+  const int64_t m = n > n_in ? n : n_in;
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < m; v += (int64_t)gridDim.x * kBlock) {
+    if (v < n) cl[v] = ids[L[v]];
+    if (v < n_in) map[v] = ids[L[map[v]]];
+  }
+}
 // map[u] <- cl[map[u]]. Batched: u runs over the padded input index space
 // (64 entries per word, word -> slot in wg; padding entries hold -1), and
 // graphs out of the loop keep the map of their last level.
@@ -1307,8 +1439,8 @@ __global__ void k_iota(int32_t *p, int32_t n) {
 // ------------------------------------------------------------ contraction
 // Inter-cluster arcs, written compacted (in arc order) into the source
 // segment's own arc range of the triple buffer: segment s = tile s, or long
-// row (class 5 / 6) after the tiles. seg[2s] = first arc, seg[2s+1] = count.
-// A scan over the counts and k_compact then pack the segments.
+// row (class 4 to 6) after the tiles: first[s] = its first arc, cnt[s] = the
+// pairs written. A scan over the counts and k_compact then pack the segments.
 __device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus, const int32_t *cs, int q,
                                            int32_t i0, int32_t acnt, const int32_t *s_rp, int32_t rows,
                                            const int32_t *s_cl, int32_t cl_row, int key_bits, int64_t out0,
@@ -1366,7 +1498,8 @@ template <int NQ>
 __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                               const int32_t *__restrict__ w, const int32_t *__restrict__ cl, int4 m,
                                               int32_t t, int key_bits, unsigned long long *__restrict__ keys,
-                                              int32_t *__restrict__ vals, int32_t *__restrict__ seg,
+                                              int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                              int32_t *__restrict__ cnt,
                                               EmitTileShared &sh) {
   const int lane = threadIdx.x;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
@@ -1460,8 +1593,8 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
     }
   }
   if (lane == 0) {
-    seg[2 * (int64_t)t] = a0;
-    seg[2 * (int64_t)t + 1] = tot;
+    first[t] = a0;
+    cnt[t] = tot;
   }
   __syncthreads();
 }
@@ -1470,15 +1603,16 @@ __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ r
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
                                                        const int4 *__restrict__ meta, int32_t ntiles,
                                                        const Status *st, unsigned long long *__restrict__ keys,
-                                                       int32_t *__restrict__ vals, int32_t *__restrict__ seg) {
+                                                       int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                                       int32_t *__restrict__ cnt) {
   __shared__ EmitTileShared sh;
   const int key_bits = bits_for(st->k);
   for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
     if (m.w <= 4 * kTB)
-      emit_tile_one<4>(rp, col, w, cl, m, t, key_bits, keys, vals, seg, sh);
+      emit_tile_one<4>(rp, col, w, cl, m, t, key_bits, keys, vals, first, cnt, sh);
     else
-      emit_tile_one<kPerThread>(rp, col, w, cl, m, t, key_bits, keys, vals, seg, sh);
+      emit_tile_one<kPerThread>(rp, col, w, cl, m, t, key_bits, keys, vals, first, cnt, sh);
   }
 }
 
@@ -1487,7 +1621,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
                                                        const int32_t *list, const int32_t *cnt_p, const Status *st,
                                                        unsigned long long *__restrict__ keys,
-                                                       int32_t *__restrict__ vals, int32_t *__restrict__ seg) {
+                                                       int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                                       int32_t *__restrict__ seg_cnt) {
   __shared__ int32_t sh[kBlock / 64];
   const int key_bits = bits_for(st->k);
   const int32_t cnt = *cnt_p;
@@ -1515,8 +1650,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      seg[2 * (int64_t)r] = beg;
-      seg[2 * (int64_t)r + 1] = (int32_t)(out - beg);
+      first[r] = beg;
+      seg_cnt[r] = (int32_t)(out - beg);
     }
   }
 }
@@ -1524,7 +1659,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
 // pack the segments into buffer 1: output element e comes from the last
 // segment s with off[s] <= e (binary search of the exclusive offsets), so the
 // work is balanced whatever the segment lengths
-__global__ void k_compact(const int32_t *seg, const int32_t *off, int32_t nseg, const Status *st,
+__global__ void k_compact(const int32_t *first, const int32_t *off, int32_t nseg, const Status *st,
                           const unsigned long long *kin, const int32_t *vin, unsigned long long *kout,
                           int32_t *vout) {
   const int64_t total = st->ax;
@@ -1534,16 +1669,10 @@ __global__ void k_compact(const int32_t *seg, const int32_t *off, int32_t nseg, 
       const int32_t mid = (lo + hi + 1) >> 1;
       if (off[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    const int64_t src = seg[2 * (int64_t)lo] + (e - off[lo]);
+    const int64_t src = first[lo] + (e - off[lo]);
     kout[e] = kin[src];
     vout[e] = vin[src];
   }
-}
-
-// counts of the interleaved (first arc, count) segment table
-__global__ void k_seg_counts(const int32_t *seg, int32_t nseg, int32_t *cnt) {
-  for (int64_t s = blockIdx.x * (int64_t)kBlock + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * kBlock)
-    cnt[s] = seg[2 * s + 1];
 }
 
 // ---- LSD radix sort of (u64 key, i32 value), 8-bit digits, stable
@@ -1553,14 +1682,20 @@ constexpr int kRsTile = kBlock * kRsItems;
 __global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shift, int32_t *hist, int32_t tiles) {
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
-  __syncthreads();
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t base = blockIdx.x * (int64_t)kRsTile + (int64_t)wid * 64 * kRsItems;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (int j = 0; j < kRsItems; j++) {
+  int dg[kRsItems];
+#pragma unroll
+  for (int j = 0; j < kRsItems; j++) {  // all loads first (clamped in range), then the ranking
     const int64_t i = base + j * 64 + lane;
-    const bool ok = i < count;
-    const int d = ok ? (int)((keys[i] >> shift) & 255) : 0;
+    dg[j] = (int)((keys[i < count ? i : count - 1] >> shift) & 255);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRsItems; j++) {
+    const bool ok = base + j * 64 + lane < count;
+    const int d = ok ? dg[j] : 0;
     unsigned long long peers = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
@@ -1597,11 +1732,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long 
   unsigned long long key[kRsItems];
   int32_t val[kRsItems], rank[kRsItems], dig[kRsItems];
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int j = 0; j < kRsItems; j++) {  // all loads first (clamped in range), then the ranking
+    const int64_t i = base + j * 64 + lane;
+    const int64_t ic = i < count ? i : count - 1;
+    key[j] = kin[ic];
+    val[j] = vin[ic];
+  }
   for (int j = 0; j < kRsItems; j++) {
     const int64_t i = base + j * 64 + lane;
     const bool ok = i < count;
-    key[j] = ok ? kin[i] : 0;
-    val[j] = ok ? vin[i] : 0;
     const int d = ok ? (int)((key[j] >> shift) & 255) : 0;
     dig[j] = ok ? d : -1;
     unsigned long long peers = __ballot(ok);
@@ -2602,22 +2742,32 @@ hipError_t status_reset(Status *st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t count, int32_t *total, int32_t *tmp,
-                          size_t tmp_elems, hipStream_t s) {
+hipError_t scan_exclusive(Work &w, const int32_t *in, int32_t *out, int64_t count, int32_t *total, hipStream_t s) {
   if (count <= 0) {
     if (total) return fill_i32(total, 0, 1, s);
     return hipSuccess;
   }
-  int64_t tiles = (count + kScanTile - 1) / kScanTile;
-  if (tiles == 1) {
-    k_scan_tile<<<1, kBlock, 0, s>>>(in, out, count, nullptr, total);
+  if (count <= kScanTile) {
+    k_scan_tile<<<1, kBlock, 0, s>>>(in, out, count, total);
     return hipGetLastError();
   }
-  if ((size_t)tiles > tmp_elems) return hipErrorInvalidValue;
-  k_scan_reduce<<<(unsigned)tiles, kBlock, 0, s>>>(in, count, tmp);
-  hipError_t e = scan_exclusive(tmp, tmp, tiles, nullptr, tmp + tiles, tmp_elems - tiles, s);
-  if (e != hipSuccess) return e;
-  k_scan_tile<<<(unsigned)tiles, kBlock, 0, s>>>(in, out, count, tmp, total);
+  // small scans: 2048-element tiles; larger ones: 8192, which keeps the
+  // look-back at a few windows of 64 predecessors
+  const bool big = count > 64ll * kScanTile;
+  const int64_t tile = big ? 4 * kScanTile : kScanTile;
+  const int64_t tiles = (count + tile - 1) / tile;
+  if (tiles > w.lb_tiles) return hipErrorInvalidValue;
+  if (w.lb_epoch == 0 || w.lb_epoch + 1 >= (1u << 30)) {
+    k_lb_clear<<<grid_for(w.lb_tiles, kBlock, 256), kBlock, 0, s>>>(w.lb_state, w.lb_tiles, w.lb_ticket);
+    w.lb_epoch = 0;
+  }
+  w.lb_epoch++;
+  if (big)
+    k_scan_lb<4 * kScanItems><<<(unsigned)tiles, kBlock, 0, s>>>(in, out, count, total, w.lb_state, w.lb_ticket,
+                                                                 w.lb_epoch, (int32_t)tiles, w.st);
+  else
+    k_scan_lb<kScanItems><<<(unsigned)tiles, kBlock, 0, s>>>(in, out, count, total, w.lb_state, w.lb_ticket,
+                                                             w.lb_epoch, (int32_t)tiles, w.st);
   return hipGetLastError();
 }
 
@@ -2637,6 +2787,11 @@ namespace {
 // items of bin b: host-known count (>= 0) or -1 when only the device knows it
 inline int64_t bin_items(const int32_t *known, int b, int64_t fallback) { return known ? known[b] : fallback; }
 inline int64_t long_rows_bound(const DGraph &g) { return g.nnz / kTile + 1; }
+// grid of a per-row launch: sized to the rows when the host knows them, else
+// about one resident wave per SIMD slot (the kernels stride over the list)
+inline unsigned rows_grid(int64_t items, int per_block, const int32_t *known) {
+  return grid_for(items, per_block, known ? 8192u : 2048u);
+}
 
 template <int G>
 void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t *L, uint32_t salt, int level0,
@@ -2644,7 +2799,7 @@ void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t
   const int64_t items = bin_items(known, b, g.n);
   if (items <= 0) return;
   const int32_t *list = w.bins + (int64_t)b * w.n_in;
-  k_lp_first<G><<<grid_for(items, kBlock / G, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
+  k_lp_first<G><<<rows_grid(items, kBlock / G, known), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
                                                                     &w.st->bin_cnt[b], L, w.deg, salt, level0,
                                                                     w.st);
 }
@@ -2654,10 +2809,23 @@ void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int
   const int64_t items = bin_items(known, b, long_rows_bound(g));
   if (items <= 0) return;
   const int32_t *list = w.bins + (int64_t)b * w.n_in;
-  k_lp_tab<G, TBL><<<grid_for(items, kBlock / G, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, list,
+  k_lp_tab<G, TBL><<<rows_grid(items, kBlock / G, known), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, list,
                                                                        &w.st->bin_cnt[b], salt, w.st, gv, gs);
 }
 }  // namespace
+
+// Grid of a persistent kernel: as many workgroups as fit on the device at
+// once (at least one), capped by the work items.
+template <class K>
+unsigned resident_grid(K kernel, int block, int64_t items) {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    per_cu = cus = 1;
+  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)std::max(per_cu, 1) * std::max(cus, 1)));
+  return (unsigned)g;
+}
 
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
                     hipStream_t s, const BatchView *bv) {
@@ -2688,7 +2856,7 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
     if (items > 0) {
       const int32_t *list = w.bins + (int64_t)b * w.n_in;
-      k_lp_first<64><<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
+      k_lp_first<64><<<rows_grid(items, kBlock / 64, known), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
                                                                           &w.st->bin_cnt[b], L, w.deg, salt, l0,
                                                                           w.st, gv, gs);
     }
@@ -2707,18 +2875,6 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   return hipGetLastError();
 }
 
-// Grid of a persistent kernel: as many workgroups as fit on the device at
-// once (at least one), capped by the work items.
-template <class K>
-unsigned resident_grid(K kernel, int block, int64_t items) {
-  int dev = 0, per_cu = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    per_cu = cus = 1;
-  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)std::max(per_cu, 1) * std::max(cus, 1)));
-  return (unsigned)g;
-}
 
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
                    hipStream_t s, const BatchView *bv) {
@@ -2768,14 +2924,13 @@ hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const Ba
   if (e != hipSuccess) return e;
   k_flag_labels<<<grid_for(n), kBlock, 0, s>>>(L, n, w.ids, gv, gs);
   // batched: ids[n] = total too, the end of the last graph's range
-  e = scan_exclusive(w.ids, w.ids, bv ? (int64_t)n + 1 : n, &w.st->k, w.scan_tmp, w.scan_tmp_elems, s);
+  e = scan_exclusive(w, w.ids, w.ids, bv ? (int64_t)n + 1 : n, &w.st->k, s);
   if (e != hipSuccess) return e;
-  k_apply_ids<<<grid_for(n), kBlock, 0, s>>>(L, w.ids, n, w.cl, gv, gs, gv_new);
-  return hipGetLastError();
-}
-
-hipError_t compose_map(Work &w, hipStream_t s) {
-  k_compose<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.cl, w.n_in, nullptr, nullptr);
+  if (bv) {
+    k_apply_ids<<<grid_for(n), kBlock, 0, s>>>(L, w.ids, n, w.cl, gv, gs, gv_new);
+  } else {
+    k_apply_compose<<<grid_for(std::max(n, w.n_in)), kBlock, 0, s>>>(L, w.ids, n, w.cl, w.map, w.n_in);
+  }
   return hipGetLastError();
 }
 
@@ -2787,19 +2942,20 @@ hipError_t init_map(Work &w, hipStream_t s) {
 hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s) {
   const int64_t long_max = g.nnz / kTile + 1;
   const int64_t nseg = w.ntiles + 3 * long_max;
-  hipError_t e = fill_i32(w.seg + 2ll * w.ntiles, 0, 6 * long_max, s);
+  // long-row segments beyond the device-side row counts stay empty
+  hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, 3 * long_max, s);
   if (e != hipSuccess) return e;
   k_emit_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles,
-                                                                 w.st, w.keys[0], w.vals[0], w.seg);
+                                                                 w.st, w.keys[0], w.vals[0], w.seg, w.seg_cnt);
   for (int b = 4; b <= 6; b++) {
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;
-    int32_t *seg = w.seg + 2 * (w.ntiles + (b - 4) * long_max);
+    const int64_t s0 = w.ntiles + (b - 4) * long_max;
     k_emit_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in,
-                                                            &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0], seg);
+                                                            &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0],
+                                                            w.seg + s0, w.seg_cnt + s0);
   }
-  k_seg_counts<<<grid_for(nseg), kBlock, 0, s>>>(w.seg, (int32_t)nseg, w.seg_cnt);
-  e = scan_exclusive(w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, w.scan_tmp, w.scan_tmp_elems, s);
+  e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
   if (e != hipSuccess) return e;
   k_compact<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st, w.keys[0],
                                                               w.vals[0], w.keys[1], w.vals[1]);
@@ -2811,7 +2967,7 @@ hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStr
   const int32_t tiles = (int32_t)((count + kRsTile - 1) / kRsTile);
   for (int shift = 0; shift < total_bits; shift += 8) {
     k_rs_hist<<<tiles, kBlock, 0, s>>>(w.keys[which], count, shift, w.hist, tiles);
-    hipError_t e = scan_exclusive(w.hist, w.hist, 256ll * tiles, nullptr, w.scan_tmp, w.scan_tmp_elems, s);
+    hipError_t e = scan_exclusive(w, w.hist, w.hist, 256ll * tiles, nullptr, s);
     if (e != hipSuccess) return e;
     k_rs_scatter<<<tiles, kBlock, 0, s>>>(w.keys[which], w.vals[which], w.keys[which ^ 1], w.vals[which ^ 1], count,
                                           shift, w.hist, tiles);
@@ -2833,7 +2989,7 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
   if (e != hipSuccess) return e;
   if (count > 0) {
     k_seg_heads<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], count, head);
-    e = scan_exclusive(head, seg, count, &w.st->nnz, w.scan_tmp, w.scan_tmp_elems, s);
+    e = scan_exclusive(w, head, seg, count, &w.st->nnz, s);
     if (e != hipSuccess) return e;
     k_seg_write<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], w.vals[which], count, seg, head, key_bits,
                                                    w.col[dst], w.w[dst], rowcnt, degu);
@@ -2841,7 +2997,7 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
     e = fill_i32(&w.st->nnz, 0, 1, s);
     if (e != hipSuccess) return e;
   }
-  e = scan_exclusive(rowcnt, rowcnt, (int64_t)k + 1, nullptr, w.scan_tmp, w.scan_tmp_elems, s);
+  e = scan_exclusive(w, rowcnt, rowcnt, (int64_t)k + 1, nullptr, s);
   if (e != hipSuccess) return e;
   if (!single_bound) return hipGetLastError();
   k_set_minkey<<<1, 64, 0, s>>>(w.st);

@@ -280,6 +280,38 @@ __global__ void k_long_rows(const int32_t *rp, int32_t n, int64_t stride, int32_
   }
 }
 
+// ------------------------------------------------------------ XCD-aware tile order
+// Workgroup i runs on XCD i mod 8, and each XCD has its own L2. With many
+// tiles, they are dealt to the XCDs in chunks of 64 consecutive tiles (chunk
+// c to XCD c mod 8), and the workgroups of an XCD walk its chunks in order:
+// the neighbour-label gathers of a tile, which mostly hit ids close to its
+// own rows in locality-ordered inputs, then find lines that the XCD's L2
+// already holds for the neighbouring tiles, while at least 32 chunks per XCD
+// keep the work balanced on skewed inputs. Fewer tiles are dealt one by one.
+// Launches use grids that are multiples of 8.
+constexpr int kXcds = 8;
+constexpr int kXcdChunkLog = 6;
+constexpr int32_t kXcdChunkMin = kXcds * 32 << kXcdChunkLog;  // tiles for chunked dealing
+struct XcdWalk {
+  int32_t x, l, step, ntiles, cl;
+  __device__ __forceinline__ explicit XcdWalk(int32_t n) : ntiles(n) {
+    x = (int32_t)(blockIdx.x % kXcds);
+    l = (int32_t)(blockIdx.x / kXcds);
+    step = (int32_t)(gridDim.x / kXcds);
+    cl = n >= kXcdChunkMin ? kXcdChunkLog : 0;
+  }
+  // increasing in l, so the walk ends at the first tile past the range
+  __device__ __forceinline__ int32_t tile() const {
+    return (((l >> cl) * kXcds + x) << cl) + (l & ((1 << cl) - 1));
+  }
+  __device__ __forceinline__ bool ok() const { return tile() < ntiles; }
+  __device__ __forceinline__ void next() { l += step; }
+};
+
+// Per-lane loops over a long row load kLoadBatch arcs (and their gathers)
+// before using any of them, so that one memory latency covers the batch.
+constexpr int kLoadBatch = 8;
+
 // ------------------------------------------------------------ LP iteration 1
 // Identity labels: S(x) = w(v, x), so the new label is the row's argmax of
 // (w, -prio). At level 0 the same pass validates the row and computes the
@@ -312,15 +344,26 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
     }
     unsigned long long best = 0, sum = 0;
     int err = 0;
-    for (int32_t i = beg + lane; i < end; i += G) {
-      int32_t x = col[i], c = w[i];
-      if (level0) {
-        if (x < 0 || x >= n) err |= ERR_COL;
-        if (x == v) err |= ERR_SELF;
-        if (c < 1) err |= ERR_WEIGHT;
+    for (int32_t i0 = beg + lane; i0 < end; i0 += G * kLoadBatch) {
+      int32_t xs[kLoadBatch], cs[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {  // the batch's loads first (clamped into the row)
+        const int32_t i = min(i0 + u * G, end - 1);
+        xs[u] = col[i];
+        cs[u] = w[i];
       }
-      sum += (unsigned long long)(uint32_t)c;
-      best = umax64(best, cand_key((uint32_t)c, x - b0, sl));
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {
+        if (i0 + u * G >= end) break;
+        const int32_t x = xs[u], c = cs[u];
+        if (level0) {
+          if (x < 0 || x >= n) err |= ERR_COL;
+          if (x == v) err |= ERR_SELF;
+          if (c < 1) err |= ERR_WEIGHT;
+        }
+        sum += (unsigned long long)(uint32_t)c;
+        best = umax64(best, cand_key((uint32_t)c, x - b0, sl));
+      }
     }
     best = grp_max<G>(best);
     sum = grp_sum<G>(sum);
@@ -382,20 +425,32 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
     }
     if (lane == 0) own_sh[gi] = 0;
     __syncthreads();
-    for (int32_t i = beg + lane; i < end; i += G) {
-      int32_t x = Lin[col[i]];
-      uint32_t c = (uint32_t)w[i];
-      uint32_t h = slot_hash(x) & (TBL - 1);
-      while (true) {
-        int32_t k = tkey[gi][h];
-        if (k == x) break;
-        if (k == -1) {
-          int32_t old = atomicCAS(&tkey[gi][h], -1, x);
-          if (old == -1 || old == x) break;
-        }
-        h = (h + 1) & (TBL - 1);
+    for (int32_t i0 = beg + lane; i0 < end; i0 += G * kLoadBatch) {
+      int32_t xs[kLoadBatch], cs[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {  // the batch's loads and gathers first
+        const int32_t i = min(i0 + u * G, end - 1);
+        xs[u] = col[i];
+        cs[u] = w[i];
       }
-      atomicAdd(&tval[gi][h], c);
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) xs[u] = Lin[xs[u]];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {
+        if (i0 + u * G >= end) break;
+        const int32_t x = xs[u];
+        uint32_t h = slot_hash(x) & (TBL - 1);
+        while (true) {
+          int32_t k = tkey[gi][h];
+          if (k == x) break;
+          if (k == -1) {
+            int32_t old = atomicCAS(&tkey[gi][h], -1, x);
+            if (old == -1 || old == x) break;
+          }
+          h = (h + 1) & (TBL - 1);
+        }
+        atomicAdd(&tval[gi][h], (uint32_t)cs[u]);
+      }
     }
     __syncthreads();
     unsigned long long best = 0;
@@ -826,32 +881,30 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
   __shared__ uint32_t s_salt[B ? kTile : 1];
   if (!B && st->err) return;
   constexpr int32_t kSmall = 4 * kTB;
-  const int32_t G = (int32_t)gridDim.x;
-  // this workgroup's next small tile at or after t
-  auto next_small = [&](int32_t t, int4 &m) {
-    for (; t < ntiles; t += G) {
-      m = meta[t];
-      if (m.w <= kSmall) break;
+  XcdWalk xw(ntiles);
+  // this workgroup's next small tile from the walk's position on (-1: none)
+  auto next_small = [&](int4 &m) {
+    for (; xw.ok(); xw.next()) {
+      m = meta[xw.tile()];
+      if (m.w <= kSmall) return xw.tile();
     }
-    return t;
+    return (int32_t)-1;
   };
   int4 m;
-  int32_t t = next_small((int32_t)blockIdx.x, m);
-  if (t >= ntiles) return;
+  if (next_small(m) < 0) return;
   LpFetch<B, 4> cur;
   lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
   lp_fetch_gather(cur, Lin);
   while (true) {
     int4 mn = make_int4(0, 0, 0, 0);
-    const int32_t tn = next_small(t + G, mn);
-    const bool more = tn < ntiles;
+    xw.next();
+    const bool more = next_small(mn) >= 0;
     LpFetch<B, 4> nxt;
     if (more) lp_fetch_loads(nxt, mn, rp, col, w, Lin, gv, gs);
     lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, [&]() {
       if (more) lp_fetch_gather(nxt, Lin);
     });
     if (!more) break;
-    t = tn;
     cur = nxt;
   }
 }
@@ -986,15 +1039,26 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
     }
     unsigned long long b = 0, sum = 0;
     int err = 0;
-    for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
-      int32_t x = col[a], c = w[a];
-      if (mode == 2) {
-        if (x < 0 || x >= n) err |= ERR_COL;
-        if (x == v) err |= ERR_SELF;
-        if (c < 1) err |= ERR_WEIGHT;
+    for (int32_t a0 = beg + threadIdx.x; a0 < end; a0 += kBlock * kLoadBatch) {
+      int32_t xs[kLoadBatch], cs[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {
+        const int32_t a = min(a0 + u * kBlock, end - 1);
+        xs[u] = col[a];
+        cs[u] = w[a];
       }
-      sum += (unsigned long long)(uint32_t)c;
-      b = umax64(b, cand_key((uint32_t)c, x - b0, sl));
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {
+        if (a0 + u * kBlock >= end) break;
+        const int32_t x = xs[u], c = cs[u];
+        if (mode == 2) {
+          if (x < 0 || x >= n) err |= ERR_COL;
+          if (x == v) err |= ERR_SELF;
+          if (c < 1) err |= ERR_WEIGHT;
+        }
+        sum += (unsigned long long)(uint32_t)c;
+        b = umax64(b, cand_key((uint32_t)c, x - b0, sl));
+      }
     }
     b = block_max(b, sh);
     sum = block_sum(sum, sh);
@@ -1042,34 +1106,53 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
       lv[e] = 0;
     }
     __syncthreads();
-    for (int32_t a = beg + threadIdx.x; a < end; a += kBlock) {
-      const int32_t x = Lin[col[a]];
-      uint32_t h = slot_hash(x) & lmask;
-      while (true) {
-        const int32_t old = atomicCAS(&lk[h], -1, x);
-        if (old == -1 || old == x) break;
-        h = (h + 1) & lmask;
+    for (int32_t a0 = beg + threadIdx.x; a0 < end; a0 += kBlock * kLoadBatch) {
+      int32_t xs[kLoadBatch], cs[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {
+        const int32_t a = min(a0 + u * kBlock, end - 1);
+        xs[u] = col[a];
+        cs[u] = w[a];
       }
-      atomicAdd(&lv[h], (uint32_t)w[a]);
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) xs[u] = Lin[xs[u]];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {
+        if (a0 + u * kBlock >= end) break;
+        const int32_t x = xs[u];
+        uint32_t h = slot_hash(x) & lmask;
+        while (true) {
+          const int32_t old = atomicCAS(&lk[h], -1, x);
+          if (old == -1 || old == x) break;
+          h = (h + 1) & lmask;
+        }
+        atomicAdd(&lv[h], (uint32_t)cs[u]);
+      }
     }
     __syncthreads();
     int32_t *K = tk + meta[3 * (int64_t)i + 1];
     uint32_t *V = tv + meta[3 * (int64_t)i + 1];
     const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
-    for (int e = threadIdx.x; e < kHugeLocal; e += kBlock) {
-      const int32_t x = lk[e];
-      if (x < 0) continue;
-      uint32_t h = slot_hash(x) & mask;
-      while (true) {
-        const int32_t k = __hip_atomic_load(&K[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (k == x) break;
-        if (k == -1) {
-          const int32_t old = atomicCAS(&K[h], -1, x);
-          if (old == -1 || old == x) break;
-        }
-        h = (h + 1) & mask;
+    // one insertion per distinct label; a thread's first probes are all in
+    // flight before any of their results is looked at
+    constexpr int kPer = kHugeLocal / kBlock;
+    int32_t xs[kPer], old[kPer];
+    uint32_t hs[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      xs[u] = lk[u * kBlock + threadIdx.x];
+      hs[u] = slot_hash(xs[u]) & mask;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; u++) old[u] = xs[u] >= 0 ? atomicCAS(&K[hs[u]], -1, xs[u]) : -1;
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      if (xs[u] < 0) continue;
+      while (old[u] != -1 && old[u] != xs[u]) {  // taken by another label: probe on
+        hs[u] = (hs[u] + 1) & mask;
+        old[u] = atomicCAS(&K[hs[u]], -1, xs[u]);
       }
-      atomicAdd(&V[h], lv[e]);
+      atomicAdd(&V[hs[u]], lv[u * kBlock + threadIdx.x]);
     }
     __syncthreads();
   }
@@ -1636,14 +1719,13 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
       const int32_t i0 = threadIdx.x * kPerThread;
       int32_t cus[kPerThread], cs[kPerThread];
 #pragma unroll
-      for (int k = 0; k < kPerThread; k++) {
-        const bool ok = i0 + k < acnt;
-        cus[k] = ok ? col[c0 + i0 + k] : 0;
-        cs[k] = ok ? w[c0 + i0 + k] : 0;
+      for (int k = 0; k < kPerThread; k++) {  // clamped loads, all issued before use
+        const int32_t a = c0 + min(i0 + k, acnt - 1);
+        cus[k] = col[a];
+        cs[k] = w[a];
       }
 #pragma unroll
-      for (int k = 0; k < kPerThread; k++)
-        if (i0 + k < acnt) cus[k] = cl[cus[k]];
+      for (int k = 0; k < kPerThread; k++) cus[k] = cl[cus[k]];
       int32_t tot;
       emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, key_bits, out, keys, vals, sh, tot);
       out += tot;
@@ -1970,7 +2052,8 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
   __shared__ int32_t s_g[B ? kTile : 1];
   const long long lam0 = B ? 0 : st->lam_hat;
   int32_t flagged = -1;
-  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (XcdWalk xw(ntiles); xw.ok(); xw.next()) {
+    const int32_t t = xw.tile();
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
     const int32_t q = (acnt + kTB - 1) / kTB;
@@ -2328,7 +2411,8 @@ __global__ void k_uf_tile(const int32_t *__restrict__ rp, const int32_t *__restr
                           const uint8_t *__restrict__ mark, const int4 *__restrict__ meta, int32_t ntiles,
                           int32_t *parent) {
   __shared__ int32_t s_rp[kTile + 1];
-  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (XcdWalk xw(ntiles); xw.ok(); xw.next()) {
+    const int32_t t = xw.tile();
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
     const int32_t q = (acnt + kTB - 1) / kTB;
@@ -2721,6 +2805,9 @@ __global__ void k_side_batch(const SideDesc *d, int32_t count, int32_t words, co
   }
 }
 
+// grid of a tile kernel walking XcdWalk: a multiple of the XCD count
+inline unsigned xcd_grid(unsigned g) { return (g + kXcds - 1) / kXcds * kXcds; }
+
 inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 8192) {
   int64_t g = (items + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -2883,12 +2970,12 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
     if (bv) {
-      k_lp_tile<true><<<resident_grid(k_lp_tile<true>, kTB, w.ntiles), kTB, 0, s>>>(
+      k_lp_tile<true><<<xcd_grid(resident_grid(k_lp_tile<true>, kTB, w.ntiles)), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs);
       k_lp_tile_big<true><<<resident_grid(k_lp_tile_big<true>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, gv, gs);
     } else {
-      k_lp_tile<false><<<resident_grid(k_lp_tile<false>, kTB, w.ntiles), kTB, 0, s>>>(
+      k_lp_tile<false><<<xcd_grid(resident_grid(k_lp_tile<false>, kTB, w.ntiles)), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr);
       k_lp_tile_big<false><<<resident_grid(k_lp_tile_big<false>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);
@@ -3028,7 +3115,7 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   const unsigned long long *degu = (const unsigned long long *)w.deg;
   int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
   int32_t *list = w.parent;               // free until the union-find
-  const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
+  const unsigned tg = xcd_grid(grid_for(w.ntiles, 1, 1u << 20));
   if (bv)
     k_pr_tile<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv, gs);
   else
@@ -3058,7 +3145,7 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
 
 hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s) {
   k_iota<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n);
-  k_uf_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, w.mark, w.tile_meta, w.ntiles,
+  k_uf_tile<<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(g.row_ptr, g.col, w.mark, w.tile_meta, w.ntiles,
                                                                w.parent);
   for (int b = 4; b <= 6; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;

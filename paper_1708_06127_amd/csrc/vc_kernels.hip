@@ -662,15 +662,19 @@ __device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8)
 }
 
 // LDS of one tile whose threads take NQ arcs each: the hash table holds two
-// slots per arc of the tile, plus a sink slot per lane.
+// slots per arc of the tile.
 template <int NQ>
 struct LpTileShared {
   static constexpr int kSlots = 2 * NQ * kTB;
   int32_t rp[kTile + 1];
   int32_t own[kTile];
-  unsigned long long best[kTile + kTB];  // + a sink per lane
-  int32_t tkey[kSlots + kTB];
-  uint32_t tval[kSlots + kTB];
+  // 8-arc tiles: a sink slot per lane takes the updates of inactive lanes
+  // (no branches); the 4-arc kernel masks them instead and keeps its LDS
+  // small enough for more resident workgroups
+  static constexpr int kSinks = NQ == kPerThread ? kTB : 0;
+  unsigned long long best[kTile + kSinks];
+  int32_t tkey[kSlots + kSinks];
+  uint32_t tval[kSlots + kSinks];
   unsigned long long row8[kTileArcs / 8];
 };
 
@@ -739,7 +743,6 @@ __device__ __forceinline__ void lp_fetch_gather(LpFetch<B, NQ> &f, const int32_t
 template <bool B, int NQ, class Hook>
 __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__restrict__ Lout, uint32_t salt,
                                             LpTileShared<NQ> &sh, int32_t *s_base, uint32_t *s_salt, Hook hook) {
-  constexpr int kSink = LpTileShared<NQ>::kSlots;
   const int lane = threadIdx.x;
   const int32_t r0 = f.m.x, rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
   const int32_t q = (acnt + kTB - 1) / kTB;
@@ -812,7 +815,10 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       hh[k] = region_slot(f.xs[k], (uint32_t)hsz[k]);
-      old[k] = atomicCAS(&sh.tkey[ok[k] ? hb[k] + (int32_t)hh[k] : kSink + lane], -1, f.xs[k]);
+      if constexpr (LpTileShared<NQ>::kSinks > 0)
+        old[k] = atomicCAS(&sh.tkey[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane], -1, f.xs[k]);
+      else
+        old[k] = ok[k] ? atomicCAS(&sh.tkey[hb[k] + (int32_t)hh[k]], -1, f.xs[k]) : -1;
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
@@ -831,7 +837,10 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
     unsigned long long key[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; k++)
-      old[k] = (int32_t)atomicAdd(&sh.tval[ok[k] ? hb[k] + (int32_t)hh[k] : kSink + lane], cc[k]);
+      if constexpr (LpTileShared<NQ>::kSinks > 0)
+        old[k] = (int32_t)atomicAdd(&sh.tval[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane], cc[k]);
+      else
+        old[k] = ok[k] ? (int32_t)atomicAdd(&sh.tval[hb[k] + (int32_t)hh[k]], cc[k]) : 0;
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       const uint32_t S = (uint32_t)old[k] + cc[k];
@@ -848,7 +857,12 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
         head[k] = false;
       }
 #pragma unroll
-    for (int k = 0; k < NQ; k++) atomicMax(&sh.best[head[k] ? rw[k] : kTile + lane], key[k]);
+    for (int k = 0; k < NQ; k++) {
+      if constexpr (LpTileShared<NQ>::kSinks > 0)
+        atomicMax(&sh.best[head[k] ? rw[k] : kTile + lane], key[k]);
+      else if (head[k])
+        atomicMax(&sh.best[rw[k]], key[k]);
+    }
   }
   hook();
   __syncthreads();
@@ -864,12 +878,11 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
   __syncthreads();
 }
 
-// Persistent: workgroup b takes the tiles b, b + G, b + 2G, ... (G = grid
-// size) of at most 4 * 64 arcs, 4 arcs per thread. The next tile's arcs and
-// row data are loaded before this tile's LDS phases and its label gathers are
-// issued after this tile's table updates, so the memory latency of one tile
-// overlaps the LDS work of the previous one. The tiles of more than 256 arcs
-// are left to k_lp_tile_big.
+// The tiles of at most 4 * 64 arcs, 4 arcs per thread, one tile per
+// workgroup in the XCD-aware order (the hardware keeps enough of these small
+// workgroups in flight to hide the load latency, which measured faster than
+// a persistent loop with the next tile's loads in flight). The tiles of more
+// than 256 arcs are left to k_lp_tile_big.
 template <bool B>
 __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
@@ -890,27 +903,19 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
     }
     return (int32_t)-1;
   };
-  int4 m;
-  if (next_small(m) < 0) return;
-  LpFetch<B, 4> cur;
-  lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
-  lp_fetch_gather(cur, Lin);
-  while (true) {
-    int4 mn = make_int4(0, 0, 0, 0);
-    xw.next();
-    const bool more = next_small(mn) >= 0;
-    LpFetch<B, 4> nxt;
-    if (more) lp_fetch_loads(nxt, mn, rp, col, w, Lin, gv, gs);
-    lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, [&]() {
-      if (more) lp_fetch_gather(nxt, Lin);
-    });
-    if (!more) break;
-    cur = nxt;
+  for (int4 m; next_small(m) >= 0; xw.next()) {
+    LpFetch<B, 4> cur;
+    lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
+    lp_fetch_gather(cur, Lin);
+    lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, []() {});
   }
 }
 
-// The listed tiles of more than 256 arcs, 8 arcs per thread, pipelined the
-// same way over the list.
+// The listed tiles of more than 256 arcs, 8 arcs per thread. Persistent
+// (as many workgroups as fit, striding over the list): the next tile's arcs
+// and row data are loaded before this tile's LDS phases and its label
+// gathers are issued after this tile's table updates, so the memory latency
+// of one tile overlaps the LDS work of the previous one.
 template <bool B>
 __global__ __launch_bounds__(kTB) void k_lp_tile_big(const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
@@ -2970,12 +2975,12 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
     if (bv) {
-      k_lp_tile<true><<<xcd_grid(resident_grid(k_lp_tile<true>, kTB, w.ntiles)), kTB, 0, s>>>(
+      k_lp_tile<true><<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs);
       k_lp_tile_big<true><<<resident_grid(k_lp_tile_big<true>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, gv, gs);
     } else {
-      k_lp_tile<false><<<xcd_grid(resident_grid(k_lp_tile<false>, kTB, w.ntiles)), kTB, 0, s>>>(
+      k_lp_tile<false><<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr);
       k_lp_tile_big<false><<<resident_grid(k_lp_tile_big<false>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);

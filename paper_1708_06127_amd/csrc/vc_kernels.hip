@@ -1577,8 +1577,8 @@ constexpr unsigned long long kNoPair = ~0ull;
 struct EmitTileShared {
   int32_t rp[kTile + 1];
   int32_t cl[kTile];
-  unsigned long long tkey[kCombSlots + kTB];  // + a sink per lane
-  uint32_t tval[kCombSlots + kTB];
+  unsigned long long tkey[kCombSlots];
+  uint32_t tval[kCombSlots];
   unsigned long long row8[kTileArcs / 8];
 };
 
@@ -1648,7 +1648,7 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
     for (int k = 0; k < NQ; k++) {
       const uint32_t fold = (uint32_t)key[k] ^ (uint32_t)(key[k] >> 32);
       hh[k] = (fold * 2654435761u) & (kCombSlots - 1);
-      old[k] = atomicCAS(&sh.tkey[ok[k] ? (int32_t)hh[k] : kCombSlots + lane], kNoPair, key[k]);
+      old[k] = ok[k] ? atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]) : kNoPair;
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
@@ -1659,7 +1659,8 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
       }
     }
 #pragma unroll
-    for (int k = 0; k < NQ; k++) atomicAdd(&sh.tval[ok[k] ? (int32_t)hh[k] : kCombSlots + lane], cc[k]);
+    for (int k = 0; k < NQ; k++)
+      if (ok[k]) atomicAdd(&sh.tval[hh[k]], cc[k]);
   }
   __syncthreads();
   // write the distinct pairs into the tile's region, in slot order

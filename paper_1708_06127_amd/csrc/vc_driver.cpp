@@ -133,7 +133,7 @@ int64_t scan_tiles_max(int64_t count) { return (count + 2047) / 2048 + 1; }
 // rows of the gather staging beyond n (one per graph in a batch).
 Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   Layout L;
-  const int64_t tiles = (nnz + 4095) / 4096 + 1;
+  const int64_t tiles = (nnz + kRsTile - 1) / kRsTile + 1;
   const int64_t huge_rows = nnz / (kHugeChunk + 1) + 1;
   const int64_t ntiles = (nnz + n) / kTile + 2;
   const int64_t nseg = ntiles + 3 * (nnz / kTile + 1) + 2;
@@ -208,7 +208,7 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
   w.vals[1] = (int32_t *)at(19);
   w.hist = (int32_t *)at(20);
   {
-    const int64_t tiles = (nnz + 4095) / 4096 + 1;
+    const int64_t tiles = (nnz + kRsTile - 1) / kRsTile + 1;
     const int64_t nseg = (nnz + n) / kTile + 2 + 3 * (nnz / kTile + 1) + 2;
     w.lb_tiles = scan_tiles_max(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg}));
     w.lb_state = (unsigned long long *)at(21);

@@ -19,6 +19,7 @@ constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
 // hold at most kTile rows and fewer than 2*kTile arcs.
 constexpr int kTB = 64;       // threads of a tile workgroup (one wave: barriers are cheap)
 constexpr int kTile = 256;
+constexpr int kRsTile = 1024;  // elements per workgroup of a radix sort pass
 constexpr int kTileArcs = 2 * kTile;
 constexpr int kPerThread = kTileArcs / kTB;  // up to 8 consecutive arcs per thread
 

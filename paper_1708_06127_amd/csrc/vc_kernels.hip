@@ -1764,8 +1764,7 @@ __global__ void k_compact(const int32_t *first, const int32_t *off, int32_t nseg
 }
 
 // ---- LSD radix sort of (u64 key, i32 value), 8-bit digits, stable
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kBlock * kRsItems;
+constexpr int kRsItems = kRsTile / kBlock;
 
 __global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shift, int32_t *hist, int32_t tiles) {
   __shared__ int32_t h[256];
@@ -2844,9 +2843,10 @@ hipError_t scan_exclusive(Work &w, const int32_t *in, int32_t *out, int64_t coun
     k_scan_tile<<<1, kBlock, 0, s>>>(in, out, count, total);
     return hipGetLastError();
   }
-  // small scans: 2048-element tiles; larger ones: 8192, which keeps the
-  // look-back at a few windows of 64 predecessors
-  const bool big = count > 64ll * kScanTile;
+  // up to 256 tiles of 2048 elements (at most 4 look-back windows of 64
+  // predecessors); longer arrays: 8192-element tiles, which keeps the
+  // look-back at a few windows
+  const bool big = count > 256ll * kScanTile;
   const int64_t tile = big ? 4 * kScanTile : kScanTile;
   const int64_t tiles = (count + tile - 1) / tile;
   if (tiles > w.lb_tiles) return hipErrorInvalidValue;

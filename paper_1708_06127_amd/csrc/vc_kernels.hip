@@ -2020,38 +2020,56 @@ __device__ __forceinline__ void flag_marked(GStat *gs, int32_t g, int32_t &flagg
     atomicExch(&gs[g].nmarked, 1);
 }
 
-// conditions 3 and 4 by merging two short sorted rows
-__device__ bool pr_merge(const int32_t *col, const int32_t *w, int32_t vb, int32_t ve, int32_t xb, int32_t xe,
+// conditions 3 and 4 for the owned arc (v, x) of a short row: v's sorted row
+// is in LDS ([vb, ve) of s_col / s_w), x's row (not longer) is read from
+// global memory 8 entries at a time, all loads first, and each entry is
+// looked up in v's row by binary search. The decision does not depend on the
+// order in which the common neighbours are met.
+__device__ bool pr_probe(const int32_t *s_col, const int32_t *s_w, int32_t vb, int32_t ve,
+                         const int32_t *__restrict__ col, const int32_t *__restrict__ w, int32_t xb, int32_t xe,
                          long long c, long long dv, long long dx, long long lam) {
   long long sum4 = c;
-  int32_t i = vb, j = xb;
-  while (i < ve && j < xe) {
-    const int32_t a = col[i], b = col[j];
-    if (a < b) {
-      i++;
-    } else if (b < a) {
-      j++;
-    } else {
-      const long long cvu = w[i], cxu = w[j];
-      if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
-      sum4 += cvu < cxu ? cvu : cxu;
-      if (sum4 >= lam) return true;
-      i++;
-      j++;
+  for (int32_t j0 = xb; j0 < xe; j0 += kLoadBatch) {
+    int32_t us[kLoadBatch], cx[kLoadBatch];
+#pragma unroll
+    for (int k = 0; k < kLoadBatch; k++) {
+      const int32_t jj = min(j0 + k, xe - 1);
+      us[k] = col[jj];
+      cx[k] = w[jj];
+    }
+#pragma unroll
+    for (int k = 0; k < kLoadBatch; k++) {
+      if (j0 + k >= xe) break;
+      int32_t lo = vb, hi = ve;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_col[mid] < us[k]) lo = mid + 1; else hi = mid;
+      }
+      if (lo < ve && s_col[lo] == us[k]) {
+        const long long cvu = s_w[lo], cxu = cx[k];
+        if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
+        sum4 += cvu < cxu ? cvu : cxu;
+        if (sum4 >= lam) return true;
+      }
     }
   }
   return sum4 >= lam;
 }
 
 // Short rows on the tiles. Rows of kPrRow arcs or more are left to k_pr_rows.
+// The PR graphs are the small coarse ones, so a tile takes a whole workgroup
+// of kPrTB threads (at most 2 arcs each) to keep enough waves in flight.
+constexpr int kPrTB = kBlock;
+constexpr int kPrPer = kTileArcs / kPrTB;
 template <bool B>
-__global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kPrTB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w,
                                                      const unsigned long long *__restrict__ degu,
                                                      const int4 *__restrict__ meta, int32_t ntiles,
                                                      uint8_t *__restrict__ mark, Status *st,
                                                      const int32_t *__restrict__ gv, GStat *gs) {
   __shared__ int32_t s_rp[kTile + 1];
+  __shared__ int32_t s_col[kTileArcs], s_w[kTileArcs];  // the tile's arcs
   __shared__ int s_any;
   __shared__ long long s_lam[B ? kTile : 1];
   __shared__ int32_t s_g[B ? kTile : 1];
@@ -2061,11 +2079,15 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
     const int32_t t = xw.tile();
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t q = (acnt + kPrTB - 1) / kPrTB;
     const int32_t i0 = threadIdx.x * q;
-    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    for (int j = threadIdx.x; j <= rows; j += kPrTB) s_rp[j] = rp[r0 + j] - a0;
+    for (int e = threadIdx.x; e < acnt; e += kPrTB) {
+      s_col[e] = col[a0 + e];
+      s_w[e] = w[a0 + e];
+    }
     if constexpr (B) {
-      for (int j = threadIdx.x; j < rows; j += kTB) {
+      for (int j = threadIdx.x; j < rows; j += kPrTB) {
         const int32_t g = gv[r0 + j];
         s_g[j] = g;
         s_lam[j] = graph_lam(gs[g]);
@@ -2075,21 +2097,35 @@ __global__ __launch_bounds__(kTB) void k_pr_tile(const int32_t *__restrict__ rp,
     __syncthreads();
     bool any = false;
     if (i0 < acnt) {
-      int32_t j = row_of(s_rp, rows, i0);
       const int32_t iend = min(i0 + q, acnt);
-      for (int32_t i = i0; i < iend; i++) {
+      // the other ends' row bounds and degrees, all loads first (clamped)
+      int32_t xs[kPrPer], xbs[kPrPer], xes[kPrPer];
+      unsigned long long dxs[kPrPer];
+#pragma unroll
+      for (int k = 0; k < kPrPer; k++) xs[k] = s_col[min(i0 + k, iend - 1)];
+#pragma unroll
+      for (int k = 0; k < kPrPer; k++) {
+        xbs[k] = rp[xs[k]];
+        xes[k] = rp[xs[k] + 1];
+        dxs[k] = degu[xs[k]];
+      }
+      int32_t j = row_of(s_rp, rows, i0);
+#pragma unroll
+      for (int k = 0; k < kPrPer; k++) {
+        const int32_t i = i0 + k;
+        if (i >= iend) break;
         while (i >= s_rp[j + 1]) j++;
         const int32_t lv = s_rp[j + 1] - s_rp[j];
         if (lv >= kPrRow) continue;  // k_pr_rows
         const int32_t v = r0 + j, a = a0 + i;
-        const int32_t x = col[a];
-        const int32_t xb = rp[x], xe = rp[x + 1];
+        const int32_t x = xs[k], xb = xbs[k], xe = xes[k];
         const long long lam = B ? s_lam[j] : lam0;
         bool mk = false;
         if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
-          const long long c = w[a];
-          const long long dv = (long long)degu[v], dx = (long long)degu[x];
-          mk = pr_cheap(c, dv, dx, lam) || pr_merge(col, w, a0 + s_rp[j], a0 + s_rp[j + 1], xb, xe, c, dv, dx, lam);
+          const long long c = s_w[i];
+          const long long dv = (long long)degu[v], dx = (long long)dxs[k];
+          mk = pr_cheap(c, dv, dx, lam) ||
+               pr_probe(s_col, s_w, s_rp[j], s_rp[j + 1], col, w, xb, xe, c, dv, dx, lam);
         }
         mark[a] = mk ? 1 : 0;
         if (mk) {
@@ -2412,7 +2448,9 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
     if (atomicCAS(&parent[b], b, a) == b) return;
   }
 }
-__global__ void k_uf_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+// one wave per tile: wider workgroups ran more unions at once and lost more
+// time to failed root links than they gained
+__global__ __launch_bounds__(kTB) void k_uf_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                           const uint8_t *__restrict__ mark, const int4 *__restrict__ meta, int32_t ntiles,
                           int32_t *parent) {
   __shared__ int32_t s_rp[kTile + 1];
@@ -2425,11 +2463,22 @@ __global__ void k_uf_tile(const int32_t *__restrict__ rp, const int32_t *__restr
     for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
     __syncthreads();
     if (i0 < acnt) {
-      int32_t j = row_of(s_rp, rows, i0);
       const int32_t iend = min(i0 + q, acnt);
-      for (int32_t i = i0; i < iend; i++) {
+      uint8_t mk[kPerThread];
+      int32_t xs[kPerThread];
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {  // the lane's marks and columns first (clamped)
+        const int32_t a = a0 + min(i0 + k, iend - 1);
+        mk[k] = k < q ? mark[a] : 0;
+        xs[k] = col[a];
+      }
+      int32_t j = row_of(s_rp, rows, i0);
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {
+        const int32_t i = i0 + k;
+        if (i >= iend) break;
         while (i >= s_rp[j + 1]) j++;
-        if (mark[a0 + i]) uf_union(parent, r0 + j, col[a0 + i]);
+        if (mk[k]) uf_union(parent, r0 + j, xs[k]);
       }
     }
     __syncthreads();
@@ -3123,9 +3172,9 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   int32_t *list = w.parent;               // free until the union-find
   const unsigned tg = xcd_grid(grid_for(w.ntiles, 1, 1u << 20));
   if (bv)
-    k_pr_tile<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv, gs);
+    k_pr_tile<true><<<tg, kPrTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv, gs);
   else
-    k_pr_tile<false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, nullptr,
+    k_pr_tile<false><<<tg, kPrTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, nullptr,
                                            nullptr);
   k_pr_list<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, list, w.st);
   const unsigned rg = grid_for(g.nnz / kPrRow + 1, 1, 4096);

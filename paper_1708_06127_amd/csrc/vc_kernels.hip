@@ -637,6 +637,20 @@ __global__ void k_reduce_parts(const unsigned long long *part, int32_t count, St
 // candidate keys (sum, -prio) of a thread's runs are folded per row piece
 // into one maximum update per piece, so no pass over the table is needed.
 // Lanes without work aim their LDS operations at per-lane sink entries.
+// Inclusive maximum over lanes 0..lane of the wave, in DPP moves: shifts
+// by 1, 2, 4 and 8 within the 16-lane rows, then the broadcasts of lane 15
+// (to rows 1 and 3) and lane 31 (to rows 2 and 3). Lanes without a source
+// keep 0, the identity of the unsigned maximum.
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false));  // row_shr:1
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false));  // row_shr:2
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false));  // row_shr:4
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false));  // row_shr:8
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return x;
+}
+
 __device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8) {
   static_assert(kTileArcs / 8 == kTB, "one 8-byte word of marks per lane");
   const int lane = threadIdx.x;
@@ -647,14 +661,9 @@ __device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8)
     run = max(run, (uint32_t)(v >> (8 * k)) & 0xFFu);
     b[k] = run;
   }
-  uint32_t incl = run;
-#pragma unroll
-  for (int off = 1; off < kTB; off <<= 1) {
-    const uint32_t y = __shfl_up(incl, off, kTB);
-    if (lane >= off) incl = max(incl, y);
-  }
-  uint32_t carry = __shfl_up(incl, 1, kTB);
-  if (lane == 0) carry = 0;
+  // the maximum over the lanes before this one: inclusive scan moved up one lane
+  const uint32_t carry =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wave_incl_max(run), 0x138, 0xF, 0xF, false);  // wave_shr:1
   unsigned long long out = 0;
 #pragma unroll
   for (int k = 0; k < 8; k++) out |= (unsigned long long)max(b[k], carry) << (8 * k);

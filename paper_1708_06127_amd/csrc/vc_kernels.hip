@@ -76,27 +76,60 @@ __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsig
   return a < b ? a : b;
 }
 
-// Reductions over aligned groups of G lanes (G <= 64 stays inside a wave).
+// Full-wave reductions in DPP moves: quad_perm [1,0,3,2] and [2,3,0,1],
+// row_half_mirror and row_mirror leave every lane of a 16-lane row with the
+// row's result; the broadcasts of lane 15 (to rows 1 and 3) and lane 31 (to
+// rows 2 and 3) then fold the rows into lane 63, which is read back into
+// every lane. ID is the identity of the operation (what a lane of a row
+// that a broadcast skips contributes).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v, unsigned long long id) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)id, (int)(uint32_t)v, CTRL, ROWS, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(id >> 32), (int)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+template <class Op>
+__device__ __forceinline__ unsigned long long wave_reduce64(unsigned long long v, unsigned long long id, Op op) {
+  v = op(v, dpp64<0xB1, 0xF>(v, id));
+  v = op(v, dpp64<0x4E, 0xF>(v, id));
+  v = op(v, dpp64<0x141, 0xF>(v, id));
+  v = op(v, dpp64<0x140, 0xF>(v, id));
+  v = op(v, dpp64<0x142, 0xA>(v, id));
+  v = op(v, dpp64<0x143, 0xC>(v, id));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Reductions over aligned groups of G lanes (G <= 64 stays inside a wave;
+// result in every lane of the group; called by whole waves).
 template <int G>
 __device__ __forceinline__ unsigned long long grp_max(unsigned long long v) {
+  if constexpr (G == 64) return wave_reduce64(v, 0ull, [](unsigned long long a, unsigned long long b) { return umax64(a, b); });
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v = umax64(v, __shfl_xor(v, off, G));
   return v;
 }
 template <int G>
 __device__ __forceinline__ unsigned long long grp_min(unsigned long long v) {
+  if constexpr (G == 64) return wave_reduce64(v, ~0ull, [](unsigned long long a, unsigned long long b) { return umin64(a, b); });
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off, G));
   return v;
 }
 template <int G>
 __device__ __forceinline__ unsigned long long grp_sum(unsigned long long v) {
+  if constexpr (G == 64) return wave_reduce64(v, 0ull, [](unsigned long long a, unsigned long long b) { return a + b; });
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
   return v;
 }
 template <int G>
 __device__ __forceinline__ int grp_or(int v) {
+  if constexpr (G == 64)
+    return (int)wave_reduce64((unsigned long long)(uint32_t)v, 0ull,
+                              [](unsigned long long a, unsigned long long b) { return a | b; });
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v |= __shfl_xor(v, off, G);
   return v;
@@ -114,8 +147,7 @@ __device__ __forceinline__ unsigned long long block_max(unsigned long long v, un
   return r;
 }
 __device__ __forceinline__ unsigned long long block_min(unsigned long long v, unsigned long long *sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = umin64(v, __shfl_xor(v, off, 64));
+  v = grp_min<64>(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();

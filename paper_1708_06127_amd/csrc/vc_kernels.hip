@@ -995,8 +995,10 @@ __global__ __launch_bounds__(kTB) void k_lp_tile_big(const int32_t *__restrict__
 // Rows longer than 4096 arcs: split into chunks; one workgroup per chunk.
 // plan: per huge vertex i, meta[3i] = first chunk, meta[3i+1] = table offset,
 // meta[3i+2] = table size (power of two >= 2 d, or 0 without a table).
+// (deg_zero, at level 0: the huge rows' degree accumulators, zeroed here)
 __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_t *cnt_p, int32_t *meta,
-                            unsigned long long *best, int with_table, int64_t cap, Status *st) {
+                            unsigned long long *best, int with_table, int64_t cap, Status *st,
+                            long long *deg_zero) {
   __shared__ int64_t sh_c[kBlock], sh_t[kBlock];
   __shared__ int64_t carry_c, carry_t;
   if (st->err) return;
@@ -1012,6 +1014,7 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
       c = (d + kHugeChunk - 1) / kHugeChunk;
       if (with_table) { t = 1; while (t < 2 * (int64_t)d) t <<= 1; }
       best[i] = 0;
+      if (deg_zero) deg_zero[v] = 0;
     }
     sh_c[threadIdx.x] = c;
     sh_t[threadIdx.x] = t;
@@ -1286,10 +1289,6 @@ __global__ void k_huge_final(const int32_t *rp, const int32_t *list, const int32
   }
 }
 
-__global__ void k_zero_deg_list(const int32_t *list, const int32_t *cnt_p, long long *deg) {
-  const int32_t cnt = *cnt_p;
-  for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) deg[list[i]] = 0;
-}
 
 // ------------------------------------------------------------ validation (flag)
 // every arc (v,u,c) has its reverse (u,v,c); rows strictly increasing
@@ -1918,9 +1917,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long 
 }
 
 // sorted triples -> coarse CSR: segment heads, column, summed weight per segment
-__global__ void k_seg_heads(const unsigned long long *keys, int64_t count, int32_t *head) {
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
-    head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+// The same pass zeroes the accumulators of the coarse graph being built (row
+// counts, int64 degrees as 32-bit words, weights) and, when given, resets the
+// minimum-degree key.
+__global__ void k_seg_heads(const unsigned long long *keys, int64_t count, int32_t *head, int32_t *rowcnt,
+                            int64_t nrow, int32_t *degw, int64_t ndeg, int32_t *wsum,
+                            unsigned long long *minkey) {
+  const int64_t m = max(count, max(nrow, ndeg));
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+    if (i < count) {
+      head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+      wsum[i] = 0;
+    }
+    if (i < nrow) rowcnt[i] = 0;
+    if (i < ndeg) degw[i] = 0;
+  }
+  if (minkey && blockIdx.x == 0 && threadIdx.x == 0) *minkey = ~0ull;
 }
 // seg = exclusive scan of head; each element adds its weight to its segment.
 // Within a wave, a segmented scan keyed by segment leaves one weight
@@ -1971,8 +1983,14 @@ __global__ void k_seg_write(const unsigned long long *keys, const int32_t *vals,
   }
 }
 
-__global__ void k_set_minkey(Status *st) {
-  if (threadIdx.x == 0) st->minkey = ~0ull;
+// counters of the PR pass
+__global__ void k_pr_reset(Status *st) {
+  if (threadIdx.x == 0) {
+    st->nmarked = 0;
+    st->huge_items = 0;
+    st->pr_rows[0] = 0;
+    st->pr_rows[1] = 0;
+  }
 }
 __global__ void k_reset_bins(Status *st) {
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
@@ -3048,8 +3066,8 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   // huge rows: chunked
   const int32_t *list6 = w.bins + 6ll * w.n_in;
   const int32_t *cnt6 = &w.st->bin_cnt[6];
-  if (level0) k_zero_deg_list<<<64, kBlock, 0, s>>>(list6, cnt6, w.deg);
-  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st);
+  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st,
+                                   level0 ? w.deg : nullptr);
   k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(
       g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, nullptr, nullptr, nullptr, w.huge_best, w.deg, salt,
       level0 ? 2 : 0, w.st, gv, gs);
@@ -3082,7 +3100,7 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
   const int32_t *list6 = w.bins + 6ll * w.n_in;
   const int32_t *cnt6 = &w.st->bin_cnt[6];
-  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st);
+  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st, nullptr);
   k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);
   k_huge_insert<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, list6, cnt6,
                                                                      w.huge_meta, Lin, w.huge_tab_key,
@@ -3166,12 +3184,11 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
   // free scratch while the sorted triples sit in buffer `which`
   int32_t *head = w.vals[which ^ 1];
   int32_t *seg = (int32_t *)w.keys[which ^ 1];
-  hipError_t e = fill_i32(rowcnt, 0, (int64_t)k + 1, s);
-  if (e == hipSuccess) e = fill_i32((int32_t *)degu, 0, 2ll * k, s);
-  if (e == hipSuccess) e = fill_i32(w.w[dst], 0, count, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  k_seg_heads<<<grid_for(std::max<int64_t>(count, 2ll * k + 1)), kBlock, 0, s>>>(
+      w.keys[which], count, head, rowcnt, (int64_t)k + 1, (int32_t *)degu, 2ll * k, w.w[dst],
+      single_bound ? &w.st->minkey : nullptr);
   if (count > 0) {
-    k_seg_heads<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], count, head);
     e = scan_exclusive(w, head, seg, count, &w.st->nnz, s);
     if (e != hipSuccess) return e;
     k_seg_write<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], w.vals[which], count, seg, head, key_bits,
@@ -3183,7 +3200,6 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
   e = scan_exclusive(w, rowcnt, rowcnt, (int64_t)k + 1, nullptr, s);
   if (e != hipSuccess) return e;
   if (!single_bound) return hipGetLastError();
-  k_set_minkey<<<1, 64, 0, s>>>(w.st);
   k_min_degree<<<grid_for(k, kBlock, 1024), kBlock, 0, s>>>(degu, k, w.st);
   k_bound<<<1, 64, 0, s>>>(w.st, level, k);
   k_witness<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.n_in, w.st, w.witness);
@@ -3204,10 +3220,7 @@ hipError_t reset_bins(Work &w, hipStream_t s) {
 hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
-  hipError_t e = fill_i32(&w.st->nmarked, 0, 1, s);
-  if (e == hipSuccess) e = fill_i32(&w.st->huge_items, 0, 1, s);
-  if (e == hipSuccess) e = fill_i32(w.st->pr_rows, 0, 2, s);
-  if (e != hipSuccess) return e;
+  k_pr_reset<<<1, 64, 0, s>>>(w.st);
   const unsigned long long *degu = (const unsigned long long *)w.deg;
   int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
   int32_t *list = w.parent;               // free until the union-find

@@ -28,9 +28,9 @@ uint64_t splitmix64_at(uint64_t seed, uint64_t index) {
 
 // ------------------------------------------------------------ kernel timing
 // Process-wide and off by default. While on, each timed launch gets an event
-// pair on its stream and a 16-byte copy of the level's tile totals (rows,
-// arcs) into page-locked memory; prof_collect() folds completed records into
-// per-kernel totals of duration and algorithmic bytes.
+// pair on its stream, and its kernel writes the level's tile totals (rows,
+// arcs: 16 bytes) into a page-locked record; prof_collect() folds completed
+// records into per-kernel totals of duration and algorithmic bytes.
 namespace {
 struct ProfRec {
   int kind;
@@ -43,6 +43,7 @@ struct ProfState {
   std::vector<ProfRec> pending;
   std::vector<hipEvent_t> pool;
   int32_t *slots = nullptr;  // 4 int32 per record: tile_rows, pad, tile_arcs (u64)
+  int32_t *dslots = nullptr;  // the same memory's device address
   int32_t cap = 0;
   int64_t launches[PROF_KINDS] = {0};
   double ms[PROF_KINDS] = {0}, bytes[PROF_KINDS] = {0};
@@ -79,6 +80,7 @@ ProfScope::ProfScope(ProfKind kind, hipStream_t stream, const Status *st_, int32
   if (!r.a || !r.b || hipEventRecord(r.a, s) != hipSuccess) return;
   slot = (int)p.pending.size();
   p.pending.push_back(r);
+  dev = p.dslots + 4 * slot;
 }
 
 ProfScope::~ProfScope() {
@@ -87,7 +89,6 @@ ProfScope::~ProfScope() {
   std::lock_guard<std::mutex> lk(p.mu);
   if (slot >= (int)p.pending.size()) return;
   (void)hipEventRecord(p.pending[slot].b, s);
-  (void)hipMemcpyAsync(&p.slots[4 * slot], &st->tile_rows, 16, hipMemcpyDeviceToHost, s);
 }
 
 void prof_collect() {
@@ -583,6 +584,11 @@ int viecut_profile_enable(int on) {
       if (hipHostMalloc((void **)&p.slots, 16 * (size_t)cap, 0) != hipSuccess) {
         p.slots = nullptr;
         return VIECUT_ENOMEM;
+      }
+      if (hipHostGetDevicePointer((void **)&p.dslots, p.slots, 0) != hipSuccess) {
+        (void)hipHostFree(p.slots);
+        p.slots = nullptr;
+        return VIECUT_EDEVICE;
       }
       p.cap = cap;
     }

@@ -262,6 +262,10 @@ struct ProfScope {
   int slot = -1;
   hipStream_t s;
   const Status *st;
+  // device address of the record's 16-byte snapshot of (tile_rows, big_tiles,
+  // tile_arcs) in page-locked host memory, or nullptr: the first launch of
+  // the scope writes it from one thread (no copy is queued)
+  int32_t *dev = nullptr;
   ProfScope(ProfKind kind, hipStream_t stream, const Status *st, int32_t ntiles);
   ~ProfScope();
 };

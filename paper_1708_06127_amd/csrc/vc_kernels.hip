@@ -517,6 +517,17 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
   }
 }
 
+// Kernel timing: one thread copies the level's tile totals (16 bytes from
+// tile_rows) into the timing record, a page-locked host buffer.
+__device__ __forceinline__ void prof_snapshot(int32_t *prof, const Status *st) {
+  if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(&st->tile_rows);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(prof);
+    dst[0] = src[0];
+    dst[1] = src[1];
+  }
+}
+
 // ------------------------------------------------------------ tiled LP (short rows)
 // A tile's arcs are split into 64 runs of q = ceil(arcs/64) <= 8 consecutive
 // arcs, one per lane of the tile's single wave. Every global load of a lane's
@@ -536,9 +547,10 @@ __global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ 
                                                         int32_t *__restrict__ L, long long *__restrict__ deg,
                                                         uint32_t salt, const Status *st,
                                                         unsigned long long *__restrict__ part,
-                                                        const int32_t *__restrict__ gv, GStat *gs) {
+                                                        const int32_t *__restrict__ gv, GStat *gs, int32_t *prof) {
   __shared__ int32_t s_rp[kTile + 1];
   __shared__ unsigned long long s_best[kTile];
+  prof_snapshot(prof, st);
   __shared__ unsigned long long s_sum[kTile];
   // batched: graph-local id offset and salt of each row
   __shared__ int32_t s_base[B ? kTile : 1];
@@ -929,10 +941,11 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
                                                      int32_t *__restrict__ Lout, const int4 *__restrict__ meta,
                                                      int32_t ntiles, uint32_t salt, const Status *st,
-                                                     const int32_t *__restrict__ gv, const GStat *gs) {
+                                                     const int32_t *__restrict__ gv, const GStat *gs, int32_t *prof) {
   __shared__ LpTileShared<4> sh;
   __shared__ int32_t s_base[B ? kTile : 1];
   __shared__ uint32_t s_salt[B ? kTile : 1];
+  prof_snapshot(prof, st);
   if (!B && st->err) return;
   constexpr int32_t kSmall = 4 * kTB;
   XcdWalk xw(ntiles);
@@ -3039,16 +3052,16 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
     if (bv) {
       if (level0)
         k_first_tile<true, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                       salt, w.st, w.part, gv, gs);
+                                                       salt, w.st, w.part, gv, gs, ps.dev);
       else
         k_first_tile<false, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                        salt, w.st, w.part, gv, gs);
+                                                        salt, w.st, w.part, gv, gs, ps.dev);
     } else if (level0) {
       k_first_tile<true, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                      salt, w.st, w.part, nullptr, nullptr);
+                                                      salt, w.st, w.part, nullptr, nullptr, ps.dev);
     } else {
       k_first_tile<false, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                       salt, w.st, w.part, nullptr, nullptr);
+                                                       salt, w.st, w.part, nullptr, nullptr, ps.dev);
     }
   }
   if (!bv && level0) k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
@@ -3085,12 +3098,12 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
     if (bv) {
       k_lp_tile<true><<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(
-          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs);
+          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs, ps.dev);
       k_lp_tile_big<true><<<resident_grid(k_lp_tile_big<true>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, gv, gs);
     } else {
       k_lp_tile<false><<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(
-          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr);
+          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr, ps.dev);
       k_lp_tile_big<false><<<resident_grid(k_lp_tile_big<false>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);
     }
@@ -3135,8 +3148,22 @@ hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const Ba
   return hipGetLastError();
 }
 
+// map = identity; the same launch clears the scans' look-back state, so the
+// first scan of the solve needs no clearing launch of its own
+__global__ void k_init_map(int32_t *map, int32_t n, unsigned long long *lb_state, int64_t lb_words,
+                           uint32_t *lb_ticket) {
+  const int64_t m = max((int64_t)n, lb_words);
+  for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < m; u += (int64_t)gridDim.x * kBlock) {
+    if (u < n) map[u] = (int32_t)u;
+    if (u < lb_words) lb_state[u] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *lb_ticket = 0;
+}
+
 hipError_t init_map(Work &w, hipStream_t s) {
-  k_iota<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.n_in);
+  k_init_map<<<grid_for(std::max<int64_t>(w.n_in, w.lb_tiles)), kBlock, 0, s>>>(w.map, w.n_in, w.lb_state,
+                                                                               w.lb_tiles, w.lb_ticket);
+  w.lb_epoch = 1;  // cleared: the next scan takes epoch 2
   return hipGetLastError();
 }
 

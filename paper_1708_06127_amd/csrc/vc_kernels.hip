@@ -232,14 +232,10 @@ __global__ void k_check_rowptr(const int32_t *rp, int32_t n, int64_t nnz, Status
 // Arc tiles: tile t starts at the first row v with rp[v] + v >= t * kTile.
 // meta[t] = {first row, short rows, first arc, arcs of the short rows}; a
 // trailing row with >= kTile arcs is excluded (the long-row kernels take it).
-__device__ __forceinline__ int32_t tile_start(const int32_t *rp, int32_t n, int64_t target) {
-  int32_t lo = 0, hi = n;  // rp[n] + n >= target for every tile start
-  while (lo < hi) {
-    int32_t mid = (lo + hi) >> 1;
-    if ((int64_t)rp[mid] + mid < target) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
+// The first row of tile t is the smallest v in [0, n] with rp[v] + v >= 256 t.
+// As f(v) = rp[v] + v grows strictly, row v is the first row of exactly the
+// tiles t with f(v - 1) < 256 t <= f(v): one pass over the rows (k_row_pass)
+// writes every tile's first row into meta[t].x, with no search.
 // Tiles of more than 4 * 64 arcs (a long row closes them) are also listed in
 // `big`, in any order, for the LP kernel that runs them with 8 arcs per thread.
 __global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st, int32_t *big) {
@@ -251,8 +247,9 @@ __global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta
     const int64_t t = t0 + threadIdx.x;
     bool is_big = false;
     if (t < ntiles) {
-      const int32_t r0 = tile_start(rp, n, t * (int64_t)kTile);
-      int32_t r1 = t + 1 == ntiles ? n : tile_start(rp, n, (t + 1) * (int64_t)kTile);
+      // first rows from k_row_pass (this pass rewrites meta[t].x unchanged)
+      const int32_t r0 = meta[t].x;
+      int32_t r1 = t + 1 == ntiles ? n : meta[t + 1].x;
       if (r1 > r0 && rp[r1] - rp[r1 - 1] >= kTile) r1--;
       const int32_t acnt = rp[r1] - rp[r0];
       meta[t] = make_int4(r0, r1 - r0, rp[r0], acnt);
@@ -294,12 +291,22 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int
 
 // Lists of long rows (classes 4-6 of degree_bin), appended per workgroup:
 // LDS counters, then one global reservation per class and workgroup.
-__global__ void k_long_rows(const int32_t *rp, int32_t n, int64_t stride, int32_t *bins, Status *st) {
+// One pass over the rows of a level: the first row of every arc tile (into
+// meta[t].x, see above) and the lists of long rows (classes 4-6 of
+// degree_bin), appended per workgroup: LDS counters, then one global
+// reservation per class and workgroup.
+__global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, int64_t stride, int32_t *bins,
+                           Status *st) {
   __shared__ int32_t cnt[3], base[3];
-  for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 < n; b0 += (int64_t)gridDim.x * kBlock) {
+  for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 <= n; b0 += (int64_t)gridDim.x * kBlock) {
     if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t v = b0 + threadIdx.x;
+    if (v <= n) {
+      const int64_t t_lo = v == 0 ? 0 : ((int64_t)rp[v - 1] + v - 1) / kTile + 1;
+      const int64_t t_hi = min(((int64_t)rp[v] + v) / kTile, (int64_t)ntiles - 1);
+      for (int64_t t = t_lo; t <= t_hi; t++) meta[t].x = (int32_t)v;
+    }
     const int32_t d = v < n ? rp[v + 1] - rp[v] : 0;
     const int cls = d >= kTile ? degree_bin(d) - 4 : -1;
     const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
@@ -2992,8 +2999,9 @@ hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
 
 hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s) {
   w.ntiles = (int32_t)((g.nnz + g.n + kTile - 1) / kTile);
+  k_row_pass<<<grid_for((int64_t)g.n + 1, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta,
+                                                                        w.n_in, w.bins, w.st);
   k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta, w.st, w.big_tiles);
-  k_long_rows<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, w.n_in, w.bins, w.st);
   return hipGetLastError();
 }
 

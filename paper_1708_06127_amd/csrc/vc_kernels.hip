@@ -1649,6 +1649,9 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
                                               int32_t *__restrict__ vals, int32_t *__restrict__ first,
                                               int32_t *__restrict__ cnt,
                                               EmitTileShared &sh) {
+  // table slots: >= the tile's arcs, so probing ends (a tile of at most
+  // 4 * 64 arcs uses half the table: half the clearing and output work)
+  constexpr int kSlots = NQ * kTB <= kCombSlots / 2 ? kCombSlots / 2 : kCombSlots;
   const int lane = threadIdx.x;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
   const int32_t q = (acnt + kTB - 1) / kTB;
@@ -1671,7 +1674,7 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
   }
   for (int j = lane; j <= rows; j += kTB) sh.rp[j] = rp[r0 + j] - a0;
   for (int j = lane; j < rows; j += kTB) sh.cl[j] = cl[r0 + j];
-  for (int e = lane; e < kCombSlots; e += kTB) {
+  for (int e = lane; e < kSlots; e += kTB) {
     sh.tkey[e] = kNoPair;
     sh.tval[e] = 0;
   }
@@ -1707,14 +1710,14 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       const uint32_t fold = (uint32_t)key[k] ^ (uint32_t)(key[k] >> 32);
-      hh[k] = (fold * 2654435761u) & (kCombSlots - 1);
+      hh[k] = (fold * 2654435761u) & (kSlots - 1);
       old[k] = ok[k] ? atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]) : kNoPair;
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       if (!ok[k]) continue;
       while (old[k] != kNoPair && old[k] != key[k]) {  // taken by another pair
-        hh[k] = (hh[k] + 1) & (kCombSlots - 1);
+        hh[k] = (hh[k] + 1) & (kSlots - 1);
         old[k] = atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]);
       }
     }
@@ -1727,7 +1730,7 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
   int32_t tot = 0;
   if (acnt > 0) {
 #pragma unroll
-    for (int k = 0; k < kCombSlots / kTB; k++) {
+    for (int k = 0; k < kSlots / kTB; k++) {
       const int e = k * kTB + lane;
       const unsigned long long kk = sh.tkey[e];
       const uint32_t vv = sh.tval[e];

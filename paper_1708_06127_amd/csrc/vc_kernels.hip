@@ -320,14 +320,15 @@ __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *m
 }
 
 // ------------------------------------------------------------ XCD-aware tile order
-// Workgroup i runs on XCD i mod 8, and each XCD has its own L2. With many
-// tiles, they are dealt to the XCDs in chunks of 64 consecutive tiles (chunk
-// c to XCD c mod 8), and the workgroups of an XCD walk its chunks in order:
-// the neighbour-label gathers of a tile, which mostly hit ids close to its
-// own rows in locality-ordered inputs, then find lines that the XCD's L2
-// already holds for the neighbouring tiles, while at least 32 chunks per XCD
-// keep the work balanced on skewed inputs. Fewer tiles are dealt one by one.
-// Launches use grids that are multiples of 8.
+// Workgroup i runs on XCD i mod 8, and each XCD has its own L2. The LP tile
+// kernel, with many tiles, deals them to the XCDs in chunks of 64 consecutive
+// tiles (chunk c to XCD c mod 8), and the workgroups of an XCD walk its chunks
+// in order: the neighbour-label gathers of a tile, which mostly hit ids close
+// to its own rows in locality-ordered inputs, then find lines that the XCD's
+// L2 already holds for the neighbouring tiles, while at least 32 chunks per
+// XCD keep the work balanced on skewed inputs. Fewer tiles are dealt one by
+// one. (The union-find tiles keep the plain order: neighbouring tiles at once
+// link into the same components and contend.) Grids are multiples of 8.
 constexpr int kXcds = 8;
 constexpr int kXcdChunkLog = 6;
 constexpr int32_t kXcdChunkMin = kXcds * 32 << kXcdChunkLog;  // tiles for chunked dealing
@@ -1649,9 +1650,9 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
                                               int32_t *__restrict__ vals, int32_t *__restrict__ first,
                                               int32_t *__restrict__ cnt,
                                               EmitTileShared &sh) {
-  // table slots: >= the tile's arcs, so probing ends (a tile of at most
-  // 4 * 64 arcs uses half the table: half the clearing and output work)
-  constexpr int kSlots = NQ * kTB <= kCombSlots / 2 ? kCombSlots / 2 : kCombSlots;
+  // table slots: twice the arcs of the largest tile (a half-size table for
+  // the small tiles measured slower on inputs with many distinct pairs)
+  constexpr int kSlots = kCombSlots;
   const int lane = threadIdx.x;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
   const int32_t q = (acnt + kTB - 1) / kTB;
@@ -1827,13 +1828,19 @@ __global__ void k_compact(const int32_t *first, const int32_t *off, int32_t nseg
 }
 
 // ---- LSD radix sort of (u64 key, i32 value), 8-bit digits, stable
-constexpr int kRsItems = kRsTile / kBlock;
+// ITEMS elements per thread: small sorts use kRsTile-element blocks (more
+// blocks than CUs), large ones 4x larger blocks (a 4x smaller digit-by-block
+// matrix to scan, longer runs per digit in the scatter).
+constexpr int kRsItemsSmall = kRsTile / kBlock;
+constexpr int kRsItemsLarge = 4 * kRsItemsSmall;
+constexpr int64_t kRsLargeFrom = 1 << 22;  // elements
 
-__global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shift, int32_t *hist, int32_t tiles) {
+template <int kRsItems>
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const unsigned long long *keys, int64_t count, int shift, int32_t *hist, int32_t tiles) {
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t base = blockIdx.x * (int64_t)kRsTile + (int64_t)wid * 64 * kRsItems;
+  const int64_t base = blockIdx.x * (int64_t)(kBlock * kRsItems) + (int64_t)wid * 64 * kRsItems;
   const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   int dg[kRsItems];
 #pragma unroll
@@ -1862,6 +1869,7 @@ __global__ void k_rs_hist(const unsigned long long *keys, int64_t count, int shi
 // in LDS in digit order, and then writes each digit's run to its global
 // position with consecutive threads on consecutive elements, so that the
 // writes of a run are coalesced instead of one scattered line per element.
+template <int kRsItems>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long *__restrict__ kin,
                                                         const int32_t *__restrict__ vin,
                                                         unsigned long long *__restrict__ kout,
@@ -1871,13 +1879,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long 
   __shared__ int32_t dstart[256];  // block-local start of each digit's run
   __shared__ int32_t goff[256];    // global position of a run minus its block-local start
   __shared__ int32_t sh[kBlock / 64];
-  __shared__ unsigned long long skey[kRsTile];
-  __shared__ int32_t sval[kRsTile];
+  __shared__ unsigned long long skey[kBlock * kRsItems];
+  __shared__ int32_t sval[kBlock * kRsItems];
   static_assert(kBlock == 256, "one thread per digit");
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int d = threadIdx.x; d < 256 * (kBlock / 64); d += kBlock) (&wcnt[0][0])[d] = 0;
   __syncthreads();
-  const int64_t blk0 = blockIdx.x * (int64_t)kRsTile;
+  const int64_t blk0 = blockIdx.x * (int64_t)(kBlock * kRsItems);
   const int64_t base = blk0 + (int64_t)wid * 64 * kRsItems;
   unsigned long long key[kRsItems];
   int32_t val[kRsItems], rank[kRsItems], dig[kRsItems];
@@ -1930,7 +1938,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const unsigned long long 
     sval[l] = val[j];
   }
   __syncthreads();
-  const int32_t nvalid = (int32_t)min<int64_t>(kRsTile, count - blk0);
+  const int32_t nvalid = (int32_t)min<int64_t>(kBlock * kRsItems, count - blk0);
   for (int e = threadIdx.x; e < nvalid; e += kBlock) {
     const unsigned long long k = skey[e];
     const int64_t pos = (int64_t)goff[(int)((k >> shift) & 255)] + e;
@@ -2104,14 +2112,15 @@ __device__ __forceinline__ void flag_marked(GStat *gs, int32_t g, int32_t &flagg
 
 // conditions 3 and 4 for the owned arc (v, x) of a short row: v's sorted row
 // is in LDS ([vb, ve) of s_col / s_w), x's row (not longer) is read from
-// global memory 8 entries at a time, all loads first, and each entry is
-// looked up in v's row by binary search. The decision does not depend on the
-// order in which the common neighbours are met.
+// global memory 8 entries at a time, all loads first, and merged with v's
+// row by a pointer that only moves forward. The decision does not depend on
+// the order in which the common neighbours are met.
 __device__ bool pr_probe(const int32_t *s_col, const int32_t *s_w, int32_t vb, int32_t ve,
                          const int32_t *__restrict__ col, const int32_t *__restrict__ w, int32_t xb, int32_t xe,
                          long long c, long long dv, long long dx, long long lam) {
   long long sum4 = c;
-  for (int32_t j0 = xb; j0 < xe; j0 += kLoadBatch) {
+  int32_t p = vb;
+  for (int32_t j0 = xb; j0 < xe && p < ve; j0 += kLoadBatch) {
     int32_t us[kLoadBatch], cx[kLoadBatch];
 #pragma unroll
     for (int k = 0; k < kLoadBatch; k++) {
@@ -2122,13 +2131,10 @@ __device__ bool pr_probe(const int32_t *s_col, const int32_t *s_w, int32_t vb, i
 #pragma unroll
     for (int k = 0; k < kLoadBatch; k++) {
       if (j0 + k >= xe) break;
-      int32_t lo = vb, hi = ve;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (s_col[mid] < us[k]) lo = mid + 1; else hi = mid;
-      }
-      if (lo < ve && s_col[lo] == us[k]) {
-        const long long cvu = s_w[lo], cxu = cx[k];
+      while (p < ve && s_col[p] < us[k]) p++;
+      if (p == ve) break;  // v's row is exhausted: no further common neighbour
+      if (s_col[p] == us[k]) {
+        const long long cvu = s_w[p], cxu = cx[k];
         if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
         sum4 += cvu < cxu ? cvu : cxu;
         if (sum4 >= lam) return true;
@@ -2138,13 +2144,35 @@ __device__ bool pr_probe(const int32_t *s_col, const int32_t *s_w, int32_t vb, i
   return sum4 >= lam;
 }
 
+// conditions 3 and 4 by merging two short sorted rows
+__device__ bool pr_merge(const int32_t *col, const int32_t *w, int32_t vb, int32_t ve, int32_t xb, int32_t xe,
+                         long long c, long long dv, long long dx, long long lam) {
+  long long sum4 = c;
+  int32_t i = vb, j = xb;
+  while (i < ve && j < xe) {
+    const int32_t a = col[i], b = col[j];
+    if (a < b) {
+      i++;
+    } else if (b < a) {
+      j++;
+    } else {
+      const long long cvu = w[i], cxu = w[j];
+      if (dv < 2 * (c + cvu) && dx < 2 * (c + cxu)) return true;
+      sum4 += cvu < cxu ? cvu : cxu;
+      if (sum4 >= lam) return true;
+      i++;
+      j++;
+    }
+  }
+  return sum4 >= lam;
+}
+
 // Short rows on the tiles. Rows of kPrRow arcs or more are left to k_pr_rows.
-// The PR graphs are the small coarse ones, so a tile takes a whole workgroup
-// of kPrTB threads (at most 2 arcs each) to keep enough waves in flight.
-constexpr int kPrTB = kBlock;
-constexpr int kPrPer = kTileArcs / kPrTB;
-template <bool B>
-__global__ __launch_bounds__(kPrTB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+// Small PR graphs (a single solve's coarse graphs): a tile takes a workgroup
+// of TB threads (kTileArcs / TB arcs each at most), which keeps enough waves
+// in flight, and the owner's row is read from LDS.
+template <bool B, int TB>
+__global__ __launch_bounds__(TB) void k_pr_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w,
                                                      const unsigned long long *__restrict__ degu,
                                                      const int4 *__restrict__ meta, int32_t ntiles,
@@ -2157,19 +2185,18 @@ __global__ __launch_bounds__(kPrTB) void k_pr_tile(const int32_t *__restrict__ r
   __shared__ int32_t s_g[B ? kTile : 1];
   const long long lam0 = B ? 0 : st->lam_hat;
   int32_t flagged = -1;
-  for (XcdWalk xw(ntiles); xw.ok(); xw.next()) {
-    const int32_t t = xw.tile();
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-    const int32_t q = (acnt + kPrTB - 1) / kPrTB;
+    const int32_t q = (acnt + TB - 1) / TB;
     const int32_t i0 = threadIdx.x * q;
-    for (int j = threadIdx.x; j <= rows; j += kPrTB) s_rp[j] = rp[r0 + j] - a0;
-    for (int e = threadIdx.x; e < acnt; e += kPrTB) {
+    for (int j = threadIdx.x; j <= rows; j += TB) s_rp[j] = rp[r0 + j] - a0;
+    for (int e = threadIdx.x; e < acnt; e += TB) {
       s_col[e] = col[a0 + e];
       s_w[e] = w[a0 + e];
     }
     if constexpr (B) {
-      for (int j = threadIdx.x; j < rows; j += kPrTB) {
+      for (int j = threadIdx.x; j < rows; j += TB) {
         const int32_t g = gv[r0 + j];
         s_g[j] = g;
         s_lam[j] = graph_lam(gs[g]);
@@ -2181,19 +2208,19 @@ __global__ __launch_bounds__(kPrTB) void k_pr_tile(const int32_t *__restrict__ r
     if (i0 < acnt) {
       const int32_t iend = min(i0 + q, acnt);
       // the other ends' row bounds and degrees, all loads first (clamped)
-      int32_t xs[kPrPer], xbs[kPrPer], xes[kPrPer];
-      unsigned long long dxs[kPrPer];
+      int32_t xs[(kTileArcs / TB)], xbs[(kTileArcs / TB)], xes[(kTileArcs / TB)];
+      unsigned long long dxs[(kTileArcs / TB)];
 #pragma unroll
-      for (int k = 0; k < kPrPer; k++) xs[k] = s_col[min(i0 + k, iend - 1)];
+      for (int k = 0; k < (kTileArcs / TB); k++) xs[k] = s_col[min(i0 + k, iend - 1)];
 #pragma unroll
-      for (int k = 0; k < kPrPer; k++) {
+      for (int k = 0; k < (kTileArcs / TB); k++) {
         xbs[k] = rp[xs[k]];
         xes[k] = rp[xs[k] + 1];
         dxs[k] = degu[xs[k]];
       }
       int32_t j = row_of(s_rp, rows, i0);
 #pragma unroll
-      for (int k = 0; k < kPrPer; k++) {
+      for (int k = 0; k < (kTileArcs / TB); k++) {
         const int32_t i = i0 + k;
         if (i >= iend) break;
         while (i >= s_rp[j + 1]) j++;
@@ -2208,6 +2235,69 @@ __global__ __launch_bounds__(kPrTB) void k_pr_tile(const int32_t *__restrict__ r
           const long long dv = (long long)degu[v], dx = (long long)dxs[k];
           mk = pr_cheap(c, dv, dx, lam) ||
                pr_probe(s_col, s_w, s_rp[j], s_rp[j + 1], col, w, xb, xe, c, dv, dx, lam);
+        }
+        mark[a] = mk ? 1 : 0;
+        if (mk) {
+          any = true;
+          if constexpr (B) flag_marked(gs, s_g[j], flagged);
+        }
+      }
+    }
+    if (any) s_any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_any && st->nmarked == 0) atomicExch(&st->nmarked, 1);
+    __syncthreads();
+  }
+}
+
+// The same on large PR graphs (batched unions): one wave per tile, each
+// owned edge merged from the two rows in global memory, which measured
+// faster there than staging the tile's rows in LDS.
+template <bool B>
+__global__ __launch_bounds__(kTB) void k_pr_tile_merge(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ w,
+                                                     const unsigned long long *__restrict__ degu,
+                                                     const int4 *__restrict__ meta, int32_t ntiles,
+                                                     uint8_t *__restrict__ mark, Status *st,
+                                                     const int32_t *__restrict__ gv, GStat *gs) {
+  __shared__ int32_t s_rp[kTile + 1];
+  __shared__ int s_any;
+  __shared__ long long s_lam[B ? kTile : 1];
+  __shared__ int32_t s_g[B ? kTile : 1];
+  const long long lam0 = B ? 0 : st->lam_hat;
+  int32_t flagged = -1;
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 m = meta[t];
+    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+    const int32_t q = (acnt + kTB - 1) / kTB;
+    const int32_t i0 = threadIdx.x * q;
+    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    if constexpr (B) {
+      for (int j = threadIdx.x; j < rows; j += kTB) {
+        const int32_t g = gv[r0 + j];
+        s_g[j] = g;
+        s_lam[j] = graph_lam(gs[g]);
+      }
+    }
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    bool any = false;
+    if (i0 < acnt) {
+      int32_t j = row_of(s_rp, rows, i0);
+      const int32_t iend = min(i0 + q, acnt);
+      for (int32_t i = i0; i < iend; i++) {
+        while (i >= s_rp[j + 1]) j++;
+        const int32_t lv = s_rp[j + 1] - s_rp[j];
+        if (lv >= kPrRow) continue;  // k_pr_rows
+        const int32_t v = r0 + j, a = a0 + i;
+        const int32_t x = col[a];
+        const int32_t xb = rp[x], xe = rp[x + 1];
+        const long long lam = B ? s_lam[j] : lam0;
+        bool mk = false;
+        if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
+          const long long c = w[a];
+          const long long dv = (long long)degu[v], dx = (long long)degu[x];
+          mk = pr_cheap(c, dv, dx, lam) || pr_merge(col, w, a0 + s_rp[j], a0 + s_rp[j + 1], xb, xe, c, dv, dx, lam);
         }
         mark[a] = mk ? 1 : 0;
         if (mk) {
@@ -2536,8 +2626,7 @@ __global__ __launch_bounds__(kTB) void k_uf_tile(const int32_t *__restrict__ rp,
                           const uint8_t *__restrict__ mark, const int4 *__restrict__ meta, int32_t ntiles,
                           int32_t *parent) {
   __shared__ int32_t s_rp[kTile + 1];
-  for (XcdWalk xw(ntiles); xw.ok(); xw.next()) {
-    const int32_t t = xw.tile();
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
     const int32_t q = (acnt + kTB - 1) / kTB;
@@ -2549,11 +2638,10 @@ __global__ __launch_bounds__(kTB) void k_uf_tile(const int32_t *__restrict__ rp,
       uint8_t mk[kPerThread];
       int32_t xs[kPerThread];
 #pragma unroll
-      for (int k = 0; k < kPerThread; k++) {  // the lane's marks and columns first (clamped)
-        const int32_t a = a0 + min(i0 + k, iend - 1);
-        mk[k] = k < q ? mark[a] : 0;
-        xs[k] = col[a];
-      }
+      for (int k = 0; k < kPerThread; k++)  // the lane's marks first (clamped), then the marked columns
+        mk[k] = k < q && i0 + k < iend ? mark[a0 + i0 + k] : 0;
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) xs[k] = mk[k] ? col[a0 + i0 + k] : 0;
       int32_t j = row_of(s_rp, rows, i0);
 #pragma unroll
       for (int k = 0; k < kPerThread; k++) {
@@ -3201,18 +3289,27 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
   return hipGetLastError();
 }
 
-hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s) {
-  if (count <= 1) return hipSuccess;
-  const int32_t tiles = (int32_t)((count + kRsTile - 1) / kRsTile);
+namespace {
+template <int ITEMS>
+hipError_t radix_passes(Work &w, int64_t count, int total_bits, int &which, hipStream_t s) {
+  constexpr int64_t tile = (int64_t)kBlock * ITEMS;
+  const int32_t tiles = (int32_t)((count + tile - 1) / tile);
   for (int shift = 0; shift < total_bits; shift += 8) {
-    k_rs_hist<<<tiles, kBlock, 0, s>>>(w.keys[which], count, shift, w.hist, tiles);
+    k_rs_hist<ITEMS><<<tiles, kBlock, 0, s>>>(w.keys[which], count, shift, w.hist, tiles);
     hipError_t e = scan_exclusive(w, w.hist, w.hist, 256ll * tiles, nullptr, s);
     if (e != hipSuccess) return e;
-    k_rs_scatter<<<tiles, kBlock, 0, s>>>(w.keys[which], w.vals[which], w.keys[which ^ 1], w.vals[which ^ 1], count,
-                                          shift, w.hist, tiles);
+    k_rs_scatter<ITEMS><<<tiles, kBlock, 0, s>>>(w.keys[which], w.vals[which], w.keys[which ^ 1],
+                                                 w.vals[which ^ 1], count, shift, w.hist, tiles);
     which ^= 1;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s) {
+  if (count <= 1) return hipSuccess;
+  return count >= kRsLargeFrom ? radix_passes<kRsItemsLarge>(w, count, total_bits, which, s)
+                               : radix_passes<kRsItemsSmall>(w, count, total_bits, which, s);
 }
 
 hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
@@ -3262,12 +3359,23 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   const unsigned long long *degu = (const unsigned long long *)w.deg;
   int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
   int32_t *list = w.parent;               // free until the union-find
-  const unsigned tg = xcd_grid(grid_for(w.ntiles, 1, 1u << 20));
-  if (bv)
-    k_pr_tile<true><<<tg, kPrTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv, gs);
-  else
-    k_pr_tile<false><<<tg, kPrTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, nullptr,
-                                           nullptr);
+  const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
+  const bool wide = w.ntiles < kXcdChunkMin;
+  if (bv) {
+    if (wide)
+      k_pr_tile<true, kBlock><<<tg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
+                                                    gv, gs);
+    else
+      k_pr_tile_merge<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv,
+                                               gs);
+  } else {
+    if (wide)
+      k_pr_tile<false, kBlock><<<tg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
+                                                     nullptr, nullptr);
+    else
+      k_pr_tile_merge<false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
+                                                nullptr, nullptr);
+  }
   k_pr_list<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, list, w.st);
   const unsigned rg = grid_for(g.nnz / kPrRow + 1, 1, 4096);
   if (bv) {
@@ -3292,7 +3400,7 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
 
 hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s) {
   k_iota<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n);
-  k_uf_tile<<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(g.row_ptr, g.col, w.mark, w.tile_meta, w.ntiles,
+  k_uf_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, w.mark, w.tile_meta, w.ntiles,
                                                                w.parent);
   for (int b = 4; b <= 6; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;

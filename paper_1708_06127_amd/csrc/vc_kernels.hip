@@ -241,6 +241,7 @@ __global__ void k_check_rowptr(const int32_t *rp, int32_t n, int64_t nnz, Status
 __global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st, int32_t *big) {
   __shared__ unsigned long long sh[kBlock / 64];
   __shared__ int32_t s_cnt, s_base;
+  if (st->err) return;  // k_row_pass built no first rows
   const int lane = threadIdx.x & 63;
   unsigned long long rows = 0, arcs = 0;
   for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < ntiles; t0 += (int64_t)gridDim.x * kBlock) {
@@ -298,6 +299,9 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int
 __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, int64_t stride, int32_t *bins,
                            Status *st) {
   __shared__ int32_t cnt[3], base[3];
+  // an invalid row_ptr (flagged by k_check_rowptr, earlier on the stream)
+  // could name tiles outside [0, ntiles): nothing is built from it
+  if (st->err) return;
   for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 <= n; b0 += (int64_t)gridDim.x * kBlock) {
     if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
     __syncthreads();

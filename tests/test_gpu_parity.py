@@ -178,6 +178,12 @@ def test_error_codes_and_recovery():
     with pytest.raises(vc.ViecutError) as e:
         vc.mincut(r2, col, w)
     assert e.value.code == vc.EINVAL
+    # a negative row pointer entry: rejected before any tile is built from it
+    r3 = rp.clone()
+    r3[2] = -1000
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(r3, col, w)
+    assert e.value.code == vc.EINVAL
     # overflow of the total weight
     big = gg.from_edges(3, [(0, 1), (1, 2)], [2**31 - 1, 5])
     with pytest.raises(vc.ViecutError) as e:

@@ -599,16 +599,17 @@ __global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ 
       uint32_t sj = salt;
       if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
       unsigned long long best = 0, sum = 0;
+      int32_t next = s_rp[j + 1];  // end of row j, in a register: read again only when a row ends
 #pragma unroll
       for (int k = 0; k < kPerThread; k++) {
         const int32_t i = i0 + k;
         if (k < q && i < acnt) {
-          if (i >= s_rp[j + 1]) {
+          if (i >= next) {
             atomicMax(&s_best[j], best);
             if (L0) atomicAdd(&s_sum[j], sum);
             best = 0;
             sum = 0;
-            do { j++; } while (i >= s_rp[j + 1]);
+            do { j++; next = s_rp[j + 1]; } while (i >= next);
             if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
           }
           const int32_t x = xs[k], c = cs[k];

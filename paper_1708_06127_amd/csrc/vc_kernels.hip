@@ -2255,7 +2255,7 @@ __global__ __launch_bounds__(TB) void k_pr_tile(const int32_t *__restrict__ rp, 
   }
 }
 
-// The same on large PR graphs (batched unions): one wave per tile, each
+// The same on the large PR graphs of batched unions: one wave per tile, each
 // owned edge merged from the two rows in global memory, which measured
 // faster there than staging the tile's rows in LDS.
 template <bool B>
@@ -3365,7 +3365,9 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   int32_t *heavy = (int32_t *)w.keys[0];  // free between contractions
   int32_t *list = w.parent;               // free until the union-find
   const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
-  const bool wide = w.ntiles < kXcdChunkMin;
+  // single solves always take the LDS variant; the merge variant is for the
+  // large unions of a batch
+  const bool wide = !bv || w.ntiles < kXcdChunkMin;
   if (bv) {
     if (wide)
       k_pr_tile<true, kBlock><<<tg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
@@ -3374,12 +3376,8 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
       k_pr_tile_merge<true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st, gv,
                                                gs);
   } else {
-    if (wide)
-      k_pr_tile<false, kBlock><<<tg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
-                                                     nullptr, nullptr);
-    else
-      k_pr_tile_merge<false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
-                                                nullptr, nullptr);
+    k_pr_tile<false, kBlock><<<tg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,
+                                                   nullptr, nullptr);
   }
   k_pr_list<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, list, w.st);
   const unsigned rg = grid_for(g.nnz / kPrRow + 1, 1, 4096);

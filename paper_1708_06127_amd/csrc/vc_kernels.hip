@@ -1816,9 +1816,49 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
 // pack the segments into buffer 1: output element e comes from the last
 // segment s with off[s] <= e (binary search of the exclusive offsets), so the
 // work is balanced whatever the segment lengths
-__global__ void k_compact(const int32_t *first, const int32_t *off, int32_t nseg, const Status *st,
-                          const unsigned long long *kin, const int32_t *vin, unsigned long long *kout,
-                          int32_t *vout) {
+// A workgroup takes kCompactItems * 256 consecutive output elements. The
+// first wave finds the segments of the range's first and last element, each
+// half-wave by a 32-way search (a probe per lane, the ballot's count narrows
+// the span 32-fold per step); the offsets in between are staged in LDS (at
+// most kCompactWin of them) and every element searches only there. A wider
+// span (long runs of empty segments) searches the global offsets between the
+// two bounds.
+constexpr int kCompactItems = 4;
+constexpr int kCompactWin = 2048;
+constexpr int64_t kCompactDirectMax = 1 << 20;  // segments up to which every element searches alone
+
+// Last segment s in [0, nseg) with off[s] <= t, by the 32 lanes of one half
+// of wave 0 (off nondecreasing, off[0] = 0 <= t). Every lane of the wave calls
+// it; the loop ends when both halves are done.
+__device__ int32_t compact_bound(const int32_t *off, int32_t nseg, int64_t t) {
+  const int half = threadIdx.x >> 5, k = threadIdx.x & 31;
+  int32_t lo = 0, hi = nseg - 1;
+  bool done = false;
+  for (;;) {
+    const int32_t stride = done ? 0 : (hi - lo + 32) >> 5;
+    const int32_t p = lo + k * stride;
+    const bool le = !done && p <= hi && off[p] <= t;
+    const int c = __popc((uint32_t)(__ballot(le) >> (32 * half)));
+    if (!done) {
+      if (stride == 1) {
+        lo += c - 1;
+        done = true;
+      } else {
+        const int32_t nlo = lo + (c - 1) * stride;
+        hi = min(hi, nlo + stride - 1);
+        lo = nlo;
+      }
+    }
+    if (__ballot(!done) == 0) break;
+  }
+  return lo;
+}
+
+// Few segments (their offsets stay in L2): every element searches all the
+// offsets itself, with no barrier or dependent bound search in between.
+__global__ void k_compact_direct(const int32_t *first, const int32_t *off, int32_t nseg, const Status *st,
+                                 const unsigned long long *kin, const int32_t *vin, unsigned long long *kout,
+                                 int32_t *vout) {
   const int64_t total = st->ax;
   for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < total; e += (int64_t)gridDim.x * kBlock) {
     int32_t lo = 0, hi = nseg - 1;
@@ -1829,6 +1869,71 @@ __global__ void k_compact(const int32_t *first, const int32_t *off, int32_t nseg
     const int64_t src = first[lo] + (e - off[lo]);
     kout[e] = kin[src];
     vout[e] = vin[src];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compact(const int32_t *first, const int32_t *off, int32_t nseg,
+                                                    const Status *st, const unsigned long long *kin,
+                                                    const int32_t *vin, unsigned long long *kout, int32_t *vout) {
+  __shared__ int32_t s_off[kCompactWin];
+  __shared__ int32_t s_bound[2];
+  constexpr int kSpan = kBlock * kCompactItems;
+  const int64_t total = st->ax;
+  for (int64_t e0 = blockIdx.x * (int64_t)kSpan; e0 < total; e0 += (int64_t)gridDim.x * kSpan) {
+    if (threadIdx.x < 64) {
+      const int64_t t = threadIdx.x < 32 ? e0 : min<int64_t>(e0 + kSpan, total) - 1;
+      const int32_t b = compact_bound(off, nseg, t);
+      if ((threadIdx.x & 31) == 0) s_bound[threadIdx.x >> 5] = b;
+    }
+    __syncthreads();
+    const int32_t slo = s_bound[0], shi = s_bound[1];
+    const bool win = shi - slo < kCompactWin;
+    if (win)
+      for (int i = threadIdx.x; i <= shi - slo; i += kBlock) s_off[i] = off[slo + i];
+    __syncthreads();
+    int64_t src[kCompactItems];
+#pragma unroll
+    for (int it = 0; it < kCompactItems; it++) {
+      const int64_t e = e0 + it * kBlock + threadIdx.x;
+      src[it] = -1;
+      if (e < total) {
+        int32_t seg, o;
+        if (win) {
+          int32_t lo = 0, hi = shi - slo;
+          while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= e) lo = mid; else hi = mid - 1;
+          }
+          seg = slo + lo;
+          o = s_off[lo];
+        } else {
+          int32_t lo = slo, hi = shi;
+          while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= e) lo = mid; else hi = mid - 1;
+          }
+          seg = lo;
+          o = off[lo];
+        }
+        src[it] = first[seg] + (e - o);
+      }
+    }
+    unsigned long long kv[kCompactItems];
+    int32_t vv[kCompactItems];
+#pragma unroll
+    for (int it = 0; it < kCompactItems; it++) {
+      const int64_t sc = src[it] < 0 ? 0 : src[it];
+      kv[it] = kin[sc];
+      vv[it] = vin[sc];
+    }
+#pragma unroll
+    for (int it = 0; it < kCompactItems; it++) {
+      if (src[it] < 0) continue;
+      const int64_t e = e0 + it * kBlock + threadIdx.x;
+      kout[e] = kv[it];
+      vout[e] = vv[it];
+    }
+    __syncthreads();
   }
 }
 
@@ -3289,8 +3394,12 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
   }
   e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
   if (e != hipSuccess) return e;
-  k_compact<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st, w.keys[0],
-                                                              w.vals[0], w.keys[1], w.vals[1]);
+  if (nseg <= kCompactDirectMax)
+    k_compact_direct<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st,
+                                                                       w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
+  else
+    k_compact<<<grid_for(g.nnz, kBlock * kCompactItems, 4096), kBlock, 0, s>>>(
+        w.seg, w.seg_cnt, (int32_t)nseg, w.st, w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
   return hipGetLastError();
 }
 

@@ -143,6 +143,25 @@ def test_batch_c4_members_vs_single_path():
             assert got(g, *r) == expect(g, kw), members[i]
 
 
+def test_batch_c4_full_sample():
+    """The whole 4,096-graph planted batch in one call (9.4 million segments at
+    the first contraction: the LDS-window compaction): sampled members ==
+    the single-graph path, and a few == the oracle."""
+    import torch
+    gs = gg.c4_batch(4096)
+    log("c4 full batch generated", sum(g.nnz for g in gs))
+    dev = [to_dev(g) for g in gs]
+    kw = dict(lp_iters=2, n0=64, seed=0)
+    res = vc.mincut_batch(dev, **kw)
+    for i in range(0, 4096, 97):
+        one = vc.mincut(*dev[i], **kw)
+        assert got(gs[i], *res[i]) == got(gs[i], *one), (i, gs[i].n)
+        if i % 1067 == 0:
+            assert got(gs[i], *res[i]) == expect(gs[i], kw), i
+    del dev, res
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------ sessions
 def test_session_staggered_arrivals(mixed):
     """Requests submitted while others are in flight join at the next step;

@@ -2195,8 +2195,8 @@ __global__ void k_witness(const int32_t *map, int32_t n_in, const Status *st, un
 //  * rows shorter than kPrRow arcs, in the tiles: the owner's thread merges
 //    the two short rows;
 //  * rows of kPrRow..kPrLds arcs: a workgroup per row holds the row in an LDS
-//    hash table (neighbour -> weight); one wave per owned arc scans the other
-//    (not longer) row in 64-wide chunks and probes the table;
+//    hash table (neighbour -> weight); a 16-lane group per owned arc scans
+//    the other (not longer) row and probes the table;
 //  * rows longer than kPrLds: owned arcs that the cheap tests leave open are
 //    queued; a wave per arc binary-searches the long row for the other row's
 //    entries, 64 at a time.
@@ -2443,11 +2443,12 @@ __global__ void k_pr_list(const int32_t *rp, int32_t n, int32_t *list, Status *s
   }
 }
 
-// A workgroup per listed row v: v's row in an LDS hash table of 2 |row|
+// A workgroup per listed row v: v's row in an LDS hash table of 2-4 |row|
 // slots; one 16-lane group per owned arc (v, x) scans x's row against it,
 // 16 entries at a time (4 arcs in flight per wave, loads still coalesced).
 // Partial sums are 32-bit: c + sum <= deg(v) <= total weight <= INT32_MAX.
 constexpr int kPrGroup = 16;  // lanes per owned arc in k_pr_rows
+constexpr int kPrBuckets = 8;  // length classes of the other row: < 16, 16-31, ..., 512-1023, >= 1024
 
 // Sum / or over each aligned row of 16 lanes with DPP moves (no LDS): after
 // the two quad permutations a lane holds its quad's value, row_half_mirror
@@ -2487,6 +2488,7 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
   __shared__ int s_any;
   // owned arcs of the current chunk that need the common neighbourhood
   __shared__ int32_t s_nwork;
+  __shared__ int32_t s_bcnt[kPrBuckets], s_bbase[kPrBuckets];
   __shared__ int32_t s_wi[kBlock], s_wb[kBlock], s_we[kBlock], s_wc[kBlock];
   __shared__ long long s_wd[kBlock];
   constexpr int G = kPrGroup;
@@ -2496,9 +2498,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
   for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
     const int32_t v = which == 0 ? list[r] : list[n - 1 - r];
     const int32_t vb = rp[v], ve = rp[v + 1], lv = ve - vb;
-    // power-of-two table of at least 2 |row| slots (TBL is a power of two >= 2 |row|)
+    // power-of-two table of 4 |row| slots or TBL, whichever is smaller (TBL
+    // is a power of two >= 2 |row|): load factor at most 1/2, mostly 1/4, so
+    // a miss (most probes) rarely takes a second slot
     uint32_t size = 64;
-    while (size < 2u * (uint32_t)lv) size <<= 1;
+    while (size < 4u * (uint32_t)lv && size < (uint32_t)TBL) size <<= 1;
     const uint32_t mask = size - 1;
     const int32_t g = B ? gv[v] : 0;
     const long long lam = B ? graph_lam(gs[g]) : st->lam_hat;
@@ -2516,26 +2520,27 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
     bool any = false;
     // The row's arcs in chunks of kBlock: every thread decides the cheap
     // cases of one arc and lists the owned arcs that need the common
-    // neighbourhood; the groups then share that list evenly.
+    // neighbourhood, grouped by the length class of the other row, so that
+    // the four groups of a wave scan rows of similar length together; the
+    // groups then share that list evenly.
     for (int32_t c0 = vb; c0 < ve; c0 += kBlock) {
-      if (threadIdx.x == 0) s_nwork = 0;
+      if (threadIdx.x < kPrBuckets) s_bcnt[threadIdx.x] = 0;
       __syncthreads();
       const int32_t i = c0 + (int32_t)threadIdx.x;
+      int32_t xb = 0, xe = 0, c = 0, bk = -1, rank = 0;
+      long long dx = 0;
       if (i < ve) {
         const int32_t x = col[i];
-        const int32_t xb = rp[x], xe = rp[x + 1];
+        xb = rp[x];
+        xe = rp[x + 1];
         bool mk = false;
         if (pr_owner(v, lv, x, xe - xb) && lam >= 0) {
-          const int32_t c = w[i];
-          const long long dx = (long long)degu[x];
+          c = w[i];
+          dx = (long long)degu[x];
           mk = pr_cheap(c, dv, dx, lam);
           if (!mk) {
-            const int32_t k = atomicAdd(&s_nwork, 1);
-            s_wi[k] = i;
-            s_wb[k] = xb;
-            s_we[k] = xe;
-            s_wc[k] = c;
-            s_wd[k] = dx;
+            bk = min(kPrBuckets - 1, max(0, 28 - __clz(xe - xb)));  // floor(log2 length) - 3, clamped
+            rank = atomicAdd(&s_bcnt[bk], 1);
           }
         }
         mark[i] = mk ? 1 : 0;
@@ -2543,6 +2548,24 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
           any = true;
           if constexpr (B) flag_marked(gs, g, flagged);
         }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int b = 0; b < kPrBuckets; b++) {
+          s_bbase[b] = acc;
+          acc += s_bcnt[b];
+        }
+        s_nwork = acc;
+      }
+      __syncthreads();
+      if (bk >= 0) {
+        const int32_t k = s_bbase[bk] + rank;
+        s_wi[k] = i;
+        s_wb[k] = xb;
+        s_we[k] = xe;
+        s_wc[k] = c;
+        s_wd[k] = dx;
       }
       __syncthreads();
       const int32_t nwork = s_nwork;
@@ -3491,12 +3514,12 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   k_pr_list<<<grid_for(g.n, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, list, w.st);
   const unsigned rg = grid_for(g.nnz / kPrRow + 1, 1, 4096);
   if (bv) {
-    k_pr_rows<2 * kPrSmallMax, true><<<rg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, list, 0, g.n, w.mark, w.st,
+    k_pr_rows<4 * kPrSmallMax, true><<<rg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, list, 0, g.n, w.mark, w.st,
                                                             gv, gs);
     k_pr_rows<2 * kPrLds, true><<<grid_for(g.nnz / kPrSmallMax + 1, 1, 1024), kBlock, 0, s>>>(
         g.row_ptr, g.col, g.w, degu, list, 1, g.n, w.mark, w.st, gv, gs);
   } else {
-    k_pr_rows<2 * kPrSmallMax, false><<<rg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, list, 0, g.n, w.mark,
+    k_pr_rows<4 * kPrSmallMax, false><<<rg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, list, 0, g.n, w.mark,
                                                              w.st, nullptr, nullptr);
     k_pr_rows<2 * kPrLds, false><<<grid_for(g.nnz / kPrSmallMax + 1, 1, 1024), kBlock, 0, s>>>(
         g.row_ptr, g.col, g.w, degu, list, 1, g.n, w.mark, w.st, nullptr, nullptr);

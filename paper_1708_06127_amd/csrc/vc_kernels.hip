@@ -2578,21 +2578,30 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
           // (dv < 2(c + a) <=> a > floor(dv/2) - c); the thresholds are clamped to
           // int32 (weights are positive int32), so the comparisons stay 32-bit
           const int32_t tv = clamp_i32(dv / 2 - c), tx = clamp_i32(dx / 2 - c);
-          // x's row in blocks of U chunks of G entries: all loads of a block
-          // first, then the first probes, then the rare longer probes; one
-          // reduction per block. The decision is the same as entry by
-          // entry: the sums only grow.
+          // x's row in blocks of U chunks of G entries: the next block's
+          // loads are issued before this block is probed (first probes, then
+          // the rare longer ones); one reduction per block. The decision is
+          // the same as entry by entry: the sums only grow.
           constexpr int U = 4;
           long long sum4 = c;
           int pr3 = 0;
-          for (int32_t j0 = xb; j0 < xe; j0 += U * G) {
-            int32_t uu[U], wx[U], kk[U];
-            uint32_t hh[U];
+          int32_t uu[U], wx[U];
 #pragma unroll
-            for (int q = 0; q < U; q++) {
-              const int32_t j = min(j0 + q * G + lane, xe - 1);
-              uu[q] = col[j];
-              wx[q] = w[j];
+          for (int q = 0; q < U; q++) {
+            const int32_t j = min(xb + q * G + lane, xe - 1);
+            uu[q] = col[j];
+            wx[q] = w[j];
+          }
+          for (int32_t j0 = xb; j0 < xe; j0 += U * G) {
+            int32_t nu[U] = {}, nw[U] = {}, kk[U];
+            uint32_t hh[U];
+            if (j0 + U * G < xe) {
+#pragma unroll
+              for (int q = 0; q < U; q++) {
+                const int32_t j = min(j0 + U * G + q * G + lane, xe - 1);
+                nu[q] = col[j];
+                nw[q] = w[j];
+              }
             }
 #pragma unroll
             for (int q = 0; q < U; q++) {
@@ -2619,6 +2628,11 @@ __global__ __launch_bounds__(kBlock) void k_pr_rows(const int32_t *__restrict__ 
             sum4 += part;
             pr3 |= p3;
             if (pr3 || sum4 >= lam) break;  // decided
+#pragma unroll
+            for (int q = 0; q < U; q++) {
+              uu[q] = nu[q];
+              wx[q] = nw[q];
+            }
           }
           mk = pr3 || sum4 >= lam;
         }

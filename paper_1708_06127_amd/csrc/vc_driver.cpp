@@ -260,9 +260,24 @@ struct Solver {
 
   Solver(Work &w_, hipStream_t s_, const viecut_params &p_) : w(w_), s(s_), p(p_) {}
 
+  // Page-locked landing buffer for the status copies, one per host thread
+  // (a thread's solves run one after another), allocated on first use and
+  // kept for the life of the process: a copy into pageable memory goes
+  // through the runtime's staging buffer and a host copy after the wait.
+  static Status *pinned_status() {
+    static thread_local Status *h = nullptr;
+    if (!h) {
+      void *q = nullptr;
+      if (hipHostMalloc(&q, sizeof(Status), 0) == hipSuccess) h = (Status *)q;
+    }
+    return h;
+  }
+
   int sync_status() {
-    VC_TRY(hipMemcpyAsync(&st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
+    Status *h = pinned_status();
+    VC_TRY(hipMemcpyAsync(h ? h : &st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
+    if (h) st = *h;
     if (st.err & ERR_DEVICE) return VIECUT_EDEVICE;
     return VIECUT_OK;
   }

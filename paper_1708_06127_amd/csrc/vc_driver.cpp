@@ -273,6 +273,29 @@ struct Solver {
     return h;
   }
 
+  // Page-locked staging for the kernel graph's hand-off to the host solve
+  // (and the side flags back), one per host thread, grown on demand up to
+  // 16 MiB and kept; larger hand-offs use pageable copies. Every use ends
+  // with a stream wait before the buffer is touched again.
+  static char *pinned_stage(size_t bytes) {
+    static thread_local void *buf = nullptr;
+    static thread_local size_t cap = 0;
+    if (bytes > ((size_t)16 << 20)) return nullptr;
+    if (bytes > cap) {
+      if (buf) (void)hipHostFree(buf);
+      buf = nullptr;
+      cap = 0;
+      size_t want = (size_t)1 << 16;
+      while (want < bytes) want <<= 1;
+      if (hipHostMalloc(&buf, want, 0) != hipSuccess) {
+        buf = nullptr;
+        return nullptr;
+      }
+      cap = want;
+    }
+    return (char *)buf;
+  }
+
   int sync_status() {
     Status *h = pinned_status();
     VC_TRY(hipMemcpyAsync(h ? h : &st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
@@ -461,15 +484,41 @@ struct Solver {
     int32_t out_level = st.wit_level;
     bool from_kernel = false;
     if (!done && !(status & (ST_COLLAPSED | ST_DISCONNECTED)) && G.n >= 2) {
-      std::vector<int32_t> rp = d2h(G.row_ptr, (int64_t)G.n + 1);
-      std::vector<int32_t> col = d2h(G.col, G.nnz), ww = d2h(G.w, G.nnz);
+      const size_t b_rp = sizeof(int32_t) * ((size_t)G.n + 1), b_arc = sizeof(int32_t) * (size_t)G.nnz;
+      char *stg = pinned_stage(b_rp + 2 * b_arc);
+      std::vector<int32_t> rp, col, ww;
+      if (stg) {  // three copies, one wait
+        rp.resize((size_t)G.n + 1);
+        col.resize((size_t)G.nnz);
+        ww.resize((size_t)G.nnz);
+        VC_TRY(hipMemcpyAsync(stg, G.row_ptr, b_rp, hipMemcpyDeviceToHost, s));
+        if (b_arc) {
+          VC_TRY(hipMemcpyAsync(stg + b_rp, G.col, b_arc, hipMemcpyDeviceToHost, s));
+          VC_TRY(hipMemcpyAsync(stg + b_rp + b_arc, G.w, b_arc, hipMemcpyDeviceToHost, s));
+        }
+        VC_TRY(hipStreamSynchronize(s));
+        std::memcpy(rp.data(), stg, b_rp);
+        if (b_arc) {
+          std::memcpy(col.data(), stg + b_rp, b_arc);
+          std::memcpy(ww.data(), stg + b_rp + b_arc, b_arc);
+        }
+      } else {
+        rp = d2h(G.row_ptr, (int64_t)G.n + 1);
+        col = d2h(G.col, G.nnz);
+        ww = d2h(G.w, G.nnz);
+      }
       std::vector<uint8_t> kside((size_t)G.n);
       int64_t lk = stoer_wagner_host(G.n, rp.data(), col.data(), ww.data(), kside.data());
       if (lk < cut) {
         cut = lk;
         out_level = -1;
         from_kernel = true;
-        VC_TRY(hipMemcpyAsync(w.flags8, kside.data(), (size_t)G.n, hipMemcpyHostToDevice, s));
+        const uint8_t *src = kside.data();
+        if (stg) {  // n flag bytes fit in the row-pointer part of the stage
+          std::memcpy(stg, kside.data(), (size_t)G.n);
+          src = (const uint8_t *)stg;
+        }
+        VC_TRY(hipMemcpyAsync(w.flags8, src, (size_t)G.n, hipMemcpyHostToDevice, s));
         VC_TRY(side_from_flags(w, w.flags8, side, s));
       }
     }

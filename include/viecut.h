@@ -131,7 +131,10 @@ size_t viecut_workspace_bytes(int32_t n, int32_t nnz, const viecut_params *p);
  * device array of ceil(n/64) uint64 words; on success bit (u & 63) of word
  * (u >> 6) is 1 iff vertex u is on the side NOT containing vertex 0 (padding
  * bits 0). out: host struct. The call returns when the result is final
- * (the exact solve runs on the host). One call at a time per workspace. */
+ * (the exact solve runs on the host). One call at a time per workspace.
+ * The calling thread keeps a small page-locked host buffer (the status
+ * reads, and kernel-graph hand-offs up to 16 MiB) for the rest of the
+ * process; larger hand-offs use pageable copies. */
 int viecut_mincut(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
                   viecut_result *out, uint64_t *side);
 

@@ -533,3 +533,59 @@ def test_lp_tie_rule_over_several_rounds(seed):
             elif ev["kind"] == oracle.EV_CONTRACT:
                 cur = _csr_of(ev)
         check_result(g, r)
+
+
+def two_blocks(seed):
+    """Two dense blocks (heavier inside) joined by 1-3 light edges, so the
+    minimum cut is usually below the minimum degree."""
+    rng = np.random.default_rng(seed)
+    sizes = [int(rng.integers(3, 7)), int(rng.integers(3, 7))]
+    n = sum(sizes)
+    wmax = int(rng.choice([2, 3, 6]))
+    pairs, ws = [], []
+    for lo, sz in ((0, sizes[0]), (sizes[0], sizes[1])):
+        for x, y in itertools.combinations(range(lo, lo + sz), 2):
+            if y == x + 1 or rng.random() < 0.75:
+                pairs.append((x, y))
+                ws.append(int(rng.integers(1, wmax + 1)))
+    for _ in range(int(rng.integers(1, 4))):
+        x, y = int(rng.integers(0, sizes[0])), int(rng.integers(sizes[0], n))
+        pairs.append((x, y))
+        ws.append(1)
+    return gg.from_edges(n, pairs, ws)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_every_pr_mark_keeps_the_result(seed):
+    """Padberg-Rinaldi soundness, edge by edge: contracting any single edge
+    that the first PR pass marks keeps min(lambda(G/e), lambda-hat) equal to
+    lambda(G) (a minimum cut survives the contraction, or the bound already
+    equals lambda). Brute force on G and on every G/e; the inputs are mostly
+    two blocks whose light joining edges make lambda < lambda-hat, where
+    every mark must keep a minimum cut."""
+    if seed % 4 == 3:
+        rng = np.random.default_rng(5000 + seed)
+        n = int(rng.integers(4, 12))
+        g = random_graph(n, float(rng.uniform(0.2, 0.9)), int(rng.choice([1, 2, 3, 10])), 5000 + seed)
+    else:
+        g = two_blocks(5000 + seed)
+    n = g.n
+    lam, _ = brute_mincut(g)
+    r = oracle.mincut_graph(g, lp_iters=0, n0=1, trace=True)
+    pr = [e for e in r.events if e["kind"] == oracle.EV_PR][0]
+    lam_hat = pr["lam_hat"]
+    assert lam_hat >= lam
+    marked = {(min(a, int(g.col[i])), max(a, int(g.col[i])))
+              for a in range(n) for i in range(g.row_ptr[a], g.row_ptr[a + 1]) if pr["mark"][i]}
+    u, v, w = edges_of(g.row_ptr, g.col, g.w)
+    for a, b in sorted(marked):
+        def ren(x):  # b merged into a, the ids above b shifted down
+            return a if x == b else (x - 1 if x > b else x)
+        pairs, ws = [], []
+        for x, y, c in zip(u.tolist(), v.tolist(), w.tolist()):
+            p, q = ren(x), ren(y)
+            if p != q:
+                pairs.append((min(p, q), max(p, q)))
+                ws.append(c)
+        lam_e = brute_mincut(gg.from_edges(n - 1, pairs, ws))[0] if pairs else 0
+        assert min(lam_e, lam_hat) == lam, ((a, b), lam_e, lam_hat, lam)

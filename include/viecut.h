@@ -11,7 +11,7 @@
  * solve on the small remaining graph and a transfer of its cut back to the
  * input (Algorithm 1, appendix A).
  *
- * What is returned follows the problem statement (Section 2): a cut
+ * What is returned follows the problem statement (Section 3, Preliminaries): a cut
  * (A, V \ A) with both sides non-empty and its capacity c(A) = the summed
  * weight of the edges between A and V \ A. The value is never below the
  * minimum cut lambda(G) (contraction only removes cuts) and never above the
@@ -47,7 +47,8 @@ enum {
   VIECUT_OK = 0,
   VIECUT_EINVAL = -1,    /* bad argument: n < 2, bad row_ptr, column out of range or a self loop, bad params */
   VIECUT_EWEIGHT = -2,   /* an edge weight < 1 */
-  VIECUT_EOVERFLOW = -3, /* total weight (sum over edges) > INT32_MAX, or nnz >= 2^31 */
+  VIECUT_EOVERFLOW = -3, /* total weight (sum over edges) > INT32_MAX, nnz >= 2^31, or more than
+                            VIECUT_MAX_VERTICES vertices (per graph, and summed over a batch) */
   VIECUT_ENOMEM = -4,    /* workspace too small, or device allocation failed */
   VIECUT_EDEVICE = -5,   /* a HIP runtime call failed */
   VIECUT_ENOTSYM = -6,   /* (with VIECUT_F_VALIDATE) not symmetric, or a row not strictly increasing */
@@ -61,6 +62,12 @@ enum {
   VIECUT_ST_NO_PROGRESS = 4,  /* a round did not shrink the graph; the exact solve ran on what remained */
   VIECUT_ST_MAX_ROUNDS = 8    /* max_rounds reached before the graph got to n0 vertices */
 };
+
+/* Largest vertex count the library accepts: one graph of at most 2^30 vertices, and at most
+ * 2^30 vertices plus graphs summed over the graphs of one batch (label gathers address the
+ * label array with 32-bit byte offsets). Larger inputs return VIECUT_EOVERFLOW before any
+ * device work. */
+#define VIECUT_MAX_VERTICES (1 << 30)
 
 /* params.flags */
 enum {
@@ -82,7 +89,9 @@ typedef struct {
   const int32_t *w;
 } viecut_csr;
 
-/* Method parameters (Section 4.1 / Algorithm 1):
+/* Method parameters (label propagation bounded to l iterations and the loop down to n0
+ * vertices: Section 4.1 and Algorithm 1 in appendix A; the defaults are the paper's
+ * configuration in Section 5):
  *   lp_iters   - label-propagation iterations per round (the paper's l; 2). 0 disables clustering.
  *   n0         - bound for the exact solve: rounds run while more than n0 vertices remain (10000).
  *   max_rounds - safety cap on rounds (64).
@@ -123,10 +132,16 @@ typedef struct {
 void viecut_default_params(viecut_params *p);
 
 /* Device workspace (bytes) that viecut_mincut needs for a graph of n vertices
- * and nnz arcs. Returns 0 for invalid sizes. */
+ * and nnz arcs: two coarse CSR levels, labels, the contraction's sort buffers
+ * and the Padberg-Rinaldi marks (about 73 bytes per arc plus 80 per vertex).
+ * Returns 0 for invalid sizes (n < 2, nnz < 0, n > VIECUT_MAX_VERTICES). */
 size_t viecut_workspace_bytes(int32_t n, int32_t nnz, const viecut_params *p);
 
-/* Solves one graph. ws: device workspace of at least viecut_workspace_bytes()
+/* Solves one graph with the whole method (Algorithm 1 in appendix A: label
+ * propagation and cluster contraction of Section 4.1, the Padberg-Rinaldi
+ * contraction of Section 4.1, the minimum-degree bound of Section 4, the
+ * exact solve of the remaining graph and the transfer of its cut).
+ * g: device CSR as above. p: parameters (host). ws: device workspace of at least viecut_workspace_bytes()
  * bytes (NULL: the library allocates and frees it inside the call). side:
  * device array of ceil(n/64) uint64 words; on success bit (u & 63) of word
  * (u >> 6) is 1 iff vertex u is on the side NOT containing vertex 0 (padding
@@ -159,22 +174,31 @@ typedef struct {
 } viecut_event;
 typedef void (*viecut_trace_fn)(void *user, const viecut_event *ev);
 
-/* viecut_mincut with a host callback receiving every intermediate state
+/* viecut_mincut (same method and arguments) with a host callback receiving every intermediate state
  * (for parity checking and debugging; it synchronises and copies at every
  * step, so it is slow). */
 int viecut_mincut_trace(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
                         viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user);
 
-/* Checks g on the device (row_ptr, column range, self loops, weights, total
- * weight; with VIECUT_F_VALIDATE in flags also symmetry and sorted rows)
- * without solving. Returns VIECUT_OK or the error code viecut_mincut would. */
+/* Checks g on the device against the input contract of the problem statement
+ * (Section 3: an undirected graph with positive integer edge weights, stored as
+ * a symmetric CSR): row_ptr, column range, self loops, weights, total weight;
+ * with VIECUT_F_VALIDATE in flags also symmetry and sorted rows. Does not
+ * solve. Allocates a temporary workspace of viecut_workspace_bytes() and frees
+ * it before returning. Returns VIECUT_OK or the error code viecut_mincut would. */
 int viecut_validate(const viecut_csr *g, uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------ batching */
-/* Workspace for solving `count` graphs together. */
+/* Device workspace (bytes) for solving the `count` graphs of gs together with
+ * viecut_mincut_batch (the union of their CSRs and per-graph state; the method
+ * is Algorithm 1 per graph). Graphs that fail the host argument checks are not
+ * counted. Returns 0 if the union exceeds VIECUT_MAX_VERTICES vertices or
+ * 2^31 - 1 arcs. */
 size_t viecut_batch_workspace_bytes(const viecut_csr *gs, int32_t count, const viecut_params *p);
 
-/* Solves `count` independent graphs in one batched execution (all graphs
+/* Solves `count` independent graphs in one batched execution, each with the
+ * method of viecut_mincut (Algorithm 1; the paper motivates many small cut
+ * problems with the separation step of branch-and-cut solvers, Section 1) (all graphs
  * advance round by round together; each graph's arithmetic and result are
  * identical to viecut_mincut on it alone). gs: host array of descriptors
  * (device pointers inside). outs: host array of count results. sides: host
@@ -185,22 +209,40 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
                         void *stream, viecut_result *outs, uint64_t *const *sides);
 
 /* ------------------------------------------------------------ serving */
-/* A session keeps admitted graphs resident and advances all of them by one
+/* Serving of the same method (Algorithm 1 per request; applications in
+ * Section 1). A session keeps admitted graphs resident and advances all of them by one
  * batched round per step (continuous batching): requests submitted while
  * others are in flight join at the next step once their workspace fits in
  * the budget; finished requests release their workspace. */
 typedef struct viecut_session viecut_session;
 
-/* hbm_budget: bytes of device memory the session may hold for workspaces. */
+/* Creates a session (Algorithm 1 per request). hbm_budget: bytes of device
+ * memory the session allocates once here for its union workspace (vertices and
+ * arcs in a 1 : 4 ratio, up to 4096 requests in flight). p: parameters of every
+ * request (host, copied). stream: the stream all of the session's work runs
+ * on. *out receives the handle. Returns VIECUT_EBUDGET if the budget holds no
+ * graph at all, VIECUT_ENOMEM if the allocation fails. */
 int viecut_session_create(size_t hbm_budget, const viecut_params *p, void *stream, viecut_session **out);
-/* Queues a request. g's arrays and side (ceil(n/64) device words) must stay
- * valid until the request is polled. Returns VIECUT_EBUDGET if it can never fit. */
+/* Queues a request (a graph as in viecut_mincut; Section 3's input). g's
+ * arrays and side (ceil(n/64) device words) are owned by the caller and must
+ * stay valid until the request is polled. request_id is returned by poll.
+ * Host argument errors return the viecut_mincut code; device-detected input
+ * errors are reported per request by poll. Returns VIECUT_EBUDGET if it can
+ * never fit in the session's workspace. */
 int viecut_session_submit(viecut_session *s, const viecut_csr *g, uint64_t *side, int64_t request_id);
-/* Admits what fits, runs one round for every active request, finishes those
- * that are done. *n_active receives the number of requests still in flight or queued. */
+/* Admits queued requests that fit, runs one round of the method (label
+ * propagation, cluster contraction, Padberg-Rinaldi contraction, bounds:
+ * Section 4.1) for every active request, exact-solves and finishes those that
+ * left the loop (Algorithm 1's last steps). Returns after the round's device
+ * work is enqueued and the finished requests' results are final.
+ * *n_active receives the number of requests still in flight or queued. */
 int viecut_session_step(viecut_session *s, int32_t *n_active);
-/* Retrieves up to max finished requests (ids and results); returns how many. */
+/* Retrieves up to max finished requests into the host arrays ids and outs
+ * (results as viecut_mincut's; an input error shows as status_bits
+ * 0x80000000 | -code). Returns how many, or VIECUT_EINVAL. */
 int viecut_session_poll(viecut_session *s, int64_t *ids, viecut_result *outs, int32_t max);
+/* Waits for the session's stream and frees its workspace; requests not yet
+ * polled are dropped. */
 void viecut_session_destroy(viecut_session *s);
 
 /* ------------------------------------------------------------ kernel timing */
@@ -213,7 +255,8 @@ void viecut_session_destroy(viecut_session *s);
  *   k_first_tile_level0 8 B per arc + 16 B per row (also the weighted degree) + 16 B per tile
  *   k_lp_tile           12 B per arc (col, w, neighbour label) + 12 B per row (row_ptr, own
  *                       label, new label) + 16 B per tile
- * Timing adds two event records and a 16-byte copy per timed launch. */
+ * Timing adds two event records per timed launch; the launch's kernel writes
+ * the tile totals (16 bytes) into page-locked host memory itself. */
 typedef struct {
   char name[32];     /* kernel name */
   int64_t launches;  /* timed launches since viecut_profile_enable(1) */

@@ -11,7 +11,7 @@
 //
 // Paper references are to Henzinger, Noe, Schulz, Strash, "Practical Minimum
 // Cut Algorithms" (arXiv 1708.06127):
-//   * problem statement, cut capacity, lambda, trivial cut bound:  Section 2
+//   * problem statement, cut capacity, lambda, trivial cut bound:  Section 3
 //     "Preliminaries";
 //   * upper bound lambda-hat = minimum weighted degree, lowered after every
 //     contraction:  Section 4 (introduction);
@@ -125,7 +125,7 @@ uint32_t fmix32(uint32_t h) {
 
 uint32_t prio(uint64_t s, int32_t x) { return fmix32((uint32_t)x ^ (uint32_t)(s & 0xFFFFFFFFULL)); }
 
-// Weighted degree c(v): sum of the weights of v's incident edges (Section 2).
+// Weighted degree c(v): sum of the weights of v's incident edges (Section 3, Preliminaries).
 std::vector<int64_t> degrees(const Graph &g) {
   std::vector<int64_t> deg(g.n, 0);
   for (int32_t v = 0; v < g.n; v++)

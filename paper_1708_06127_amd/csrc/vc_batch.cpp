@@ -230,7 +230,8 @@ struct Engine {
     cap.a = std::max<int64_t>(cap.a, 1);
     cap.s = std::max(cap.s, 1);
     cap.w = std::max(cap.w, 1);
-    if (cap.a >= INT32_MAX || (int64_t)cap.n + cap.s >= INT32_MAX || 64ll * cap.w >= INT32_MAX) return VIECUT_EOVERFLOW;
+    if (cap.a >= INT32_MAX || (int64_t)cap.n + cap.s > kMaxVertices || 64ll * cap.w >= INT32_MAX)
+      return VIECUT_EOVERFLOW;
     const size_t need = engine_bytes(cap);
     if (!buf) {
       if (hipMalloc(&buf, need) != hipSuccess) return VIECUT_ENOMEM;
@@ -693,7 +694,7 @@ size_t viecut_batch_workspace_bytes(const viecut_csr *gs, int32_t count, const v
     c.w += (gs[i].n + 63) / 64;
     c.s += 1;
   }
-  if (c.a >= INT32_MAX || (int64_t)c.n + c.s >= INT32_MAX) return 0;
+  if (c.a >= INT32_MAX || (int64_t)c.n + c.s > vc::kMaxVertices || 64ll * c.w >= INT32_MAX) return 0;
   return vc::engine_bytes(c);
 }
 
@@ -716,7 +717,7 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
     c.s += 1;
   }
   if (c.s == 0) return VIECUT_OK;
-  if (c.a >= INT32_MAX || (int64_t)c.n + c.s >= INT32_MAX) return VIECUT_EOVERFLOW;
+  if (c.a >= INT32_MAX || (int64_t)c.n + c.s > vc::kMaxVertices || 64ll * c.w >= INT32_MAX) return VIECUT_EOVERFLOW;
   vc::Engine eng;
   const double ti = vc::now_ms();
   int rc = eng.init(c, q, (hipStream_t)stream, ws, ws_bytes);

@@ -543,6 +543,7 @@ struct Solver {
 int check_args(const viecut_csr *g, const viecut_params *p) {
   if (!g || !p) return VIECUT_EINVAL;
   if (g->n < 2 || g->nnz < 0 || !g->row_ptr) return VIECUT_EINVAL;
+  if (g->n > kMaxVertices) return VIECUT_EOVERFLOW;
   if (g->nnz > 0 && (!g->col || !g->w)) return VIECUT_EINVAL;
   if (p->lp_iters < 0 || p->n0 < 0 || p->max_rounds < 0) return VIECUT_EINVAL;
   return VIECUT_OK;
@@ -594,7 +595,7 @@ void viecut_default_params(viecut_params *p) {
 
 size_t viecut_workspace_bytes(int32_t n, int32_t nnz, const viecut_params *p) {
   (void)p;
-  if (n < 2 || nnz < 0) return 0;
+  if (n < 2 || nnz < 0 || n > vc::kMaxVertices) return 0;
   return vc::work_bytes(n, nnz);
 }
 
@@ -687,7 +688,7 @@ const char *viecut_strerror(int code) {
     case VIECUT_OK: return "ok";
     case VIECUT_EINVAL: return "invalid argument or malformed CSR";
     case VIECUT_EWEIGHT: return "edge weight < 1";
-    case VIECUT_EOVERFLOW: return "total edge weight exceeds INT32_MAX";
+    case VIECUT_EOVERFLOW: return "total edge weight exceeds INT32_MAX, or too many arcs or vertices";
     case VIECUT_ENOMEM: return "workspace too small or device allocation failed";
     case VIECUT_EDEVICE: return "HIP runtime error";
     case VIECUT_ENOTSYM: return "graph not symmetric or rows not strictly increasing";

@@ -11,6 +11,9 @@
 namespace vc {
 
 constexpr int kBlock = 256;   // threads per workgroup everywhere (4 wave64)
+// Largest vertex count of a graph or a batch union: label gathers address the
+// label array with 32-bit byte offsets (4 * x < 2^32).
+constexpr int32_t kMaxVertices = VIECUT_MAX_VERTICES;
 constexpr int kBins = 7;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
 // Row-aligned arc tiles: tile t holds the rows v with rp[v] + v in

@@ -13,11 +13,14 @@
 //    "Padberg-Rinaldi") and a lock-free union-find over marked edges;
 //  * transfer of a side back to the input vertices as a bitmap.
 //
-// Work per vertex is binned by row length: 8/16/32/64 lanes per vertex for
-// short rows (neighbour-label sums in an LDS hash table per group), a whole
-// wave with a 1024-slot table up to 512 arcs, a workgroup with an 8192-slot
-// table up to 4096 arcs, and beyond that rows split into 4096-arc chunks
-// handled by many workgroups that share a global-memory table per row.
+// Work is cut by arc count: rows of fewer than 256 arcs are processed on
+// row-aligned arc tiles (tile t holds the rows v with row_ptr[v] + v in
+// [256 t, 256 (t + 1)), one 64-lane workgroup per tile, each row owning a
+// region of an LDS hash table keyed by neighbour label). Longer rows are
+// listed per level: a wave per row with an LDS table up to 1023 arcs, a
+// workgroup per row with an LDS table up to 4096 arcs, and beyond that rows
+// split into 4096-arc chunks handled by many workgroups that share a
+// global-memory table per row.
 #include "vc_internal.h"
 
 namespace vc {

@@ -21,7 +21,7 @@ def edges_of(row_ptr, col, w):
 
 
 def cut_value(g, side_bool) -> int:
-    """Capacity c(A) of the cut (A, V \\ A) given a bool per vertex (Section 2)."""
+    """Capacity c(A) of the cut (A, V \\ A) given a bool per vertex (Section 3, Preliminaries)."""
     u, v, w = edges_of(g.row_ptr, g.col, g.w)
     s = np.asarray(side_bool, dtype=bool)
     return int(w[s[u] != s[v]].sum())

@@ -56,3 +56,28 @@ def test_invalid_arguments_rejected_on_host():
     g.n = 5
     p.lp_iters = -1
     assert lib.viecut_mincut(ctypes.byref(g), ctypes.byref(p), None, 0, None, ctypes.byref(res), None) == vc.EINVAL
+
+
+def test_vertex_limit_rejected_on_host():
+    """More than 2^30 vertices (label gathers use 32-bit byte offsets) is
+    refused with EOVERFLOW by the host checks, before any device call: the
+    pointers here are never dereferenced, and no GPU is needed."""
+    lib = vc.load()
+    res = vc.Result()
+    p = vc.params()
+    g = vc.Csr()
+    g.n, g.nnz = (1 << 30) + 1, 0
+    g.row_ptr = ctypes.c_void_p(0x1000)
+    side = ctypes.c_void_p(0x2000)
+    assert lib.viecut_mincut(ctypes.byref(g), ctypes.byref(p), None, 0, None, ctypes.byref(res), side) == \
+        vc.EOVERFLOW
+    assert lib.viecut_validate(ctypes.byref(g), 0, None) == vc.EOVERFLOW
+    assert vc.workspace_bytes((1 << 30) + 1, 0) == 0
+    # a batch whose graphs together exceed the limit: the union is refused
+    gs = (vc.Csr * 3)()
+    for i in range(3):
+        gs[i].n, gs[i].nnz, gs[i].row_ptr = (1 << 29) - 4, 0, ctypes.c_void_p(0x1000)
+    outs = (vc.Result * 3)()
+    sides = (ctypes.c_void_p * 3)(0x2000, 0x2000, 0x2000)
+    assert lib.viecut_batch_workspace_bytes(gs, 3, ctypes.byref(p)) == 0
+    assert lib.viecut_mincut_batch(gs, 3, ctypes.byref(p), None, 0, None, outs, sides) == vc.EOVERFLOW

@@ -144,7 +144,7 @@ def test_sw_clique_closed_form(n):
 def check_result(g, r, lam=None):
     """Properties every result must have: the side is non-trivial, excludes
     vertex 0, and its recomputed capacity equals the returned value; the value
-    lies between lambda and the minimum degree (Section 2, Section 4)."""
+    lies between lambda and the minimum degree (Section 3 Preliminaries, Section 4)."""
     side = side_from_words(r.side, g.n)
     assert not side[0]
     assert 0 < side.sum() < g.n

@@ -52,7 +52,8 @@ enum {
   VIECUT_ENOMEM = -4,    /* workspace too small, or device allocation failed */
   VIECUT_EDEVICE = -5,   /* a HIP runtime call failed */
   VIECUT_ENOTSYM = -6,   /* (with VIECUT_F_VALIDATE) not symmetric, or a row not strictly increasing */
-  VIECUT_EBUDGET = -7    /* (sessions) a request larger than the whole memory budget */
+  VIECUT_EBUDGET = -7,   /* (sessions) a request larger than the whole memory budget */
+  VIECUT_ETOOBIG = -8    /* (viecut_mincut_noalloc) the graph's workspace exceeds the static scratch */
 };
 
 /* status_bits of a result */
@@ -173,6 +174,31 @@ typedef struct {
   const int32_t *e;
 } viecut_event;
 typedef void (*viecut_trace_fn)(void *user, const viecut_event *ev);
+
+/* Size of the static device scratch array that serves as the workspace of
+ * viecut_mincut_noalloc: 64 MiB, held by every GPU the library runs on for the
+ * life of the process. A graph fits if viecut_workspace_bytes(n, nnz) is at
+ * most this (about 73 bytes per arc plus 80 per vertex: e.g. 8192 vertices of
+ * average degree 64). */
+#define VIECUT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* viecut_mincut for callers that cannot allocate (tight serving loops,
+ * harnesses that forbid allocation): the same solve with the same results,
+ * without a workspace argument and without allocating anything on the
+ * device or in page-locked host memory (no hipMalloc, hipHostMalloc or
+ * their frees; nothing through torch). Its workspace is a static device array
+ * of VIECUT_NOALLOC_SCRATCH_BYTES per GPU; status reads and the exact solve's
+ * hand-off use ordinary (pageable) host memory. g, p, out and side are as for
+ * viecut_mincut; stream must belong to the current device (NULL: its default
+ * stream). Returns VIECUT_ETOOBIG, before any device work, if
+ * viecut_workspace_bytes(g->n, g->nnz) exceeds the scratch.
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents (the solve clears what must start at zero). Calls that overlapped
+ * on one GPU would race on it, so the library serialises the calls of a
+ * process per device with a lock: a second call waits until the first has
+ * returned. Other processes have arrays of their own. */
+int viecut_mincut_noalloc(const viecut_csr *g, const viecut_params *p, void *stream, viecut_result *out,
+                          uint64_t *side);
 
 /* viecut_mincut (same method and arguments) with a host callback receiving every intermediate state
  * (for parity checking and debugging; it synchronises and copies at every

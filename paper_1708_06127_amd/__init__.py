@@ -22,10 +22,12 @@ from dataclasses import dataclass, field
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libviecut.so")
 
-OK, EINVAL, EWEIGHT, EOVERFLOW, ENOMEM, EDEVICE, ENOTSYM, EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EWEIGHT, EOVERFLOW, ENOMEM, EDEVICE, ENOTSYM, EBUDGET, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8
+NOALLOC_SCRATCH_BYTES = 64 << 20  # VIECUT_NOALLOC_SCRATCH_BYTES
 ST_COLLAPSED, ST_DISCONNECTED, ST_NO_PROGRESS, ST_MAX_ROUNDS = 1, 2, 4, 8
 F_VALIDATE = 1
-EXPORTED = ["viecut_default_params", "viecut_workspace_bytes", "viecut_mincut", "viecut_mincut_trace",
+EXPORTED = ["viecut_default_params", "viecut_workspace_bytes", "viecut_mincut", "viecut_mincut_noalloc",
+            "viecut_mincut_trace",
             "viecut_validate", "viecut_batch_workspace_bytes", "viecut_mincut_batch", "viecut_session_create",
             "viecut_session_submit", "viecut_session_step", "viecut_session_poll", "viecut_session_destroy",
             "viecut_profile_enable", "viecut_profile_read", "viecut_strerror"]
@@ -95,6 +97,8 @@ def load():
     lib.viecut_workspace_bytes.restype = sz
     lib.viecut_mincut.argtypes = [P(Csr), P(Params), vp, sz, vp, P(Result), vp]
     lib.viecut_mincut.restype = ctypes.c_int
+    lib.viecut_mincut_noalloc.argtypes = [P(Csr), P(Params), vp, P(Result), vp]
+    lib.viecut_mincut_noalloc.restype = ctypes.c_int
     lib.viecut_mincut_trace.argtypes = [P(Csr), P(Params), vp, sz, vp, P(Result), vp, TRACE_FN, vp]
     lib.viecut_mincut_trace.restype = ctypes.c_int
     lib.viecut_validate.argtypes = [P(Csr), u32, vp]
@@ -238,6 +242,20 @@ def mincut(row_ptr, col, w, *, lp_iters=2, n0=10000, max_rounds=64, seed=0, vali
     if trace:
         info["events"] = log.events
     return int(res.cut), side, info
+
+
+def mincut_noalloc(row_ptr, col, w, *, side, lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False,
+                   stream=None):
+    """viecut_mincut_noalloc: the same solve on the library's static device
+    scratch (no allocation inside the call; ``side`` must be given).
+    Returns (cut, side, info)."""
+    lib = load()
+    g = csr(row_ptr, col, w)
+    p = params(lp_iters, n0, max_rounds, seed, validate)
+    res = Result()
+    _check(lib.viecut_mincut_noalloc(ctypes.byref(g), ctypes.byref(p), _stream_ptr(stream), ctypes.byref(res),
+                                     side.data_ptr()))
+    return int(res.cut), side, res.as_dict()
 
 
 def validate(row_ptr, col, w, *, check_symmetry=True, stream=None) -> int:

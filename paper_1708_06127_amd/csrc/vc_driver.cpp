@@ -257,6 +257,9 @@ struct Solver {
   const viecut_params &p;
   Tracer tr;
   Status st{};  // host copy
+  // false: no page-locked host buffers (the allocation-free entry point);
+  // status reads and the kernel-graph hand-off use pageable host memory
+  bool pinned = true;
 
   Solver(Work &w_, hipStream_t s_, const viecut_params &p_) : w(w_), s(s_), p(p_) {}
 
@@ -297,7 +300,7 @@ struct Solver {
   }
 
   int sync_status() {
-    Status *h = pinned_status();
+    Status *h = pinned ? pinned_status() : nullptr;
     VC_TRY(hipMemcpyAsync(h ? h : &st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
     VC_TRY(hipStreamSynchronize(s));
     if (h) st = *h;
@@ -485,7 +488,7 @@ struct Solver {
     bool from_kernel = false;
     if (!done && !(status & (ST_COLLAPSED | ST_DISCONNECTED)) && G.n >= 2) {
       const size_t b_rp = sizeof(int32_t) * ((size_t)G.n + 1), b_arc = sizeof(int32_t) * (size_t)G.nnz;
-      char *stg = pinned_stage(b_rp + 2 * b_arc);
+      char *stg = pinned ? pinned_stage(b_rp + 2 * b_arc) : nullptr;
       std::vector<int32_t> rp, col, ww;
       if (stg) {  // three copies, one wait
         rp.resize((size_t)G.n + 1);
@@ -579,6 +582,42 @@ int solve_one(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_b
   return rc;
 }
 
+// The allocation-free single solve: the workspace is the calling device's
+// static scratch array. One call at a time per device: a lock per device
+// serialises the calls of this process, which all share that device's array
+// (it keeps the last call's contents; every buffer that must start cleared is
+// cleared by the solve itself).
+int solve_noalloc(const viecut_csr *g, const viecut_params *p, void *stream, viecut_result *out,
+                  uint64_t *side) {
+  int rc = check_args(g, p);
+  if (rc) return rc;
+  if (!out || !side) return VIECUT_EINVAL;
+  if (work_bytes(g->n, g->nnz) > kScratchBytes) return VIECUT_ETOOBIG;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = -1;
+  VC_TRY(hipGetDevice(&dev));
+  if (s) {
+    hipDevice_t sdev = -1;
+    VC_TRY(hipStreamGetDevice(s, &sdev));
+    if (sdev != dev) return VIECUT_EINVAL;  // the stream must belong to the current device
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices) return VIECUT_EDEVICE;
+  static std::mutex locks[kMaxScratchDevices];
+  std::lock_guard<std::mutex> lk(locks[dev]);
+  void *base = nullptr;
+  VC_TRY(scratch_address(dev, &base));
+  Work w;
+  if (!carve(base, kScratchBytes, g->n, g->nnz, w)) return VIECUT_ETOOBIG;
+  Solver sv(w, s, *p);
+  sv.pinned = false;
+  viecut_result res{};
+  rc = sv.run(*g, &res, side);
+  if (rc != VIECUT_OK) (void)hipStreamSynchronize(s);
+  prof_collect();
+  if (rc == VIECUT_OK) *out = res;
+  return rc;
+}
+
 }  // namespace vc
 
 // ============================================================ C ABI
@@ -607,6 +646,11 @@ int viecut_mincut(const viecut_csr *g, const viecut_params *p, void *ws, size_t 
 int viecut_mincut_trace(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
                         viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user) {
   return vc::solve_one(g, p, ws, ws_bytes, stream, out, side, fn, user);
+}
+
+int viecut_mincut_noalloc(const viecut_csr *g, const viecut_params *p, void *stream, viecut_result *out,
+                          uint64_t *side) {
+  return vc::solve_noalloc(g, p, stream, out, side);
 }
 
 int viecut_validate(const viecut_csr *g, uint32_t flags, void *stream) {
@@ -693,6 +737,7 @@ const char *viecut_strerror(int code) {
     case VIECUT_EDEVICE: return "HIP runtime error";
     case VIECUT_ENOTSYM: return "graph not symmetric or rows not strictly increasing";
     case VIECUT_EBUDGET: return "request exceeds the session memory budget";
+    case VIECUT_ETOOBIG: return "graph needs more workspace than the static scratch of viecut_mincut_noalloc";
     default: return "unknown error";
   }
 }

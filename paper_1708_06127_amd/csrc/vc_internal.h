@@ -14,6 +14,9 @@ constexpr int kBlock = 256;   // threads per workgroup everywhere (4 wave64)
 // Largest vertex count of a graph or a batch union: label gathers address the
 // label array with 32-bit byte offsets (4 * x < 2^32).
 constexpr int32_t kMaxVertices = VIECUT_MAX_VERTICES;
+// Static device scratch of the allocation-free single solve (one per GPU).
+constexpr size_t kScratchBytes = VIECUT_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxScratchDevices = 64;
 constexpr int kBins = 7;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
 // Row-aligned arc tiles: tile t holds the rows v with rp[v] + v in
@@ -278,6 +281,10 @@ void prof_collect();  // after a synchronisation: fold finished records into the
 int check_args(const viecut_csr *g, const viecut_params *p);
 int solve_one(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_bytes, void *stream,
               viecut_result *out, uint64_t *side, viecut_trace_fn fn, void *user);
+
+// device address of the static scratch on `device` (which must be current);
+// looked up on the first call per device and kept
+hipError_t scratch_address(int device, void **ptr);
 
 // host helpers
 uint64_t splitmix64_at(uint64_t seed, uint64_t index);

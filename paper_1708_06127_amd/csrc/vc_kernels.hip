@@ -21,6 +21,8 @@
 // workgroup per row with an LDS table up to 4096 arcs, and beyond that rows
 // split into 4096-arc chunks handled by many workgroups that share a
 // global-memory table per row.
+#include <mutex>
+
 #include "vc_internal.h"
 
 namespace vc {
@@ -3659,6 +3661,30 @@ hipError_t b_side(const SideDesc *d, int32_t count, int32_t words, const int32_t
   if (count <= 0 || words <= 0) return hipSuccess;
   k_side_batch<<<grid_for(64ll * words, kBlock, 8192), kBlock, 0, s>>>(d, count, words, map, wit, flags, wg);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ static scratch
+// Workspace of viecut_mincut_noalloc: a file-scope device array, so that the
+// call needs no allocation. Every GPU the library runs on holds its own copy
+// for the life of the process. In host code `scratch` names a host-side
+// stand-in, never the device memory: kernels and copies get the address that
+// hipGetSymbolAddress returns for the device (scratch_address).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void **ptr) {
+  static std::mutex mu;
+  static void *addr[kMaxScratchDevices] = {};
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {  // once per device, with that device current
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || ((uintptr_t)p & 255)) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 }  // namespace vc

@@ -32,7 +32,7 @@ def test_default_params():
 
 def test_strerror():
     assert vc.strerror(0) == "ok"
-    for code in range(-7, 0):
+    for code in range(-8, 0):
         assert vc.strerror(code) and vc.strerror(code) != "unknown error"
     assert vc.strerror(-99) == "unknown error"
 
@@ -81,3 +81,23 @@ def test_vertex_limit_rejected_on_host():
     sides = (ctypes.c_void_p * 3)(0x2000, 0x2000, 0x2000)
     assert lib.viecut_batch_workspace_bytes(gs, 3, ctypes.byref(p)) == 0
     assert lib.viecut_mincut_batch(gs, 3, ctypes.byref(p), None, 0, None, outs, sides) == vc.EOVERFLOW
+
+
+def test_noalloc_rejects_graphs_beyond_the_scratch_on_host():
+    """viecut_mincut_noalloc refuses, before any device call, a graph whose
+    workspace exceeds the static scratch (ETOOBIG), and takes the same host
+    argument checks as viecut_mincut."""
+    lib = vc.load()
+    res = vc.Result()
+    p = vc.params()
+    g = vc.Csr()
+    g.row_ptr, g.col, g.w = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000)
+    side = ctypes.c_void_p(0x2000)
+    g.n, g.nnz = 1 << 20, 1 << 22
+    assert vc.workspace_bytes(g.n, g.nnz) > vc.NOALLOC_SCRATCH_BYTES
+    assert lib.viecut_mincut_noalloc(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(res), side) == vc.ETOOBIG
+    g.n = 1
+    assert lib.viecut_mincut_noalloc(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(res), side) == vc.EINVAL
+    g.n, g.nnz = 8192, 8192 * 64
+    assert vc.workspace_bytes(g.n, g.nnz) <= vc.NOALLOC_SCRATCH_BYTES  # the largest planted batch member fits
+    assert lib.viecut_mincut_noalloc(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(res), None) == vc.EINVAL

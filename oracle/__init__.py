@@ -20,7 +20,8 @@ _SRC = os.path.join(_HERE, "viecut_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-EV_LP, EV_CONTRACT, EV_BOUND, EV_PR, EV_UF = 1, 2, 3, 4, 5
+EV_LP, EV_CONTRACT, EV_BOUND, EV_PR, EV_UF, EV_FIX = 1, 2, 3, 4, 5, 6
+F_CORRECT = 1
 ST_COLLAPSED, ST_DISCONNECTED, ST_NO_PROGRESS, ST_MAX_ROUNDS = 1, 2, 4, 8
 
 
@@ -62,7 +63,9 @@ def _load():
         lib.oracle_stoer_wagner.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         lib.oracle_mincut.restype = ctypes.c_int
         lib.oracle_mincut.argtypes = [ctypes.c_int32, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                      ctypes.c_uint64, vp, vp, vp, _TRACE_FN, vp]
+                                      ctypes.c_uint64, ctypes.c_uint32, vp, vp, vp, _TRACE_FN, vp]
+        lib.oracle_fix_misplaced.restype = ctypes.c_int
+        lib.oracle_fix_misplaced.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -129,8 +132,22 @@ def stoer_wagner(row_ptr, col, w):
     return int(cut.value), side[:n].astype(bool)
 
 
+def fix_misplaced(row_ptr, col, w, labels):
+    """The correcting step alone on given labels (values in [0, n)); returns the
+    corrected labels (a removed vertex v gets label n + v)."""
+    rp, c, ww = _csr_args(row_ptr, col, w)
+    n = rp.size - 1
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.zeros(max(n, 1), np.int32)
+    rc = _load().oracle_fix_misplaced(n, rp.ctypes.data, c.ctypes.data, ww.ctypes.data, lab.ctypes.data,
+                                      out.ctypes.data)
+    if rc:
+        raise OracleError(rc)
+    return out[:n]
+
+
 def mincut(row_ptr, col, w, lp_iters: int = 2, n0: int = 10000, max_rounds: int = 64, seed: int = 0,
-           trace: bool = False) -> Result:
+           trace: bool = False, correct: bool = False) -> Result:
     """Run the whole method on a host CSR. With ``trace`` every intermediate
     state is recorded as a dict in ``Result.events``."""
     rp, c, ww = _csr_args(row_ptr, col, w)
@@ -145,7 +162,7 @@ def mincut(row_ptr, col, w, lp_iters: int = 2, n0: int = 10000, max_rounds: int 
         ev = evp.contents
         k = ev.kind
         d = {"kind": k, "round": ev.round, "iter": ev.iter, "level": ev.level, "n": ev.n}
-        if k == EV_LP:
+        if k in (EV_LP, EV_FIX):
             d["labels"] = _arr(ev.a, ev.n, np.int32)
         elif k == EV_CONTRACT:
             d["row_ptr"] = _arr(ev.a, ev.n + 1, np.int32)
@@ -166,7 +183,8 @@ def mincut(row_ptr, col, w, lp_iters: int = 2, n0: int = 10000, max_rounds: int 
 
     cb = _TRACE_FN(on_event) if trace else _TRACE_FN()
     rc = _load().oracle_mincut(n, rp.ctypes.data, c.ctypes.data, ww.ctypes.data, int(lp_iters), int(n0),
-                               int(max_rounds), int(seed) & (2**64 - 1), ctypes.addressof(cut), side.ctypes.data,
+                               int(max_rounds), int(seed) & (2**64 - 1), F_CORRECT if correct else 0,
+                               ctypes.addressof(cut), side.ctypes.data,
                                info.ctypes.data, cb, None)
     if rc:
         raise OracleError(rc)

@@ -37,7 +37,16 @@
 //     "only edge" guard of the lemma is not applied.
 //   * lambda-hat is lowered only on a strictly smaller minimum degree; the
 //     witness is the smallest vertex id attaining it at the earliest level.
-//   * The correcting step (fixing misplaced vertices) is not applied.
+//   * The correcting step (fixing misplaced vertices; Section 4.1 and
+//     Algorithm 1's fixMisplacedVertices) runs only when asked for (flag 1).
+//     Reading: after label propagation, a cluster C with
+//     2 <= |C| <= floor(log2 n) (n: vertices of the current graph) loses at
+//     most one vertex: the member v whose removal leaves C minus {v} with the
+//     smallest weighted degree in the contracted graph (smallest v on ties),
+//     and only if that degree is strictly below the minimum weighted degree of
+//     the contracted graph without any correction. The removed vertex becomes
+//     a singleton cluster with label n + v, so coarse ids follow the ordinary
+//     labels first and then the corrected vertices in ascending id.
 //   * The exact solve is Stoer-Wagner: every phase starts at the smallest
 //     surviving id, maximum-adjacency ties go to the smallest id, the last
 //     vertex t is merged into the second-to-last s (s keeps its id), and the
@@ -63,7 +72,8 @@ enum {
   OK = 0, E_INVAL = -1, E_WEIGHT = -2, E_OVERFLOW = -3, E_NOTSYM = -6
 };
 enum { ST_COLLAPSED = 1, ST_DISCONNECTED = 2, ST_NO_PROGRESS = 4, ST_MAX_ROUNDS = 8 };
-enum { EV_LP = 1, EV_CONTRACT = 2, EV_BOUND = 3, EV_PR = 4, EV_UF = 5 };
+enum { EV_LP = 1, EV_CONTRACT = 2, EV_BOUND = 3, EV_PR = 4, EV_UF = 5, EV_FIX = 6 };
+enum { F_CORRECT = 1 };
 
 }  // namespace
 
@@ -75,6 +85,7 @@ extern "C" {
 //   EV_BOUND    lam_hat, witness vertex and level after the update at `level`
 //   EV_PR       a = mark[nnz] (1 on both arcs of a marked edge) on the graph at `level`
 //   EV_UF       a = rep[n] (smallest vertex id of the marked-edge component)
+//   EV_FIX      a = labels[n] after the correcting step of round `round`
 typedef struct {
   int32_t kind, round, iter, level;
   int32_t n, n_prev;
@@ -167,6 +178,48 @@ std::vector<int32_t> label_propagation(const Graph &g, int32_t iters, uint64_t s
     }
   }
   return L;
+}
+
+// The correcting step (Section 4.1, "correcting algorithm": a misplaced
+// vertex is one whose removal from its cluster improves the minimum weighted
+// degree of the contracted graph; only clusters of up to log2(n) vertices are
+// checked), with the reading in the file header. Weighted degrees of clusters
+// are recounted from the arcs for every candidate.
+std::vector<int32_t> fix_misplaced(const Graph &g, const std::vector<int32_t> &L) {
+  std::map<int32_t, std::vector<int32_t>> members;  // label -> vertices, ascending
+  for (int32_t v = 0; v < g.n; v++) members[L[v]].push_back(v);
+  // weighted degree of each cluster in the contracted graph
+  std::map<int32_t, int64_t> cut;
+  for (const auto &kv : members) cut[kv.first] = 0;
+  for (int32_t v = 0; v < g.n; v++)
+    for (int64_t i = g.row[v]; i < g.row[v + 1]; i++)
+      if (L[g.col[i]] != L[v]) cut[L[v]] += g.w[i];
+  int64_t delta_c = INT64_MAX;
+  for (const auto &kv : cut) delta_c = std::min(delta_c, kv.second);
+  int32_t limit = 0;  // floor(log2(n))
+  while (((int64_t)1 << (limit + 1)) <= (int64_t)g.n) limit++;
+  std::vector<int32_t> out(L);
+  for (const auto &kv : members) {
+    const std::vector<int32_t> &mem = kv.second;
+    if (mem.size() < 2 || (int64_t)mem.size() > limit) continue;
+    int64_t best = INT64_MAX;
+    int32_t best_v = -1;
+    for (int32_t v : mem) {
+      // weighted degree of the cluster without v: its edges to every vertex
+      // outside it, v included
+      int64_t c = 0;
+      for (int32_t x : mem) {
+        if (x == v) continue;
+        for (int64_t i = g.row[x]; i < g.row[x + 1]; i++) {
+          const int32_t u = g.col[i];
+          if (L[u] != kv.first || u == v) c += g.w[i];
+        }
+      }
+      if (c < best) { best = c; best_v = v; }
+    }
+    if (best < delta_c) out[best_v] = g.n + best_v;
+  }
+  return out;
 }
 
 // Contract the partition given by `label` (any int32 values): each block
@@ -366,6 +419,24 @@ uint64_t oracle_splitmix64_output(uint64_t seed, uint64_t i) { return splitmix64
 uint32_t oracle_fmix32(uint32_t h) { return fmix32(h); }
 uint32_t oracle_prio(uint64_t s, int32_t x) { return prio(s, x); }
 
+// The correcting step alone on given labels (values in [0, n)); out_labels
+// receives the corrected labels (a removed vertex v gets n + v).
+int oracle_fix_misplaced(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *w,
+                         const int32_t *labels, int32_t *out_labels) {
+  int rc = validate(n, row_ptr, col, w, true);
+  if (rc) return rc;
+  for (int32_t v = 0; v < n; v++)
+    if (labels[v] < 0 || labels[v] >= n) return E_INVAL;
+  Graph g;
+  g.n = n;
+  g.row.assign(row_ptr, row_ptr + n + 1);
+  g.col.assign(col, col + row_ptr[n]);
+  g.w.assign(w, w + row_ptr[n]);
+  std::vector<int32_t> out = fix_misplaced(g, std::vector<int32_t>(labels, labels + n));
+  std::memcpy(out_labels, out.data(), sizeof(int32_t) * (size_t)n);
+  return OK;
+}
+
 // Exact minimum cut of a CSR graph by Stoer-Wagner (tie rules above).
 // side: one byte per vertex, 1 on the returned side (vertex-0 normalisation
 // is NOT applied here). Returns 0 or a negative error code.
@@ -389,8 +460,8 @@ int oracle_stoer_wagner(int32_t n, const int32_t *row_ptr, const int32_t *col, c
 // vertex u is on the side that does not contain vertex 0.
 // out_info[0..3] = rounds, kernel_n, witness_level (-1: exact solve), status bits.
 int oracle_mincut(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *w, int32_t lp_iters,
-                  int32_t n0, int32_t max_rounds, uint64_t seed, int64_t *out_cut, uint64_t *out_side,
-                  int32_t *out_info, oracle_trace_fn cb, void *user) {
+                  int32_t n0, int32_t max_rounds, uint64_t seed, uint32_t flags, int64_t *out_cut,
+                  uint64_t *out_side, int32_t *out_info, oracle_trace_fn cb, void *user) {
   if (lp_iters < 0 || n0 < 0 || max_rounds < 0) return E_INVAL;
   int rc = validate(n, row_ptr, col, w, true);
   if (rc) return rc;
@@ -450,6 +521,14 @@ int oracle_mincut(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
     int32_t n_start = g.n;
     if (lp_iters > 0) {
       std::vector<int32_t> L = label_propagation(g, lp_iters, seed, r, cb, user);
+      if (flags & F_CORRECT) {
+        L = fix_misplaced(g, L);
+        if (cb) {
+          oracle_event ev{};
+          ev.kind = EV_FIX; ev.round = r; ev.n = g.n; ev.a = L.data();
+          cb(user, &ev);
+        }
+      }
       if (apply_contraction(L)) { done = true; break; }
     }
     std::vector<int32_t> mark = pr_marks(g, deg, lam);

@@ -204,6 +204,11 @@ struct Engine {
   int32_t n_active = 0, drained = 0;
   WordAlloc words;
   std::vector<int32_t> free_slots;
+  // slots of finished graphs whose rows may still be in the union: a graph
+  // that leaves the loop keeps its rows until the next relabelling drops
+  // them (it does so for every graph not in the loop), and a slot reused
+  // before that would make those rows count as the new graph's
+  std::vector<int32_t> zombie_slots;
   std::vector<ReqRec> slot_req;
   std::deque<ReqRec> pending;
   std::vector<DoneRec> staged, ready;
@@ -301,6 +306,8 @@ struct Engine {
     if (n_active == 0) {  // nothing in the loop and everything drained: restart the union
       N = 0;
       A = 0;
+      free_slots.insert(free_slots.end(), zombie_slots.begin(), zombie_slots.end());
+      zombie_slots.clear();
     }
     N0 = N;
     std::vector<GDesc> fd;
@@ -497,7 +504,7 @@ struct Engine {
       wsum += r.words;
       staged.push_back(DoneRec{r.id, res, r.t_submit});
       words.release(r.woff, r.words);
-      free_slots.push_back(e.slot);
+      zombie_slots.push_back(e.slot);
     }
     VC_TRY(hipMemcpyAsync(d_sdesc, sd, sizeof(SideDesc) * m, hipMemcpyHostToDevice, s));
     VC_TRY(b_side(d_sdesc, m, wsum, w.map, w.witness, w.flags8, wg, s));
@@ -531,7 +538,12 @@ struct Engine {
   // mode 0: clusters of the labels L; mode 1: components of marked edges
   int contract(const int32_t *L, int mode, DGraph &G) {
     BatchView bv{gvb[gvc], gs, cap.s};
+    // this relabelling drops the rows of every graph already finished: their
+    // slots can be reused by admissions after it (in stream order)
+    std::vector<int32_t> release;
+    release.swap(zombie_slots);
     VC_TRY(relabel(L, G.n, w, s, &bv, gvb[gvc ^ 1]));
+    free_slots.insert(free_slots.end(), release.begin(), release.end());
     VC_TRY(b_gsizes(gs, cap.s, w.ids, mode, s));
     VC_TRY(b_compose(w.map, w.cl, 64ll * cap.w, wg, gs, s));
     VC_TRY(contract_emit(G, w, known, s));

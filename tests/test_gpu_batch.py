@@ -221,3 +221,46 @@ def test_session_budget_admission():
         sess.submit(99, *huge)
     assert e.value.code == vc.EBUDGET
     sess.close()
+
+
+def _serve_all(sess, dev, order, arrivals_per_step=None, rng=None):
+    results = {}
+    pending = list(order)
+    steps = 0
+    while True:
+        k = len(pending) if arrivals_per_step is None else int(rng.integers(0, arrivals_per_step + 1))
+        for _ in range(k):
+            if pending:
+                i = pending.pop(0)
+                sess.submit(i, *dev[i])
+        n = sess.step()
+        steps += 1
+        for rid, cut, side, info in sess.poll():
+            results[rid] = (cut, side, info)
+        assert steps < 20000
+        if not pending and n == 0:
+            break
+    return results
+
+
+def test_session_waves_reuse_slots():
+    """Regression: requests admitted in waves, most of which leave the loop
+    by collapsing (their rows stay in the union until the next relabelling),
+    so later requests reuse slots of finished ones. Every result equals the
+    oracle's for that graph alone."""
+    gs = [gg.planted(int(n), float(d), 8, 1, 100, 900 + s)
+          for s, (n, d) in enumerate([(24000, 16), (30000, 20), (20000, 24), (36000, 16), (28000, 20),
+                                      (22000, 18), (32000, 16), (26000, 22), (34000, 18), (21000, 20)])]
+    dev = [to_dev(g) for g in gs]
+    kw = dict(lp_iters=2, n0=64, seed=0)
+    one = max(vc.batch_workspace_bytes([d], vc.params(**kw)) for d in dev)
+    sess = vc.Session(int(one * 2.6), **kw)  # one lane, two or three requests at a time
+    results = _serve_all(sess, dev, list(range(len(gs))))
+    sess.close()
+    statuses = set()
+    for i, g in enumerate(gs):
+        want = expect(g, kw)
+        statuses.add(want[5])
+        assert got(g, *results[i]) == want, (i, g.n)
+    assert oracle.ST_COLLAPSED in statuses  # the case that leaves rows behind is exercised
+

@@ -72,7 +72,13 @@ enum {
 
 /* params.flags */
 enum {
-  VIECUT_F_VALIDATE = 1 /* check symmetry (w(u,v) == w(v,u)) and strictly increasing rows (O(nnz log d)) */
+  VIECUT_F_VALIDATE = 1, /* check symmetry (w(u,v) == w(v,u)) and strictly increasing rows (O(nnz log d)) */
+  VIECUT_F_CORRECT = 2   /* the correcting step after label propagation (Section 4.1's correcting algorithm,
+                            fixMisplacedVertices in Algorithm 1): in every cluster of 2 to floor(log2 n)
+                            vertices, the vertex whose removal leaves the cluster the smallest weighted
+                            degree in the contracted graph becomes a singleton if that degree is below the
+                            contracted graph's minimum weighted degree. Single-graph calls only: batches and
+                            sessions return VIECUT_EINVAL. */
 };
 
 /* Input graph: a symmetric CSR. Row v lists the neighbours of v.
@@ -162,7 +168,9 @@ int viecut_mincut(const viecut_csr *g, const viecut_params *p, void *ws, size_t 
  *   kind 3 (BOUND):    lam_hat, witness_vertex, witness_level after the update at `level`
  *   kind 4 (PR):       a = mark[nnz] on the graph at `level`: 1 on the arc (v, x), v < x, of
  *                      every marked edge, 0 elsewhere
- *   kind 5 (UF):       a = rep[n], the smallest vertex id of each marked-edge component */
+ *   kind 5 (UF):       a = rep[n], the smallest vertex id of each marked-edge component
+ *   kind 6 (FIX):      a = labels[n] after the correcting step of round `round` (a vertex v made a
+ *                      singleton has label n + v) */
 typedef struct {
   int32_t kind, round, iter, level;
   int32_t n, n_prev;
@@ -236,18 +244,25 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
 
 /* ------------------------------------------------------------ serving */
 /* Serving of the same method (Algorithm 1 per request; applications in
- * Section 1). A session keeps admitted graphs resident and advances all of them by one
- * batched round per step (continuous batching): requests submitted while
- * others are in flight join at the next step once their workspace fits in
- * the budget; finished requests release their workspace. */
+ * Section 1). A session keeps admitted graphs resident and advances them by
+ * batched rounds (continuous batching): requests submitted while others are
+ * in flight join at the next round once their workspace fits in the budget;
+ * finished requests release their workspace. Requests of up to 2^20 arcs go
+ * to a small-request lane (a quarter of the budget) that the caller's thread
+ * advances one round per viecut_session_step; larger ones go to a second lane
+ * that a worker thread of the session advances on a stream of its own, so a
+ * round of large graphs does not hold back small requests. One thread drives
+ * a session (its calls are not to be made concurrently). */
 typedef struct viecut_session viecut_session;
 
 /* Creates a session (Algorithm 1 per request). hbm_budget: bytes of device
- * memory the session allocates once here for its union workspace (vertices and
- * arcs in a 1 : 4 ratio, up to 4096 requests in flight). p: parameters of every
- * request (host, copied). stream: the stream all of the session's work runs
- * on. *out receives the handle. Returns VIECUT_EBUDGET if the budget holds no
- * graph at all, VIECUT_ENOMEM if the allocation fails. */
+ * memory the session allocates once here for the workspaces of its two lanes
+ * (vertices and arcs in a 1 : 4 ratio, up to 4096 requests in flight per
+ * lane). p: parameters of every request (host, copied). stream: the stream
+ * of the small-request lane; the large lane creates one of its own (default
+ * priority). A budget whose quarter cannot hold a 2^20-arc request keeps one
+ * lane for every request. *out receives the handle. Returns VIECUT_EBUDGET if
+ * the budget holds no graph at all, VIECUT_ENOMEM if an allocation fails. */
 int viecut_session_create(size_t hbm_budget, const viecut_params *p, void *stream, viecut_session **out);
 /* Queues a request (a graph as in viecut_mincut; Section 3's input). g's
  * arrays and side (ceil(n/64) device words) are owned by the caller and must
@@ -256,12 +271,14 @@ int viecut_session_create(size_t hbm_budget, const viecut_params *p, void *strea
  * errors are reported per request by poll. Returns VIECUT_EBUDGET if it can
  * never fit in the session's workspace. */
 int viecut_session_submit(viecut_session *s, const viecut_csr *g, uint64_t *side, int64_t request_id);
-/* Admits queued requests that fit, runs one round of the method (label
+/* Admits queued small requests that fit, runs one round of the method (label
  * propagation, cluster contraction, Padberg-Rinaldi contraction, bounds:
- * Section 4.1) for every active request, exact-solves and finishes those that
- * left the loop (Algorithm 1's last steps). Returns after the round's device
- * work is enqueued and the finished requests' results are final.
- * *n_active receives the number of requests still in flight or queued. */
+ * Section 4.1) for every active small request, exact-solves and finishes
+ * those that left the loop (Algorithm 1's last steps); the large lane runs its
+ * rounds meanwhile on its own. With no small request in flight it waits up to
+ * a millisecond for the large lane to finish a round. Returns an error of
+ * either lane. *n_active receives the number of requests still in flight or
+ * queued in both lanes. */
 int viecut_session_step(viecut_session *s, int32_t *n_active);
 /* Retrieves up to max finished requests into the host arrays ids and outs
  * (results as viecut_mincut's; an input error shows as status_bits

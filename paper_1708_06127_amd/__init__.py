@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libviecut.so")
 OK, EINVAL, EWEIGHT, EOVERFLOW, ENOMEM, EDEVICE, ENOTSYM, EBUDGET, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8
 NOALLOC_SCRATCH_BYTES = 64 << 20  # VIECUT_NOALLOC_SCRATCH_BYTES
 ST_COLLAPSED, ST_DISCONNECTED, ST_NO_PROGRESS, ST_MAX_ROUNDS = 1, 2, 4, 8
-F_VALIDATE = 1
+F_VALIDATE, F_CORRECT = 1, 2
 EXPORTED = ["viecut_default_params", "viecut_workspace_bytes", "viecut_mincut", "viecut_mincut_noalloc",
             "viecut_mincut_trace",
             "viecut_validate", "viecut_batch_workspace_bytes", "viecut_mincut_batch", "viecut_session_create",
@@ -138,12 +138,12 @@ def _check(code: int):
         raise ViecutError(code, strerror(code))
 
 
-def params(lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False) -> Params:
+def params(lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, correct=False) -> Params:
     p = Params()
     load().viecut_default_params(ctypes.byref(p))
     p.lp_iters, p.n0, p.max_rounds = int(lp_iters), int(n0), int(max_rounds)
     p.seed = int(seed) & (2**64 - 1)
-    p.flags = F_VALIDATE if validate else 0
+    p.flags = (F_VALIDATE if validate else 0) | (F_CORRECT if correct else 0)
     return p
 
 
@@ -196,7 +196,7 @@ def _event_dict(ev):
         return np.ctypeslib.as_array(p, shape=(int(count),)).copy().astype(dt, copy=False)
     k = ev.kind
     d = {"kind": k, "round": ev.round, "iter": ev.iter, "level": ev.level, "n": ev.n}
-    if k == 1:
+    if k in (1, 6):
         d["labels"] = arr(ev.a, ev.n, np.int32)
     elif k == 2:
         d["row_ptr"] = arr(ev.a, ev.n + 1, np.int32)
@@ -216,13 +216,13 @@ def _event_dict(ev):
     return d
 
 
-def mincut(row_ptr, col, w, *, lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, ws=None,
-           side=None, stream=None, trace=False):
+def mincut(row_ptr, col, w, *, lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, correct=False,
+           ws=None, side=None, stream=None, trace=False):
     """Solve one graph given as int32 CUDA tensors. Returns (cut, side, info)."""
     torch = _torch()
     lib = load()
     g = csr(row_ptr, col, w)
-    p = params(lp_iters, n0, max_rounds, seed, validate)
+    p = params(lp_iters, n0, max_rounds, seed, validate, correct)
     words = (g.n + 63) // 64
     if side is None:
         side = torch.empty(max(words, 1), dtype=torch.int64, device=row_ptr.device)

@@ -22,12 +22,14 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -688,10 +690,63 @@ Caps caps_for_budget(size_t budget) {
 }  // namespace
 }  // namespace vc
 
-// ============================================================ C ABI
+// ============================================================ serving lanes
+namespace vc {
+namespace {
+// A session serves requests in two lanes, each an Engine with its own union,
+// workspace and stream: requests of up to kSmallLaneArcs arcs go to the small
+// lane, which the caller's thread steps, and larger ones to the large lane,
+// which a worker thread steps on its own stream. A round of large graphs
+// (tens of milliseconds) then no longer holds the rounds of small requests
+// that arrive meanwhile (they overlap on the device), and each lane's host
+// work (admission, exact solves) overlaps the other lane's kernels. Every
+// request's arithmetic is that of a solo solve in either lane.
+constexpr int64_t kSmallLaneArcs = 1 << 20;
+}  // namespace
+}  // namespace vc
+
 struct viecut_session {
-  vc::Engine eng;
+  vc::Engine small, large;
   size_t budget = 0;
+  hipStream_t large_stream = nullptr;
+  std::thread worker;
+  std::mutex mu;                       // guards everything below
+  std::condition_variable cv_work;     // worker: new large requests or stop
+  std::condition_variable cv_done;     // caller: the large lane finished a step
+  std::deque<vc::ReqRec> large_in;     // submitted, not yet handed to the large lane
+  std::vector<vc::DoneRec> large_ready;
+  int32_t large_in_flight = 0;
+  int64_t large_steps = 0;
+  int large_err = VIECUT_OK;
+  bool stop = false;
+  bool two_lanes = false;  // false: a budget too small to split, every request in the one lane
+
+  void run_large() {
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      cv_work.wait(lk, [&] { return stop || !large_in.empty() || large_in_flight > 0; });
+      if (stop) return;
+      while (!large_in.empty()) {
+        const vc::ReqRec &r = large_in.front();
+        large.submit(r.g, r.side, r.id, r.t_submit);
+        large_in.pop_front();
+      }
+      lk.unlock();
+      const int rc = large.step();
+      lk.lock();
+      if (rc && large_err == VIECUT_OK) large_err = rc;
+      for (const auto &d : large.ready) large_ready.push_back(d);
+      large.ready.clear();
+      large_in_flight = rc ? 0 : large.in_flight();
+      large_steps++;
+      cv_done.notify_all();
+      if (rc) {
+        large_in.clear();
+        cv_work.wait(lk, [&] { return stop; });
+        return;
+      }
+    }
+  }
 };
 
 extern "C" {
@@ -715,6 +770,7 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
   if (!gs || !p || !outs || !sides || count < 0) return VIECUT_EINVAL;
   viecut_params q = *p;
   if (q.lp_iters < 0 || q.n0 < 0 || q.max_rounds < 0) return VIECUT_EINVAL;
+  if (q.flags & VIECUT_F_CORRECT) return VIECUT_EINVAL;  // the correcting step runs on the single path only
   vc::Caps c;
   for (int32_t i = 0; i < count; i++) {
     const int rc = vc::check_args(&gs[i], p);
@@ -753,53 +809,113 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
 int viecut_session_create(size_t hbm_budget, const viecut_params *p, void *stream, viecut_session **out) {
   if (!p || !out) return VIECUT_EINVAL;
   if (p->lp_iters < 0 || p->n0 < 0 || p->max_rounds < 0) return VIECUT_EINVAL;
-  vc::Caps c = vc::caps_for_budget(hbm_budget);
-  if (c.a < 1) return VIECUT_EBUDGET;
+  if (p->flags & VIECUT_F_CORRECT) return VIECUT_EINVAL;  // the correcting step runs on the single path only
+  // a quarter of the budget for the small lane, the rest for the large one;
+  // a budget whose quarter cannot hold a small-lane request keeps one lane
+  vc::Caps cs = vc::caps_for_budget(hbm_budget / 4);
+  vc::Caps cl = vc::caps_for_budget(hbm_budget - hbm_budget / 4);
+  const bool two = cs.a >= vc::kSmallLaneArcs && cl.a >= 1;
+  if (!two) cs = vc::caps_for_budget(hbm_budget);
+  if (cs.a < 1) return VIECUT_EBUDGET;
   viecut_session *ss = new (std::nothrow) viecut_session;
   if (!ss) return VIECUT_ENOMEM;
   ss->budget = hbm_budget;
-  const int rc = ss->eng.init(c, *p, (hipStream_t)stream, nullptr, 0);
-  if (rc) {
+  ss->two_lanes = two;
+  if (two && hipStreamCreateWithFlags(&ss->large_stream, hipStreamNonBlocking) != hipSuccess) {
     delete ss;
+    return VIECUT_EDEVICE;
+  }
+  int rc = ss->small.init(cs, *p, (hipStream_t)stream, nullptr, 0);
+  if (!rc && two) rc = ss->large.init(cl, *p, ss->large_stream, nullptr, 0);
+  if (rc) {
+    hipStream_t ls = ss->large_stream;
+    if (ls) (void)hipStreamSynchronize(ls);
+    delete ss;
+    if (ls) (void)hipStreamDestroy(ls);
     return rc;
   }
+  if (two) ss->worker = std::thread([ss] { ss->run_large(); });
   *out = ss;
   return VIECUT_OK;
 }
 
 int viecut_session_submit(viecut_session *s, const viecut_csr *g, uint64_t *side, int64_t request_id) {
   if (!s || !g || !side) return VIECUT_EINVAL;
-  const int rc = vc::check_args(g, &s->eng.p);
+  const int rc = vc::check_args(g, &s->small.p);
   if (rc) return rc;
-  if (!s->eng.fits_ever(*g)) return VIECUT_EBUDGET;
-  s->eng.submit(*g, side, request_id, vc::now_ms());
+  const double t = vc::now_ms();
+  if (!s->two_lanes || ((int64_t)g->nnz <= vc::kSmallLaneArcs && s->small.fits_ever(*g))) {
+    if (!s->small.fits_ever(*g)) return VIECUT_EBUDGET;
+    s->small.submit(*g, side, request_id, t);
+    return VIECUT_OK;
+  }
+  if (!s->large.fits_ever(*g)) return VIECUT_EBUDGET;
+  vc::ReqRec r;
+  r.g = *g;
+  r.side = side;
+  r.id = request_id;
+  r.t_submit = t;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->large_in.push_back(r);
+  }
+  s->cv_work.notify_one();
   return VIECUT_OK;
 }
 
 int viecut_session_step(viecut_session *s, int32_t *n_active) {
   if (!s) return VIECUT_EINVAL;
-  const int rc = s->eng.step();
-  if (n_active) *n_active = s->eng.in_flight();
+  int rc = VIECUT_OK;
+  if (s->small.in_flight() > 0) {
+    rc = s->small.step();
+  } else {
+    // nothing for the small lane: wait up to a millisecond for the large
+    // lane to finish a step instead of returning at once (a caller that
+    // loops over step and its own arrivals then neither spins nor delays a
+    // new arrival by more than that)
+    std::unique_lock<std::mutex> lk(s->mu);
+    const int64_t seen = s->large_steps;
+    if (!s->large_in.empty() || s->large_in_flight > 0)
+      s->cv_done.wait_for(lk, std::chrono::milliseconds(1),
+                          [&] { return s->large_steps != seen || s->large_err != VIECUT_OK; });
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!rc && s->large_err) rc = s->large_err;
+  if (n_active) *n_active = s->small.in_flight() + s->large_in_flight + (int32_t)s->large_in.size();
   return rc;
 }
 
 int viecut_session_poll(viecut_session *s, int64_t *ids, viecut_result *outs, int32_t max) {
   if (!s || max < 0 || (max > 0 && (!ids || !outs))) return VIECUT_EINVAL;
-  auto &r = s->eng.ready;
-  const int32_t k = std::min<int32_t>(max, (int32_t)r.size());
-  for (int32_t i = 0; i < k; i++) {
-    ids[i] = r[i].id;
-    outs[i] = r[i].res;
+  std::lock_guard<std::mutex> lk(s->mu);
+  int32_t k = 0;
+  for (auto *r : {&s->small.ready, &s->large_ready}) {
+    const int32_t take = std::min<int32_t>(max - k, (int32_t)r->size());
+    for (int32_t i = 0; i < take; i++) {
+      ids[k + i] = (*r)[i].id;
+      outs[k + i] = (*r)[i].res;
+    }
+    r->erase(r->begin(), r->begin() + take);
+    k += take;
   }
-  r.erase(r.begin(), r.begin() + k);
   return k;
 }
 
 void viecut_session_destroy(viecut_session *s) {
   if (!s) return;
-  (void)hipStreamSynchronize(s->eng.s);
-  s->eng.report("session");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipStreamSynchronize(s->small.s);
+  if (s->large_stream) (void)hipStreamSynchronize(s->large_stream);
+  s->small.report("session small lane");
+  if (s->two_lanes) s->large.report("session large lane");
+  hipStream_t ls = s->large_stream;
   delete s;
+  if (ls) (void)hipStreamDestroy(ls);
 }
 
 }  // extern "C"

@@ -36,6 +36,7 @@ struct ProfRec {
   int kind;
   int32_t ntiles;
   hipEvent_t a, b;
+  double bytes = -1;  // >= 0: set by the host (spans); < 0: from the kernel's tile totals
 };
 struct ProfState {
   std::mutex mu;
@@ -52,10 +53,10 @@ ProfState &prof() {
   static ProfState p;
   return p;
 }
-const char *kProfNames[PROF_KINDS] = {"k_first_tile", "k_first_tile_level0", "k_lp_tile"};
-// algorithmic bytes per arc and per row of each timed kernel
-const double kProfPerArc[PROF_KINDS] = {8, 8, 12};   // col, w (+ the label gather Lin[col])
-const double kProfPerRow[PROF_KINDS] = {8, 16, 12};  // rp + label out (+ degree, + own label)
+const char *kProfNames[PROF_KINDS] = {"k_first_tile", "k_first_tile_level0", "k_lp_tile", "lp_contract_sweep"};
+// algorithmic bytes per arc and per row of each timed kernel (spans carry their own)
+const double kProfPerArc[PROF_KINDS] = {8, 8, 12, 0};   // col, w (+ the label gather Lin[col])
+const double kProfPerRow[PROF_KINDS] = {8, 16, 12, 0};  // rp + label out (+ degree, + own label)
 hipEvent_t prof_event(ProfState &p) {
   if (!p.pool.empty()) {
     hipEvent_t e = p.pool.back();
@@ -91,6 +92,35 @@ ProfScope::~ProfScope() {
   (void)hipEventRecord(p.pending[slot].b, s);
 }
 
+int prof_span_begin(ProfKind kind, hipStream_t s) {
+  ProfState &p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (!p.on || !p.slots || (int32_t)p.pending.size() >= p.cap) return -1;
+  ProfRec r;
+  r.kind = kind;
+  r.ntiles = 0;
+  r.a = prof_event(p);
+  r.b = prof_event(p);
+  if (!r.a || !r.b || hipEventRecord(r.a, s) != hipSuccess) return -1;
+  r.bytes = 0;
+  p.pending.push_back(r);
+  return (int)p.pending.size() - 1;
+}
+
+void prof_span_end(int id, hipStream_t s) {
+  if (id < 0) return;
+  ProfState &p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (id < (int)p.pending.size()) (void)hipEventRecord(p.pending[id].b, s);
+}
+
+void prof_span_bytes(int id, double bytes) {
+  if (id < 0) return;
+  ProfState &p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (id < (int)p.pending.size()) p.pending[id].bytes = bytes;
+}
+
 void prof_collect() {
   ProfState &p = prof();
   std::lock_guard<std::mutex> lk(p.mu);
@@ -98,12 +128,16 @@ void prof_collect() {
     ProfRec &r = p.pending[i];
     float ms = 0;
     if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-      const int32_t rows = p.slots[4 * i];
-      uint64_t arcs;
-      std::memcpy(&arcs, &p.slots[4 * i + 2], 8);
       p.launches[r.kind]++;
       p.ms[r.kind] += ms;
-      p.bytes[r.kind] += kProfPerArc[r.kind] * (double)arcs + kProfPerRow[r.kind] * rows + 16.0 * r.ntiles;
+      if (r.bytes >= 0) {
+        p.bytes[r.kind] += r.bytes;
+      } else {
+        const int32_t rows = p.slots[4 * i];
+        uint64_t arcs;
+        std::memcpy(&arcs, &p.slots[4 * i + 2], 8);
+        p.bytes[r.kind] += kProfPerArc[r.kind] * (double)arcs + kProfPerRow[r.kind] * rows + 16.0 * r.ntiles;
+      }
     }
     p.pool.push_back(r.a);
     p.pool.push_back(r.b);
@@ -138,7 +172,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   const int64_t huge_rows = nnz / (kHugeChunk + 1) + 1;
   const int64_t ntiles = (nnz + n) / kTile + 2;
   const int64_t nseg = ntiles + 3 * (nnz / kTile + 1) + 2;
-  int64_t maxscan = std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg});
+  int64_t maxscan = std::max<int64_t>({nnz, 2 * (int64_t)n + 1, 256 * tiles, nseg});
   L.add(sizeof(Status));                       // 0 st
   for (int b = 0; b < 2; b++) {
     L.add(4 * ((size_t)n + 1));                // rp
@@ -148,7 +182,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   L.add(8 * (size_t)n + 8);                    // 7 deg
   L.add(4 * (size_t)n + 4);                    // 8 La
   L.add(4 * (size_t)n + 4);                    // 9 Lb
-  L.add(4 * ((size_t)n + 1));                  // 10 ids
+  L.add(4 * (2 * (size_t)n + 1));              // 10 ids (label range up to 2n with the correcting step)
   L.add(4 * (size_t)n + 4);                    // 11 cl
   L.add(4 * (size_t)map_n + 4);                // 12 map
   L.add(8 * (((size_t)map_n + 63) / 64) + 8);  // 13 witness
@@ -172,6 +206,10 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   L.add(8 * (size_t)nseg);                     // 31 seg
   L.add(4 * (size_t)nseg + 4);                 // 32 seg_cnt
   L.add(4 * (size_t)ntiles);                   // 33 big_tiles
+  L.add(4 * (size_t)n + 4);                    // 34 fix_cnt
+  L.add(4 * (size_t)n + 4);                    // 35 fix_out
+  L.add(8 * (size_t)n + 8);                    // 36 fix_cut
+  L.add(8 * (size_t)n + 8);                    // 37 fix_key
   return L;
 }
 
@@ -211,7 +249,7 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
   {
     const int64_t tiles = (nnz + kRsTile - 1) / kRsTile + 1;
     const int64_t nseg = (nnz + n) / kTile + 2 + 3 * (nnz / kTile + 1) + 2;
-    w.lb_tiles = scan_tiles_max(std::max<int64_t>({nnz, (int64_t)n + 1, 256 * tiles, nseg}));
+    w.lb_tiles = scan_tiles_max(std::max<int64_t>({nnz, 2 * (int64_t)n + 1, 256 * tiles, nseg}));
     w.lb_state = (unsigned long long *)at(21);
     w.lb_ticket = (uint32_t *)(w.lb_state + w.lb_tiles);
     w.lb_epoch = 0;
@@ -229,6 +267,10 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
   w.seg = (int32_t *)at(31);
   w.seg_cnt = (int32_t *)at(32);
   w.big_tiles = (int32_t *)at(33);
+  w.fix_cnt = (int32_t *)at(34);
+  w.fix_out = (uint32_t *)at(35);
+  w.fix_cut = (unsigned long long *)at(36);
+  w.fix_key = (unsigned long long *)at(37);
   return true;
 }
 
@@ -260,6 +302,9 @@ struct Solver {
   // false: no page-locked host buffers (the allocation-free entry point);
   // status reads and the kernel-graph hand-off use pageable host memory
   bool pinned = true;
+  // kernel timer span of round 1's label propagation and cluster contraction
+  // (from the solve's first launch to the coarse CSR), -1 when not timed
+  int sweep = -1;
 
   Solver(Work &w_, hipStream_t s_, const viecut_params &p_) : w(w_), s(s_), p(p_) {}
 
@@ -322,11 +367,11 @@ struct Solver {
     }
     return h;
   }
-  void trace_labels(int32_t round, int32_t iter, const int32_t *L, int32_t n) {
+  void trace_labels(int32_t round, int32_t iter, const int32_t *L, int32_t n, int32_t kind = 1) {
     if (!tr.fn) return;
     std::vector<int32_t> h = d2h(L, n);
     viecut_event ev{};
-    ev.kind = 1; ev.round = round; ev.iter = iter; ev.n = n; ev.a = h.data();
+    ev.kind = kind; ev.round = round; ev.iter = iter; ev.n = n; ev.a = h.data();
     tr.fn(tr.user, &ev);
   }
   void trace_graph(int32_t level, const DGraph &G, int32_t n_prev) {
@@ -370,8 +415,9 @@ struct Solver {
   // the new graph, whose arc tiles and long-row lists are built here.
   // `known` holds the host copy of G's long-row counts (nullptr: unknown) and
   // is invalidated for the new graph.
-  int contract(const int32_t *L, DGraph &G, int &cur, int32_t &level, const int32_t *&known) {
-    VC_TRY(relabel(L, G.n, w, s));
+  int contract(const int32_t *L, DGraph &G, int &cur, int32_t &level, const int32_t *&known,
+               int64_t lspace = -1) {
+    VC_TRY(relabel(L, G.n, w, s, nullptr, nullptr, lspace));
     VC_TRY(contract_emit(G, w, known, s));
     int rc = sync_status();
     if (rc) return rc;
@@ -383,8 +429,20 @@ struct Solver {
     const int dst = cur == 0 ? 1 : 0;
     level++;
     VC_TRY(contract_build(w, which, ax, kb, k, dst, level, s));
+    if (sweep >= 0) prof_span_end(sweep, s);
     rc = sync_status();
     if (rc) return rc;
+    if (sweep >= 0) {
+      // algorithmic bytes of the sweep: LP iteration 1 with the level-0 degrees
+      // (8A + 16n), iteration 2 (12A + 12n), relabel and map (24n), contraction
+      // (8A + 4 A_x + 8 A' + 8n): 28A + 4A_x + 8A' + 60n, plus 12A + 12n per
+      // further LP iteration
+      const double A = (double)w.nnz_in, n = (double)w.n_in;
+      const double extra = (double)std::max(p.lp_iters - 2, 0) * (12 * A + 12 * n) -
+                           (p.lp_iters < 2 ? 12 * A + 12 * n : 0.0);
+      prof_span_bytes(sweep, 28 * A + 4 * (double)ax + 8 * (double)st.nnz + 60 * n + extra);
+      sweep = -1;
+    }
     DGraph H;
     H.n = k;
     H.nnz = st.nnz;
@@ -415,6 +473,7 @@ struct Solver {
     G.col = g.col;
     G.w = g.w;
     const bool do_lp = p.lp_iters > 0 && g.n > p.n0;
+    if (do_lp && !tr.fn) sweep = prof_span_begin(PROF_SWEEP, s);
     VC_TRY(status_reset(w.st, s));
     VC_TRY(init_map(w, s));
     VC_TRY(check_rowptr(G, w.st, s));
@@ -456,9 +515,15 @@ struct Solver {
           std::swap(Lc, Lo);
           trace_labels(r, t, Lc, G.n);
         }
+        int64_t lspace = -1;
+        if (p.flags & VIECUT_F_CORRECT) {  // misplaced vertices become singletons (labels n + v)
+          VC_TRY(fix_misplaced(G, w, Lc, s));
+          trace_labels(r, 0, Lc, G.n, 6);
+          lspace = 2ll * G.n;
+        }
         t_ms[1] += ms_since(tl);  // enqueue time: the LP kernels finish inside the contraction's first sync
         auto tc = std::chrono::steady_clock::now();
-        rc = contract(Lc, G, cur, level, known);
+        rc = contract(Lc, G, cur, level, known, lspace);
         if (rc) return rc;
         t_ms[2] += ms_since(tc);
         if (st.stop) { status |= (uint32_t)st.stop; done = true; break; }

@@ -68,6 +68,7 @@ struct Status {
   int32_t big_tiles;           // tiles of more than 256 arcs (listed in Work::big_tiles)
   unsigned long long tile_arcs;  // arcs covered by the arc tiles of the current level
   int32_t pr_rows[2];          // rows marked with an LDS table of their row (short / long tables)
+  unsigned long long fix_delta;  // correcting step: minimum weighted degree of the contracted graph
 };
 
 // ------------------------------------------------------------ batched solves
@@ -190,6 +191,13 @@ struct Work {
   unsigned long long *part = nullptr;  // per-block partial results (3 per tile)
   int32_t *seg = nullptr;        // emission segments: first arc of each
   int32_t *seg_cnt = nullptr;    // their counts, then exclusive offsets
+  // correcting step (per label of the current level): member counts, the
+  // cluster's weighted degree in the contracted graph, the best removal key;
+  // per vertex: weight of its edges to other clusters
+  int32_t *fix_cnt = nullptr;
+  uint32_t *fix_out = nullptr;
+  unsigned long long *fix_cut = nullptr;
+  unsigned long long *fix_key = nullptr;
 };
 
 size_t work_bytes(int32_t n, int64_t nnz, int64_t map_n = -1, int64_t extra = 0);
@@ -219,8 +227,12 @@ hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchV
 // a single solve also composes map[u] <- cl[map[u]] in the same pass
 // (batched: only graphs in the round loop keep their vertices; gv_new receives
 // the graph index of every new vertex; the map is composed separately)
+// lspace: size of the label value range (n, or 2n after the correcting step)
 hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const BatchView *bv = nullptr,
-                   int32_t *gv_new = nullptr);
+                   int32_t *gv_new = nullptr, int64_t lspace = -1);
+// correcting step on the labels L of the graph g (single solve): a misplaced
+// vertex v gets label n + v (labels then range over [0, 2n))
+hipError_t fix_misplaced(const DGraph &g, Work &w, int32_t *L, hipStream_t s);
 hipError_t init_map(Work &w, hipStream_t s);
 // contraction: inter-cluster triples packed into buffer 1 (count -> st->ax, key bits from st->k)
 hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);
@@ -263,7 +275,7 @@ constexpr int kPackArcs = 8192;  // arcs per chunk of the packing and gather wor
 
 // ---- optional kernel timing (viecut_profile_*): an event pair around a
 // launch plus a copy of the level's tile totals for its algorithmic bytes
-enum ProfKind : int { PROF_FIRST_TILE = 0, PROF_FIRST_TILE_L0 = 1, PROF_LP_TILE = 2, PROF_KINDS = 3 };
+enum ProfKind : int { PROF_FIRST_TILE = 0, PROF_FIRST_TILE_L0 = 1, PROF_LP_TILE = 2, PROF_SWEEP = 3, PROF_KINDS = 4 };
 struct ProfScope {
   int slot = -1;
   hipStream_t s;
@@ -276,6 +288,13 @@ struct ProfScope {
   ~ProfScope();
 };
 void prof_collect();  // after a synchronisation: fold finished records into the totals
+// An event-timed span on a stream whose algorithmic bytes the host knows only
+// later (the round-1 label-propagation + contraction sweep): begin returns a
+// record id (-1 when timing is off), end records the closing event, and
+// prof_span_bytes sets the record's bytes once they are known.
+int prof_span_begin(ProfKind kind, hipStream_t s);
+void prof_span_end(int id, hipStream_t s);
+void prof_span_bytes(int id, double bytes);
 
 // host driver entry points shared by the single, batched and session paths
 int check_args(const viecut_csr *g, const viecut_params *p);

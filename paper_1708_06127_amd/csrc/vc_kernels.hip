@@ -445,10 +445,17 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
 }
 
 // ------------------------------------------------------------ LP iteration t >= 2
-// S(x) = sum of w(v,u) over neighbours u with Lin[u] == x, accumulated in an
-// open-addressing hash table (int32 key, uint32 sum; sums are bounded by the
-// total weight <= INT32_MAX). Then the candidate of largest (S, -prio) wins
-// unless the vertex's own label already attains the maximum S.
+// Long rows (256..4096 arcs), G lanes per row: S(x) = sum of w(v,u) over
+// neighbours u with Lin[u] == x, accumulated in an open-addressing LDS table
+// (int32 key, uint32 sum; sums are bounded by the total weight <= INT32_MAX)
+// of T = the power of two >= 2 d slots (d the row's arcs), so that probing
+// ends and only T slots are cleared. Each weight is added with a returning
+// atomic: the returned partial sum plus the weight is a lower bound of the
+// label's final sum, and the last update of a label sees the final sum, so
+// the row maximum of the keys (S, own, -prio) over all updates is the maximum
+// over the labels' final sums; no pass over the table is needed. The own-label
+// bit sits between S and prio: the maximum has it set exactly when the own
+// label attains the maximum sum, which keeps the own label.
 template <int G, int TBL>
 __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
@@ -459,21 +466,31 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
   __shared__ int32_t tkey[NG][TBL];
   __shared__ uint32_t tval[NG][TBL];
   __shared__ unsigned long long red[kBlock / 64];
-  __shared__ uint32_t own_sh[NG];
   if (!gv && st->err) return;
   const int gi = threadIdx.x / G, lane = threadIdx.x % G;
   const int32_t cnt = *cnt_p;
   for (int64_t base = blockIdx.x * (int64_t)NG; base < cnt; base += (int64_t)gridDim.x * NG) {
-    int64_t idx = base + gi;
-    bool act = idx < cnt;
-    int32_t v = act ? list[idx] : 0;
-    int32_t beg = act ? rp[v] : 0, end = act ? rp[v + 1] : 0;
-    for (int s = lane; s < TBL; s += G) {
-      tkey[gi][s] = -1;
-      tval[gi][s] = 0;
+    const int64_t idx = base + gi;
+    const bool act = idx < cnt;
+    const int32_t v = act ? list[idx] : 0;
+    const int32_t beg = act ? rp[v] : 0, end = act ? rp[v + 1] : 0;
+    const int32_t own = act ? Lin[v] : -1;
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv && act) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
     }
-    if (lane == 0) own_sh[gi] = 0;
+    uint32_t T = 2 * G;  // power of two >= 2 d, at most TBL (d <= TBL / 2 for the rows of this class)
+    while (T < 2u * (uint32_t)(end - beg) && T < (uint32_t)TBL) T <<= 1;
+    const uint32_t mask = T - 1;
+    for (uint32_t e = lane; e < T; e += G) {
+      tkey[gi][e] = -1;
+      tval[gi][e] = 0;
+    }
     __syncthreads();
+    unsigned long long best = 0;
     for (int32_t i0 = beg + lane; i0 < end; i0 += G * kLoadBatch) {
       int32_t xs[kLoadBatch], cs[kLoadBatch];
 #pragma unroll
@@ -484,52 +501,37 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
       }
 #pragma unroll
       for (int u = 0; u < kLoadBatch; u++) xs[u] = Lin[xs[u]];
+      uint32_t hs[kLoadBatch];
+      int32_t old[kLoadBatch];
+      bool real[kLoadBatch];
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++) {  // claims first, all in flight
+        real[u] = i0 + u * G < end;
+        hs[u] = slot_hash(xs[u]) & mask;
+        old[u] = real[u] ? atomicCAS(&tkey[gi][hs[u]], -1, xs[u]) : -1;
+      }
 #pragma unroll
       for (int u = 0; u < kLoadBatch; u++) {
-        if (i0 + u * G >= end) break;
-        const int32_t x = xs[u];
-        uint32_t h = slot_hash(x) & (TBL - 1);
-        while (true) {
-          int32_t k = tkey[gi][h];
-          if (k == x) break;
-          if (k == -1) {
-            int32_t old = atomicCAS(&tkey[gi][h], -1, x);
-            if (old == -1 || old == x) break;
-          }
-          h = (h + 1) & (TBL - 1);
+        if (!real[u]) continue;
+        while (old[u] != -1 && old[u] != xs[u]) {  // taken by another label: probe on
+          hs[u] = (hs[u] + 1) & mask;
+          old[u] = atomicCAS(&tkey[gi][hs[u]], -1, xs[u]);
         }
-        atomicAdd(&tval[gi][h], (uint32_t)cs[u]);
       }
-    }
-    __syncthreads();
-    unsigned long long best = 0;
-    const int32_t own = act ? Lin[v] : -1;
-    int32_t b0 = 0;
-    uint32_t sl = salt;
-    if (gv && act) {
-      const GStat &g = gs[gv[v]];
-      b0 = g.base;
-      sl = g.salt;
-    }
-    for (int s = lane; s < TBL; s += G) {
-      int32_t k = tkey[gi][s];
-      if (k >= 0) {
-        uint32_t S = tval[gi][s];
-        best = umax64(best, cand_key(S, k - b0, sl));
-        if (k == own) own_sh[gi] = S;
-      }
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++)
+        old[u] = real[u] ? (int32_t)atomicAdd(&tval[gi][hs[u]], (uint32_t)cs[u]) : 0;
+#pragma unroll
+      for (int u = 0; u < kLoadBatch; u++)
+        if (real[u])
+          best = umax64(best, own_key((uint32_t)old[u] + (uint32_t)cs[u], xs[u] == own, xs[u] - b0, sl));
     }
     if constexpr (G <= 64) {
       best = grp_max<G>(best);
     } else {
       best = block_max(best, red);  // G == kBlock: one group per block
     }
-    __syncthreads();
-    if (act && lane == 0) {
-      uint32_t S_own = own_sh[gi];
-      if (end == beg || (uint32_t)(best >> 32) == S_own) Lout[v] = own;
-      else Lout[v] = key_label(best, sl) + b0;
-    }
+    if (act && lane == 0) Lout[v] = (end == beg || ((best >> 32) & 1)) ? own : key_label(best, sl) + b0;
     __syncthreads();
   }
 }
@@ -1169,9 +1171,11 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
                                                         const int32_t *__restrict__ w, const int32_t *list,
                                                         const int32_t *cnt_p, const int32_t *meta,
                                                         const int32_t *__restrict__ Lin, int32_t *tk, uint32_t *tv,
-                                                        const Status *st, const int32_t *__restrict__ gv) {
+                                                        unsigned long long *best, uint32_t salt, const Status *st,
+                                                        const int32_t *__restrict__ gv, const GStat *gs) {
   __shared__ int32_t lk[kHugeLocal];
   __shared__ uint32_t lv[kHugeLocal];
+  __shared__ unsigned long long red[kBlock / 64];
   if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
@@ -1213,14 +1217,26 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
     int32_t *K = tk + meta[3 * (int64_t)i + 1];
     uint32_t *V = tv + meta[3 * (int64_t)i + 1];
     const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
+    const int32_t own = Lin[v];
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
+    }
     // one insertion per distinct label; a thread's first probes are all in
-    // flight before any of their results is looked at
+    // flight before any of their results is looked at. The returned partial
+    // sum plus the chunk's sum bounds the label's final sum from below and the
+    // row's last update of the label sees it: the row's best key is the
+    // maximum over these updates (no pass over the table).
     constexpr int kPer = kHugeLocal / kBlock;
     int32_t xs[kPer], old[kPer];
-    uint32_t hs[kPer];
+    uint32_t hs[kPer], add[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; u++) {
       xs[u] = lk[u * kBlock + threadIdx.x];
+      add[u] = lv[u * kBlock + threadIdx.x];
       hs[u] = slot_hash(xs[u]) & mask;
     }
 #pragma unroll
@@ -1232,57 +1248,24 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
         hs[u] = (hs[u] + 1) & mask;
         old[u] = atomicCAS(&K[hs[u]], -1, xs[u]);
       }
-      atomicAdd(&V[hs[u]], lv[u * kBlock + threadIdx.x]);
     }
+#pragma unroll
+    for (int u = 0; u < kPer; u++) old[u] = xs[u] >= 0 ? (int32_t)atomicAdd(&V[hs[u]], add[u]) : 0;
+    unsigned long long key = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; u++)
+      if (xs[u] >= 0) key = umax64(key, own_key((uint32_t)old[u] + add[u], xs[u] == own, xs[u] - b0, sl));
+    key = block_max(key, red);
+    if (threadIdx.x == 0 && key) atomicMax(&best[i], key);
     __syncthreads();
-  }
-}
-
-// table scan: each wave takes one contiguous range of slots, 64 at a time.
-// Every table is a power of two of at least 2 * 4096 slots, so the tables
-// start at multiples of 8192 and 64 aligned slots lie in one table; the wave
-// finds the table of its first slot once and then steps through the table
-// ends. Per 64 slots the candidate keys are reduced and the row's best key
-// gets one maximum update.
-__global__ void k_huge_scan(const int32_t *meta, const int32_t *cnt_p, const int32_t *tk, const uint32_t *tv,
-                            unsigned long long *best, uint32_t salt, const Status *st, const int32_t *list,
-                            const int32_t *__restrict__ gv, const GStat *gs) {
-  if (!gv && st->err) return;
-  const int32_t cnt = *cnt_p;
-  const int64_t slots = st->huge_slots;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
-  const int64_t span = ((slots + nwaves - 1) / nwaves + 63) & ~(int64_t)63;
-  const int64_t lo = wave * span, hi = min<int64_t>(slots, lo + span);
-  if (lo >= hi) return;
-  int32_t i = huge_find(meta, cnt, (int32_t)lo, 1);
-  int64_t row_end = i + 1 < cnt ? meta[3 * (int64_t)(i + 1) + 1] : slots;
-  for (int64_t s0 = lo; s0 < hi; s0 += 64) {
-    while (s0 >= row_end) {  // next table (uniform across the wave)
-      i++;
-      row_end = i + 1 < cnt ? meta[3 * (int64_t)(i + 1) + 1] : slots;
-    }
-    int32_t b0 = 0;
-    uint32_t sl = salt;
-    if (gv) {
-      const GStat &g = gs[gv[list[i]]];
-      b0 = g.base;
-      sl = g.salt;
-    }
-    const int64_t s = s0 + lane;
-    const int32_t k = s < slots ? tk[s] : -1;
-    unsigned long long key = k >= 0 ? cand_key(tv[s], k - b0, sl) : 0ull;
-    key = grp_max<64>(key);
-    if (lane == 0 && key) atomicMax(&best[i], key);
   }
 }
 
 // final decision per huge vertex
 __global__ void k_huge_final(const int32_t *rp, const int32_t *list, const int32_t *cnt_p, const int32_t *meta,
-                             const unsigned long long *best, const int32_t *Lin, const int32_t *tk,
-                             const uint32_t *tv, int32_t *Lout, long long *deg, uint32_t salt, int mode,
-                             Status *st, const int32_t *__restrict__ gv, const GStat *gs) {
+                             const unsigned long long *best, const int32_t *Lin, int32_t *Lout, long long *deg,
+                             uint32_t salt, int mode, Status *st, const int32_t *__restrict__ gv,
+                             const GStat *gs) {
   if (!gv && st->err) return;
   const int32_t cnt = *cnt_p;
   for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
@@ -1296,19 +1279,9 @@ __global__ void k_huge_final(const int32_t *rp, const int32_t *list, const int32
       sl = g.salt;
     }
     if (mode == 1) {
-      // own label's sum by probing the row's table
-      const int32_t own = Lin[v];
-      const int32_t *K = tk + meta[3 * (int64_t)i + 1];
-      const uint32_t *V = tv + meta[3 * (int64_t)i + 1];
-      const uint32_t mask = (uint32_t)meta[3 * (int64_t)i + 2] - 1;
-      uint32_t h = slot_hash(own) & mask, S_own = 0;
-      for (uint32_t probes = 0; probes <= mask; probes++) {
-        int32_t k = K[h];
-        if (k == own) { S_own = V[h]; break; }
-        if (k == -1) break;
-        h = (h + 1) & mask;
-      }
-      Lout[v] = ((uint32_t)(b >> 32) == S_own) ? own : key_label(b, sl) + b0;
+      // the best key (S, own, -prio) of k_huge_insert: its own bit is set
+      // exactly when the own label attains the maximum sum
+      Lout[v] = ((b >> 32) & 1) ? Lin[v] : key_label(b, sl) + b0;
     } else {
       Lout[v] = key_label(b, sl) + b0;
       if (mode == 2 && !gv) {
@@ -1565,6 +1538,71 @@ __global__ void k_apply_ids(const int32_t *L, const int32_t *ids, int32_t n, int
     }
   }
 }
+// ------------------------------------------------------------ correcting step
+// Section 4.1's correcting algorithm (fixMisplacedVertices of Algorithm 1):
+// a vertex of a cluster C with 2 <= |C| <= floor(log2 n) is misplaced if its
+// removal lowers the minimum weighted degree of the contracted graph; per
+// cluster at most one, the one leaving C - {v} the smallest degree (smallest
+// v on ties). With out(v) the weight from v to other clusters and c(v) its
+// degree, C - {v} has degree cut(C) - out(v) + (c(v) - out(v)).
+__global__ void k_fix_clear(int32_t *cnt, unsigned long long *cut, unsigned long long *key, int32_t n, Status *st) {
+  for (int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x; x < n; x += (int64_t)gridDim.x * kBlock) {
+    cnt[x] = 0;
+    cut[x] = 0;
+    key[x] = ~0ull;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->fix_delta = ~0ull;
+}
+// one wave per row: out(v), the member count and the cluster's degree
+__global__ void k_fix_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           const int32_t *__restrict__ w, const int32_t *__restrict__ L, int32_t n, int32_t *cnt,
+                           uint32_t *out, unsigned long long *cut) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+  for (int64_t v = wave; v < n; v += nw) {
+    const int32_t lv = L[v];
+    const int32_t beg = rp[v], end = rp[v + 1];
+    unsigned long long o = 0;
+    for (int32_t i = beg + lane; i < end; i += 64)
+      if (L[col[i]] != lv) o += (uint32_t)w[i];
+    o = grp_sum<64>(o);
+    if (lane == 0) {
+      out[v] = (uint32_t)o;  // <= the total weight <= INT32_MAX
+      atomicAdd(&cnt[lv], 1);
+      if (o) atomicAdd(&cut[lv], o);
+    }
+  }
+}
+// minimum weighted degree of the contracted graph (every cluster)
+__global__ void k_fix_delta(const int32_t *cnt, const unsigned long long *cut, int32_t n, Status *st) {
+  unsigned long long m = ~0ull;
+  for (int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x; x < n; x += (int64_t)gridDim.x * kBlock)
+    if (cnt[x] > 0) m = umin64(m, cut[x]);
+  m = grp_min<64>(m);
+  if ((threadIdx.x & 63) == 0 && m != ~0ull) atomicMin(&st->fix_delta, m);
+}
+// candidate removals: (degree of C - {v}) << 32 | v, minimum per cluster
+__global__ void k_fix_cand(const int32_t *__restrict__ L, const long long *__restrict__ deg, const int32_t *cnt,
+                           const unsigned long long *cut, const uint32_t *out, int32_t n, int32_t limit,
+                           const Status *st, unsigned long long *key) {
+  const unsigned long long delta = st->fix_delta;
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    const int32_t lv = L[v];
+    const int32_t c = cnt[lv];
+    if (c < 2 || c > limit) continue;
+    const unsigned long long rest = cut[lv] + (unsigned long long)deg[v] - 2ull * out[v];
+    if (rest < delta) atomicMin(&key[lv], (rest << 32) | (uint32_t)v);
+  }
+}
+// the chosen vertex of each cluster becomes a singleton with label n + v
+__global__ void k_fix_apply(int32_t *L, const unsigned long long *key, int32_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    const unsigned long long k = key[L[v]];
+    if (k != ~0ull && (int32_t)(uint32_t)k == (int32_t)v) L[v] = n + (int32_t)v;
+  }
+}
+
 // single solve: cl[v] = ids[L[v]] and, in the same pass, map[u] <- ids[L[map[u]]]
 // (the composed map reads the ids directly, so it need not wait for cl)
 __global__ void k_apply_compose(const int32_t *L, const int32_t *ids, int32_t n, int32_t *cl, int32_t *map,
@@ -3335,8 +3373,8 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(
       g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, nullptr, nullptr, nullptr, w.huge_best, w.deg, salt,
       level0 ? 2 : 0, w.st, gv, gs);
-  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, nullptr, nullptr, L,
-                                     w.deg, salt, level0 ? 2 : 0, w.st, gv, gs);
+  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, L, w.deg, salt,
+                                     level0 ? 2 : 0, w.st, gv, gs);
   return hipGetLastError();
 }
 
@@ -3368,11 +3406,10 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);
   k_huge_insert<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, list6, cnt6,
                                                                      w.huge_meta, Lin, w.huge_tab_key,
-                                                                     w.huge_tab_val, w.st, gv);
-  k_huge_scan<<<2048, kBlock, 0, s>>>(w.huge_meta, cnt6, w.huge_tab_key, w.huge_tab_val, w.huge_best, salt, w.st,
-                                      list6, gv, gs);
-  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, Lin, w.huge_tab_key,
-                                     w.huge_tab_val, Lout, nullptr, salt, 1, w.st, gv, gs);
+                                                                     w.huge_tab_val, w.huge_best, salt, w.st, gv,
+                                                                     gs);
+  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, Lin, Lout, nullptr, salt, 1,
+                                     w.st, gv, gs);
   return hipGetLastError();
 }
 
@@ -3382,14 +3419,16 @@ hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchV
   return hipGetLastError();
 }
 
-hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const BatchView *bv, int32_t *gv_new) {
+hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const BatchView *bv, int32_t *gv_new,
+                   int64_t lspace) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   const GStat *gs = bv ? bv->gs : nullptr;
-  hipError_t e = fill_i32(w.ids, 0, (int64_t)n + 1, s);
+  if (lspace < 0) lspace = n;
+  hipError_t e = fill_i32(w.ids, 0, lspace + 1, s);
   if (e != hipSuccess) return e;
   k_flag_labels<<<grid_for(n), kBlock, 0, s>>>(L, n, w.ids, gv, gs);
   // batched: ids[n] = total too, the end of the last graph's range
-  e = scan_exclusive(w, w.ids, w.ids, bv ? (int64_t)n + 1 : n, &w.st->k, s);
+  e = scan_exclusive(w, w.ids, w.ids, bv ? lspace + 1 : lspace, &w.st->k, s);
   if (e != hipSuccess) return e;
   if (bv) {
     k_apply_ids<<<grid_for(n), kBlock, 0, s>>>(L, w.ids, n, w.cl, gv, gs, gv_new);
@@ -3409,6 +3448,20 @@ __global__ void k_init_map(int32_t *map, int32_t n, unsigned long long *lb_state
     if (u < lb_words) lb_state[u] = 0;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *lb_ticket = 0;
+}
+
+hipError_t fix_misplaced(const DGraph &g, Work &w, int32_t *L, hipStream_t s) {
+  const int32_t n = g.n;
+  if (n <= 0) return hipSuccess;
+  int32_t limit = 0;  // floor(log2 n)
+  while (((int64_t)1 << (limit + 1)) <= (int64_t)n) limit++;
+  k_fix_clear<<<grid_for(n), kBlock, 0, s>>>(w.fix_cnt, w.fix_cut, w.fix_key, n, w.st);
+  k_fix_rows<<<grid_for(64ll * n, kBlock, 1u << 16), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, L, n, w.fix_cnt,
+                                                                     w.fix_out, w.fix_cut);
+  k_fix_delta<<<grid_for(n, kBlock, 4096), kBlock, 0, s>>>(w.fix_cnt, w.fix_cut, n, w.st);
+  k_fix_cand<<<grid_for(n), kBlock, 0, s>>>(L, w.deg, w.fix_cnt, w.fix_cut, w.fix_out, n, limit, w.st, w.fix_key);
+  k_fix_apply<<<grid_for(n), kBlock, 0, s>>>(L, w.fix_key, n);
+  return hipGetLastError();
 }
 
 hipError_t init_map(Work &w, hipStream_t s) {

@@ -31,6 +31,8 @@ def canon(events, graphs_from_contract=True):
         k = ev["kind"]
         if k == 1:
             out.append(("lp", ev["round"], ev["iter"], ev["labels"].tobytes()))
+        elif k == 6:
+            out.append(("fix", ev["round"], ev["labels"].tobytes()))
         elif k == 2:
             out.append(("graph", ev["level"], ev["row_ptr"].tobytes(), ev["col"].tobytes(), ev["w"].tobytes(),
                         ev["deg"].tobytes(), ev["cl"].tobytes()))

@@ -264,3 +264,24 @@ def test_session_waves_reuse_slots():
         assert got(g, *results[i]) == want, (i, g.n)
     assert oracle.ST_COLLAPSED in statuses  # the case that leaves rows behind is exercised
 
+
+def test_session_two_lanes():
+    """Small and large requests (more than 2^20 arcs) in one session: the
+    large lane runs on its own stream and thread, admits in waves, and every
+    result equals the oracle's for that graph alone."""
+    large = [gg.planted(int(n), 32.0, 10, 1, 100, 950 + s) for s, n in enumerate([40000, 36000, 44000, 38000])]
+    assert all(g.nnz > (1 << 20) for g in large)
+    small = [gg.c1_planted(s) for s in range(4)] + [gg.rhg(6000, 24.0, 5.0, 9, wlo=1, whi=100)] + \
+        [load_golden(name)[0] for name in GOLDEN]
+    gs = large + small
+    dev = [to_dev(g) for g in gs]
+    kw = dict(lp_iters=2, n0=64, seed=1)
+    one = max(vc.batch_workspace_bytes([d], vc.params(**kw)) for d in dev[:len(large)])
+    sess = vc.Session(int(max(one * 2.5 / 0.75, 600 << 20)), **kw)
+    rng = np.random.default_rng(3)
+    order = list(range(len(gs)))
+    rng.shuffle(order)
+    results = _serve_all(sess, dev, order, arrivals_per_step=2, rng=rng)
+    sess.close()
+    for i, g in enumerate(gs):
+        assert got(g, *results[i]) == expect(g, kw), (i, g.n)

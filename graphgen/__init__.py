@@ -233,3 +233,26 @@ def c5_make(p) -> Graph:
         return rhg(max(n, 8), deg, 5.0, s, 1, 100, True)
     _, n, d, kx, s = p
     return planted(n, d, kx, 1, 100, s)
+
+
+def reweight_device(row_ptr, col, seed: int):
+    """Fresh symmetric weights U{1..100} for a device CSR (torch int32 tensors,
+    rows sorted by column): every undirected edge {u, v} gets one draw of a
+    seeded torch generator on the tensors' device, shared by its two arcs.
+    Used to make each request of a served stream a distinct weighted graph on
+    a topology drawn from a pool."""
+    import torch
+    dev = col.device
+    n = row_ptr.numel() - 1
+    nnz = col.numel()
+    if nnz == 0:
+        return torch.zeros(0, dtype=torch.int32, device=dev)
+    rows = torch.repeat_interleave(torch.arange(n, device=dev, dtype=torch.int64),
+                                   (row_ptr[1:] - row_ptr[:-1]).to(torch.int64))
+    c = col.to(torch.int64)
+    keys = rows * n + c               # ascending: rows ascend, columns ascend within a row
+    rev = torch.searchsorted(keys, c * n + rows)   # position of the reverse arc (v, u)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed) & (2**63 - 1))
+    draw = torch.randint(1, 101, (nnz,), generator=gen, device=dev, dtype=torch.int32)
+    return torch.where(rows < c, draw, draw[rev]).contiguous()

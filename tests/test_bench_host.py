@@ -102,3 +102,30 @@ def test_more_than_one_gpu_is_refused():
     assert p.returncode == 2
     assert "one GPU" in p.stderr
     assert p.stdout == ""
+
+
+def test_roofline_ignores_the_sweep_span(fake_root):
+    prof = {"k_lp_tile": {"launches": 4, "total_ms": 0.8, "bytes": 4 * 400e6},
+            "lp_contract_sweep": {"launches": 4, "total_ms": 2.4, "bytes": 4 * 1.0e9}}
+    assert bench.roofline(prof, "wl")["kernel"] == "k_lp_tile"
+    s = bench.sweep_roofline(prof)
+    assert s["avg_us"] == pytest.approx(600.0)
+    assert s["achieved"] == pytest.approx(1.0e9 / 600e-6 / 1e9, abs=0.1)
+    assert s["frac"] == pytest.approx(s["achieved"] / bench.HBM_PEAK_GBS, abs=1e-4)
+    assert s["algorithmic_bytes"] == 1_000_000_000
+    assert bench.sweep_roofline({"k_lp_tile": prof["k_lp_tile"]}) is None
+
+
+def test_median():
+    assert bench.median([3.0, 1.0, 2.0]) == 2.0
+    assert bench.median([4.0, 1.0, 2.0, 3.0]) == 2.5
+    assert bench.median([5.0]) == 5.0
+
+
+def test_cpu_child_times_the_oracle_on_the_planted_graph():
+    env = dict(os.environ, OMP_NUM_THREADS="2")
+    p = subprocess.run([sys.executable, os.path.join(HERE, "bench.py"), "--cpu-child", "c1", "--cpu-budget", "1",
+                        "--cpu-runs", "2"], capture_output=True, text=True, timeout=300, env=env)
+    assert p.returncode == 0, p.stderr
+    rec = json.loads(p.stdout.strip().splitlines()[-1])
+    assert rec["threads"] == 2 and 1 <= rec["runs"] <= 2 and rec["value"] > 0

@@ -215,19 +215,31 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, command):
     hash, which is how the roofline's "traffic" knows it is still current."""
     import csv
 
-    def per_kernel(path, counter):
-        copy_best, vals = 0.0, {k: [] for k in TIMED_UNITS.get(kernel, [kernel])}
+    def rows(path):
+        """(kernel name, counter name, value in KiB) per dispatch, from the
+        counter CSV or from the rocpd database rocprofv3 writes by default"""
+        if path.endswith(".db"):
+            import sqlite3
+            db = sqlite3.connect(path)
+            for name, cname, val in db.execute("select kernel_name, counter_name, value from counters_collection"):
+                yield name, cname, float(val)
+            db.close()
+            return
         with open(path) as f:
             for r in csv.DictReader(f):
-                if r["Counter_Name"] != counter:
-                    continue
-                v = float(r["Counter_Value"]) * 1024.0
-                name = r["Kernel_Name"]
-                if "copyBuffer" in name:
-                    copy_best = max(copy_best, v)
-                for k in vals:
-                    if "::%s(" % k in name or "::%s<" % k in name:
-                        vals[k].append(v)
+                yield r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+
+    def per_kernel(path, counter):
+        copy_best, vals = 0.0, {k: [] for k in TIMED_UNITS.get(kernel, [kernel])}
+        for name, cname, kib in rows(path):
+            if cname != counter:
+                continue
+            v = kib * 1024.0
+            if "copyBuffer" in name:
+                copy_best = max(copy_best, v)
+            for k in vals:
+                if "::%s(" % k in name or "::%s<" % k in name:
+                    vals[k].append(v)
         if not copy_best or not all(vals.values()):
             raise SystemExit("%s: no copy probe or no %s dispatch with %s" % (path, kernel, counter))
         # per timed unit: the sum over its kernels of the mean per dispatch

@@ -171,7 +171,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   const int64_t tiles = (nnz + kRsTile - 1) / kRsTile + 1;
   const int64_t huge_rows = nnz / (kHugeChunk + 1) + 1;
   const int64_t ntiles = (nnz + n) / kTile + 2;
-  const int64_t nseg = ntiles + 3 * (nnz / kTile + 1) + 2;
+  const int64_t nseg = ntiles + 4 * (nnz / kTile + 1) + 2;
   int64_t maxscan = std::max<int64_t>({nnz, 2 * (int64_t)n + 1, 256 * tiles, nseg});
   L.add(sizeof(Status));                       // 0 st
   for (int b = 0; b < 2; b++) {
@@ -248,7 +248,7 @@ bool carve(void *ws, size_t bytes, int32_t n, int64_t nnz, Work &w, int64_t map_
   w.hist = (int32_t *)at(20);
   {
     const int64_t tiles = (nnz + kRsTile - 1) / kRsTile + 1;
-    const int64_t nseg = (nnz + n) / kTile + 2 + 3 * (nnz / kTile + 1) + 2;
+    const int64_t nseg = (nnz + n) / kTile + 2 + 4 * (nnz / kTile + 1) + 2;
     w.lb_tiles = scan_tiles_max(std::max<int64_t>({nnz, 2 * (int64_t)n + 1, 256 * tiles, nseg}));
     w.lb_state = (unsigned long long *)at(21);
     w.lb_ticket = (uint32_t *)(w.lb_state + w.lb_tiles);

@@ -17,7 +17,7 @@ constexpr int32_t kMaxVertices = VIECUT_MAX_VERTICES;
 // Static device scratch of the allocation-free single solve (one per GPU).
 constexpr size_t kScratchBytes = VIECUT_NOALLOC_SCRATCH_BYTES;
 constexpr int kMaxScratchDevices = 64;
-constexpr int kBins = 7;      // degree classes for per-vertex work
+constexpr int kBins = 8;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
 // Row-aligned arc tiles: tile t holds the rows v with rp[v] + v in
 // [t*kTile, (t+1)*kTile). A row with d >= kTile arcs is always the last row of
@@ -30,12 +30,14 @@ constexpr int kTileArcs = 2 * kTile;
 constexpr int kPerThread = kTileArcs / kTB;  // up to 8 consecutive arcs per thread
 
 // Degree classes (by arc count d of the row). Only the long classes are
-// listed per level: 4: kTile <= d < 1024 (a wave per row, LDS table),
-// 5: 1024 <= d <= 4096 (a workgroup per row, LDS table), 6: d > 4096 (rows
-// split into 4096-arc chunks sharing a global table). Shorter rows are
-// handled by the arc tiles.
+// listed per level: 4: kTile <= d < 512 and 5: 512 <= d < 1024 (a wave per
+// row, LDS tables of 1024 / 2048 slots: the smaller table keeps more waves
+// resident), 6: 1024 <= d <= 4096 (a workgroup per row, LDS table), 7: d >
+// 4096 (rows split into kHugeChunk-arc chunks sharing a global table).
+// Shorter rows are handled by the arc tiles.
+constexpr int kBinHuge = 7;
 __host__ __device__ inline int degree_bin(int32_t d) {
-  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d < 1024 ? 4 : d <= 4096 ? 5 : 6;
+  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d < 512 ? 4 : d < 1024 ? 5 : d <= 4096 ? 6 : 7;
 }
 
 enum : int32_t {

@@ -298,17 +298,18 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int
 // Lists of long rows (classes 4-6 of degree_bin), appended per workgroup:
 // LDS counters, then one global reservation per class and workgroup.
 // One pass over the rows of a level: the first row of every arc tile (into
-// meta[t].x, see above) and the lists of long rows (classes 4-6 of
+// meta[t].x, see above) and the lists of long rows (classes 4-7 of
 // degree_bin), appended per workgroup: LDS counters, then one global
 // reservation per class and workgroup.
 __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, int64_t stride, int32_t *bins,
                            Status *st) {
-  __shared__ int32_t cnt[3], base[3];
+  constexpr int kLong = kBins - 4;  // long classes 4 .. kBins - 1
+  __shared__ int32_t cnt[kLong], base[kLong];
   // an invalid row_ptr (flagged by k_check_rowptr, earlier on the stream)
   // could name tiles outside [0, ntiles): nothing is built from it
   if (st->err) return;
   for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 <= n; b0 += (int64_t)gridDim.x * kBlock) {
-    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    if (threadIdx.x < kLong) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t v = b0 + threadIdx.x;
     if (v <= n) {
@@ -320,7 +321,7 @@ __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *m
     const int cls = d >= kTile ? degree_bin(d) - 4 : -1;
     const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
     __syncthreads();
-    if (threadIdx.x < 3)
+    if (threadIdx.x < kLong)
       base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&st->bin_cnt[4 + threadIdx.x], cnt[threadIdx.x]) : 0;
     __syncthreads();
     if (cls >= 0) bins[(int64_t)(4 + cls) * stride + base[cls] + pos] = (int32_t)v;
@@ -1817,6 +1818,71 @@ __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ r
   }
 }
 
+// Exclusive prefix sum over the 64 lanes of a wave; *total gets the sum.
+__device__ __forceinline__ int32_t wave_excl_scan(int32_t x, int32_t &total) {
+  const int lane = threadIdx.x & 63;
+  int32_t v = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(v, d, 64);
+    if (lane >= d) v += y;
+  }
+  total = __shfl(v, 63, 64);
+  return v - x;
+}
+
+// rows of 256..1023 arcs: one wave per row, 8 arcs per lane per pass with
+// consecutive lanes on consecutive arcs; the wave's inter-cluster arcs are
+// appended in order with a wave prefix sum (no workgroup barriers)
+__global__ __launch_bounds__(kBlock) void k_emit_wave(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
+                                                       const int32_t *list, const int32_t *cnt_p, const Status *st,
+                                                       unsigned long long *__restrict__ keys,
+                                                       int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                                       int32_t *__restrict__ seg_cnt) {
+  constexpr int kPer = 8;
+  const int key_bits = bits_for(st->k);
+  const int32_t cnt = *cnt_p;
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
+  for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; r < cnt; r += nwaves) {
+    const int32_t v0 = list[r];
+    const int32_t cv = cl[v0];
+    const int32_t beg = rp[v0], end = rp[v0 + 1];
+    int64_t out = beg;
+    for (int32_t c0 = beg; c0 < end; c0 += 64 * kPer) {
+      int32_t cus[kPer], cs[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; k++) {  // clamped loads, all issued before use
+        const int32_t a = min(c0 + lane + 64 * k, end - 1);
+        cus[k] = col[a];
+        cs[k] = w[a];
+      }
+#pragma unroll
+      for (int k = 0; k < kPer; k++) cus[k] = cl[cus[k]];
+      uint32_t fl = 0;
+#pragma unroll
+      for (int k = 0; k < kPer; k++)
+        if (c0 + lane + 64 * k < end && cus[k] != cv) fl |= 1u << k;
+      int32_t tot;
+      const int32_t off = wave_excl_scan(__popc(fl), tot);
+      int32_t o = 0;
+#pragma unroll
+      for (int k = 0; k < kPer; k++)
+        if (fl & (1u << k)) {
+          keys[out + off + o] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cus[k];
+          vals[out + off + o] = cs[k];
+          o++;
+        }
+      out += tot;
+    }
+    if (lane == 0) {
+      first[r] = beg;
+      seg_cnt[r] = (int32_t)(out - beg);
+    }
+  }
+}
+
 // long rows: one workgroup per row, chunks of kBlock * kPerThread arcs
 __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
@@ -1852,6 +1918,50 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
     if (threadIdx.x == 0) {
       first[r] = beg;
       seg_cnt[r] = (int32_t)(out - beg);
+    }
+  }
+}
+
+// huge rows (more than 4096 arcs): one workgroup per 4096-arc chunk (the
+// chunk offsets of k_huge_plan), one segment per chunk, so that a hub row is
+// spread over many workgroups instead of one
+__global__ __launch_bounds__(kBlock) void k_emit_huge(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
+                                                       const int32_t *list, const int32_t *cnt_p, const int32_t *meta,
+                                                       const Status *st, unsigned long long *__restrict__ keys,
+                                                       int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                                       int32_t *__restrict__ seg_cnt) {
+  __shared__ int32_t sh[kBlock / 64];
+  const int key_bits = bits_for(st->k);
+  const int32_t cnt = *cnt_p;
+  const int32_t items = st->huge_items;
+  for (int32_t p = blockIdx.x; p < items; p += gridDim.x) {
+    const int32_t i = huge_find(meta, cnt, p, 0);
+    const int32_t v0 = list[i];
+    const int32_t cv = cl[v0];
+    const int32_t beg = rp[v0] + (p - meta[3 * (int64_t)i]) * kHugeChunk;
+    const int32_t end = min(rp[v0 + 1], beg + kHugeChunk);
+    int64_t out = beg;
+    for (int32_t c0 = beg; c0 < end; c0 += kBlock * kPerThread) {
+      const int32_t acnt = min(kBlock * kPerThread, end - c0);
+      const int32_t i0 = threadIdx.x * kPerThread;
+      int32_t cus[kPerThread], cs[kPerThread];
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) {  // clamped loads, all issued before use
+        const int32_t a = c0 + min(i0 + k, acnt - 1);
+        cus[k] = col[a];
+        cs[k] = w[a];
+      }
+#pragma unroll
+      for (int k = 0; k < kPerThread; k++) cus[k] = cl[cus[k]];
+      int32_t tot;
+      emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, key_bits, out, keys, vals, sh, tot);
+      out += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      first[p] = beg;
+      seg_cnt[p] = (int32_t)(out - beg);
     }
   }
 }
@@ -3355,7 +3465,7 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   }
   if (!bv && level0) k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
   // long rows: a wave per row up to 4096 arcs, chunked beyond
-  for (int b = 4; b <= 5; b++) {
+  for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
     if (items > 0) {
       const int32_t *list = w.bins + (int64_t)b * w.n_in;
@@ -3364,10 +3474,10 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
                                                                           w.st, gv, gs);
     }
   }
-  if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
+  if (bin_items(known, kBinHuge, 1) <= 0) return hipGetLastError();
   // huge rows: chunked
-  const int32_t *list6 = w.bins + 6ll * w.n_in;
-  const int32_t *cnt6 = &w.st->bin_cnt[6];
+  const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
+  const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st,
                                    level0 ? w.deg : nullptr);
   k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(
@@ -3397,11 +3507,12 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);
     }
   }
-  launch_tab<64, 2048>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
-  launch_tab<256, 8192>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);
-  if (bin_items(known, 6, 1) <= 0) return hipGetLastError();
-  const int32_t *list6 = w.bins + 6ll * w.n_in;
-  const int32_t *cnt6 = &w.st->bin_cnt[6];
+  launch_tab<64, 1024>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
+  launch_tab<64, 2048>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);
+  launch_tab<256, 8192>(g, w, 6, known, Lin, Lout, salt, s, gv, gs);
+  if (bin_items(known, kBinHuge, 1) <= 0) return hipGetLastError();
+  const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
+  const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st, nullptr);
   k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);
   k_huge_insert<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, list6, cnt6,
@@ -3473,19 +3584,35 @@ hipError_t init_map(Work &w, hipStream_t s) {
 
 hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s) {
   const int64_t long_max = g.nnz / kTile + 1;
-  const int64_t nseg = w.ntiles + 3 * long_max;
+  constexpr int kLong = kBins - 4;  // one region of long_max segments per long class
+  const int64_t nseg = w.ntiles + kLong * long_max;
   // long-row segments beyond the device-side row counts stay empty
-  hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, 3 * long_max, s);
+  hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, kLong * long_max, s);
   if (e != hipSuccess) return e;
   k_emit_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles,
                                                                  w.st, w.keys[0], w.vals[0], w.seg, w.seg_cnt);
-  for (int b = 4; b <= 6; b++) {
+  for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;
     const int64_t s0 = w.ntiles + (b - 4) * long_max;
-    k_emit_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in,
-                                                            &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0],
-                                                            w.seg + s0, w.seg_cnt + s0);
+    if (b < 6)  // rows of fewer than 1024 arcs: a wave per row
+      k_emit_wave<<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(
+          g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0],
+          w.seg + s0, w.seg_cnt + s0);
+    else
+      k_emit_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl,
+                                                              w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st,
+                                                              w.keys[0], w.vals[0], w.seg + s0, w.seg_cnt + s0);
+  }
+  if (bin_items(known, kBinHuge, 1) > 0) {
+    // chunks of the huge rows (at most long_max of them: one segment each)
+    const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
+    const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
+    const int64_t s0 = w.ntiles + (kBinHuge - 4) * long_max;
+    k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st, nullptr);
+    k_emit_huge<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, list6, cnt6,
+                                                                      w.huge_meta, w.st, w.keys[0], w.vals[0],
+                                                                      w.seg + s0, w.seg_cnt + s0);
   }
   e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
   if (e != hipSuccess) return e;
@@ -3596,10 +3723,11 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
     k_pr_rows<2 * kPrLds, false><<<grid_for(g.nnz / kPrSmallMax + 1, 1, 1024), kBlock, 0, s>>>(
         g.row_ptr, g.col, g.w, degu, list, 1, g.n, w.mark, w.st, nullptr, nullptr);
   }
-  const int64_t items6 = known ? known[6] : g.nnz / kHugeChunk + 1;
+  const int64_t items6 = known ? known[kBinHuge] : g.nnz / kHugeChunk + 1;
   if (items6 > 0) {
-    k_pr_long<<<grid_for(items6, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.bins + 6ll * w.n_in,
-                                                          &w.st->bin_cnt[6], w.mark, heavy, w.st, gv, gs);
+    k_pr_long<<<grid_for(items6, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu,
+                                                          w.bins + (int64_t)kBinHuge * w.n_in,
+                                                          &w.st->bin_cnt[kBinHuge], w.mark, heavy, w.st, gv, gs);
     k_pr_heavy<<<1024, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, g.n, heavy, w.mark, w.st, gv, gs);
   }
   return hipGetLastError();
@@ -3609,7 +3737,7 @@ hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *r
   k_iota<<<grid_for(g.n), kBlock, 0, s>>>(w.parent, g.n);
   k_uf_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, w.mark, w.tile_meta, w.ntiles,
                                                                w.parent);
-  for (int b = 4; b <= 6; b++) {
+  for (int b = 4; b <= kBinHuge; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
     if (items <= 0) continue;
     k_uf_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, w.mark, w.bins + (int64_t)b * w.n_in,

@@ -615,6 +615,8 @@ def main():
                    "cut": cut, "rounds": info["rounds"], "kernel_n": info["kernel_n"]},
         "roofline": roofline(prof, args.workload),
         "sweep": sweep_roofline(prof),
+        # launch-shape table in use (the tuner's file beside the library, or the defaults)
+        "tuning": [l for l in vc.tuning_get().splitlines() if l.strip()],
     }
     log("roofline:", out["roofline"])
     log("sweep:", out["sweep"])

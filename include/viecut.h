@@ -313,6 +313,29 @@ int viecut_profile_enable(int on);
  * the solves that have returned (batched: the rounds completed). */
 int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
 
+/* ------------------------------------------------------------ launch-shape tuning */
+/* Measurement aid for the project's tuner (paper_1708_06127_amd/autotune.py),
+ * process-wide. Some launch shapes change no result, only speed: the sort
+ * elements from which radix blocks hold 4096 elements (radix_large_from), the
+ * segment count up to which the compaction searches all segment offsets per
+ * element (compact_direct_max), the union tile count from which batched PR
+ * marking of short rows merges rows from global memory (pr_merge_tiles), the
+ * row length splitting the 1024- and 2048-slot long-row LP classes
+ * (long_split, 256..512), and the long-row emission variant (emit_wave, 0/1).
+ * The library keeps one set per size bucket (arcs of the level being worked
+ * on, at most max_arcs; max_arcs < 0: no bound) and reads the table at load
+ * time from the file named by the environment variable VIECUT_TUNING, else
+ * viecut_tuning.txt beside the library; lines read
+ *   bucket <max_arcs> key=value ...
+ * viecut_tuning_set sets one key of one bucket (creating it with defaults);
+ * returns VIECUT_EINVAL for an unknown key or a value out of range. */
+int viecut_tuning_set(int64_t max_arcs, const char *key, int64_t value);
+/* Drops every bucket (back to the defaults; the file is not read again). */
+int viecut_tuning_clear(void);
+/* Writes the table in the file format into buf (len bytes, NUL-terminated);
+ * with buf == NULL returns the length needed. Returns the bytes written. */
+int viecut_tuning_get(char *buf, size_t len);
+
 /* Static message for a status code. */
 const char *viecut_strerror(int code);
 

@@ -30,7 +30,8 @@ EXPORTED = ["viecut_default_params", "viecut_workspace_bytes", "viecut_mincut", 
             "viecut_mincut_trace",
             "viecut_validate", "viecut_batch_workspace_bytes", "viecut_mincut_batch", "viecut_session_create",
             "viecut_session_submit", "viecut_session_step", "viecut_session_poll", "viecut_session_destroy",
-            "viecut_profile_enable", "viecut_profile_read", "viecut_strerror"]
+            "viecut_profile_enable", "viecut_profile_read", "viecut_tuning_set", "viecut_tuning_clear",
+            "viecut_tuning_get", "viecut_strerror"]
 
 
 class Csr(ctypes.Structure):
@@ -88,6 +89,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libviecut.so is not built (run __graft_entry__.build() or "
                            "python paper_1708_06127_amd/build.py)")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so that one runtime serves torch's memory and the library's launches
+    _torch()
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
     P = ctypes.POINTER
@@ -125,6 +129,12 @@ def load():
     lib.viecut_profile_enable.restype = ctypes.c_int
     lib.viecut_profile_read.argtypes = [P(KernelStat), i32]
     lib.viecut_profile_read.restype = ctypes.c_int
+    lib.viecut_tuning_set.argtypes = [ctypes.c_int64, ctypes.c_char_p, ctypes.c_int64]
+    lib.viecut_tuning_set.restype = ctypes.c_int
+    lib.viecut_tuning_clear.argtypes = []
+    lib.viecut_tuning_clear.restype = ctypes.c_int
+    lib.viecut_tuning_get.argtypes = [ctypes.c_char_p, sz]
+    lib.viecut_tuning_get.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -378,3 +388,38 @@ def profile_read():
         _check(k)
     return {out[i].name.decode(): {"launches": int(out[i].launches), "total_ms": float(out[i].total_ms),
                                    "bytes": float(out[i].bytes)} for i in range(k)}
+
+
+TUNING_KEYS = ("radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave")
+
+
+def tuning_set(max_arcs: int, key: str, value: int):
+    """Set one launch-shape choice for the size bucket bounded by max_arcs
+    (< 0: unbounded); see viecut_tuning_set."""
+    _check(load().viecut_tuning_set(int(max_arcs), key.encode(), int(value)))
+
+
+def tuning_clear():
+    _check(load().viecut_tuning_clear())
+
+
+def tuning_get() -> str:
+    lib = load()
+    n = lib.viecut_tuning_get(None, 0)
+    buf = ctypes.create_string_buffer(max(n, 1))
+    lib.viecut_tuning_get(buf, len(buf))
+    return buf.value.decode()
+
+
+def tuning_load_text(text: str):
+    """Replace the table by the one in `text` (the file format, as
+    tuning_get returns it)."""
+    tuning_clear()
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) < 2 or parts[0] != "bucket":
+            continue
+        bound = int(parts[1])
+        for kv in parts[2:]:
+            k, _, v = kv.partition("=")
+            tuning_set(bound, k, int(v))

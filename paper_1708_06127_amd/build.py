@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libviecut.so")
-SOURCES = ["vc_kernels.hip", "vc_driver.cpp", "vc_sw.cpp", "vc_batch.cpp"]
+SOURCES = ["vc_kernels.hip", "vc_driver.cpp", "vc_sw.cpp", "vc_batch.cpp", "vc_tuning.cpp"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # no packed fp32 instructions anywhere (the code is integer-only anyway)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -36,7 +36,7 @@ def build(verbose: bool = False) -> str:
             raise RuntimeError("hipcc failed on %s" % src)
         objs.append(obj)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-ldl", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -307,6 +307,17 @@ int solve_one(const viecut_csr *g, const viecut_params *p, void *ws, size_t ws_b
 // looked up on the first call per device and kept
 hipError_t scratch_address(int device, void **ptr);
 
+// Launch-shape choices that change no result, per size bucket (arcs of the
+// level): read at load time from the tuning file, else these defaults.
+struct Tuning {
+  int64_t radix_large_from = 1 << 22;    // sort elements from which radix blocks hold 4096 elements
+  int64_t compact_direct_max = 1 << 20;  // segments up to which each output element searches all offsets
+  int64_t pr_merge_tiles = 16384;        // batch unions: tiles from which short rows merge from global memory
+  int64_t long_split = 512;              // long rows below this many arcs take the 1024-slot LDS class
+  int64_t emit_wave = 1;                 // rows of 256..1023 arcs emitted by a wave per row (0: a workgroup)
+};
+Tuning tuning_for(int64_t arcs);
+
 // host helpers
 uint64_t splitmix64_at(uint64_t seed, uint64_t index);
 int64_t stoer_wagner_host(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *w,

@@ -302,7 +302,7 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int
 // degree_bin), appended per workgroup: LDS counters, then one global
 // reservation per class and workgroup.
 __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, int64_t stride, int32_t *bins,
-                           Status *st) {
+                           Status *st, int32_t long_split) {
   constexpr int kLong = kBins - 4;  // long classes 4 .. kBins - 1
   __shared__ int32_t cnt[kLong], base[kLong];
   // an invalid row_ptr (flagged by k_check_rowptr, earlier on the stream)
@@ -318,7 +318,8 @@ __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *m
       for (int64_t t = t_lo; t <= t_hi; t++) meta[t].x = (int32_t)v;
     }
     const int32_t d = v < n ? rp[v + 1] - rp[v] : 0;
-    const int cls = d >= kTile ? degree_bin(d) - 4 : -1;
+    // classes 4 and 5 split at long_split (<= 512) instead of degree_bin's 512
+    const int cls = d < kTile ? -1 : d < long_split ? 0 : d < 1024 ? 1 : degree_bin(d) - 4;
     const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
     __syncthreads();
     if (threadIdx.x < kLong)
@@ -1978,7 +1979,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_huge(const int32_t *__restrict_
 // two bounds.
 constexpr int kCompactItems = 4;
 constexpr int kCompactWin = 2048;
-constexpr int64_t kCompactDirectMax = 1 << 20;  // segments up to which every element searches alone
 
 // Last segment s in [0, nseg) with off[s] <= t, by the 32 lanes of one half
 // of wave 0 (off nondecreasing, off[0] = 0 <= t). Every lane of the wave calls
@@ -2096,7 +2096,6 @@ __global__ __launch_bounds__(kBlock) void k_compact(const int32_t *first, const 
 // matrix to scan, longer runs per digit in the scatter).
 constexpr int kRsItemsSmall = kRsTile / kBlock;
 constexpr int kRsItemsLarge = 4 * kRsItemsSmall;
-constexpr int64_t kRsLargeFrom = 1 << 22;  // elements
 
 template <int kRsItems>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const unsigned long long *keys, int64_t count, int shift, int32_t *hist, int32_t tiles) {
@@ -3390,8 +3389,8 @@ hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
 
 hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s) {
   w.ntiles = (int32_t)((g.nnz + g.n + kTile - 1) / kTile);
-  k_row_pass<<<grid_for((int64_t)g.n + 1, kBlock, 2048), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta,
-                                                                        w.n_in, w.bins, w.st);
+  k_row_pass<<<grid_for((int64_t)g.n + 1, kBlock, 2048), kBlock, 0, s>>>(
+      g.row_ptr, g.n, w.ntiles, w.tile_meta, w.n_in, w.bins, w.st, (int32_t)tuning_for(g.nnz).long_split);
   k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta, w.st, w.big_tiles);
   return hipGetLastError();
 }
@@ -3595,7 +3594,7 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;
     const int64_t s0 = w.ntiles + (b - 4) * long_max;
-    if (b < 6)  // rows of fewer than 1024 arcs: a wave per row
+    if (b < 6 && tuning_for(g.nnz).emit_wave)  // rows of fewer than 1024 arcs: a wave per row
       k_emit_wave<<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(
           g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0],
           w.seg + s0, w.seg_cnt + s0);
@@ -3616,7 +3615,7 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
   }
   e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
   if (e != hipSuccess) return e;
-  if (nseg <= kCompactDirectMax)
+  if (nseg <= tuning_for(g.nnz).compact_direct_max)
     k_compact_direct<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st,
                                                                        w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
   else
@@ -3644,7 +3643,7 @@ hipError_t radix_passes(Work &w, int64_t count, int total_bits, int &which, hipS
 
 hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s) {
   if (count <= 1) return hipSuccess;
-  return count >= kRsLargeFrom ? radix_passes<kRsItemsLarge>(w, count, total_bits, which, s)
+  return count >= tuning_for(count).radix_large_from ? radix_passes<kRsItemsLarge>(w, count, total_bits, which, s)
                                : radix_passes<kRsItemsSmall>(w, count, total_bits, which, s);
 }
 
@@ -3698,7 +3697,7 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
   const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
   // single solves always take the LDS variant; the merge variant is for the
   // large unions of a batch
-  const bool wide = !bv || w.ntiles < kXcdChunkMin;
+  const bool wide = !bv || w.ntiles < tuning_for(g.nnz).pr_merge_tiles;
   if (bv) {
     if (wide)
       k_pr_tile<true, kBlock><<<tg, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, degu, w.tile_meta, w.ntiles, w.mark, w.st,

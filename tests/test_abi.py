@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 import paper_1708_06127_amd as vc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -101,3 +103,42 @@ def test_noalloc_rejects_graphs_beyond_the_scratch_on_host():
     g.n, g.nnz = 8192, 8192 * 64
     assert vc.workspace_bytes(g.n, g.nnz) <= vc.NOALLOC_SCRATCH_BYTES  # the largest planted batch member fits
     assert lib.viecut_mincut_noalloc(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(res), None) == vc.EINVAL
+
+
+def test_tuning_table_on_host(tmp_path):
+    """The launch-shape table: keys and ranges checked, buckets kept in
+    order, the file format read back (no GPU: only host state)."""
+    vc.tuning_clear()
+    assert "bucket -1" in vc.tuning_get()
+    vc.tuning_set(1 << 26, "long_split", 384)
+    vc.tuning_set(-1, "radix_large_from", 1 << 24)
+    vc.tuning_set(1 << 20, "emit_wave", 0)
+    text = vc.tuning_get()
+    lines = [l for l in text.splitlines() if l.startswith("bucket")]
+    assert [int(l.split()[1]) for l in lines] == [1 << 20, 1 << 26, -1]
+    assert "long_split=384" in lines[1] and "radix_large_from=16777216" in lines[2] and "emit_wave=0" in lines[0]
+    for key, bad in [("long_split", 600), ("long_split", 100), ("emit_wave", 2), ("nonsense", 1)]:
+        with pytest.raises(vc.ViecutError):
+            vc.tuning_set(-1, key, bad)
+    vc.tuning_clear()
+    assert "long_split=512" in vc.tuning_get()
+
+
+def test_tuning_file_read_at_load(tmp_path):
+    """A fresh process reads the table from the file VIECUT_TUNING names."""
+    import os
+    import subprocess
+    import sys
+    f = tmp_path / "t.txt"
+    f.write_text("# tuned\nbucket 1000000 long_split=320 emit_wave=0\nbucket -1 radix_large_from=123\n"
+                 "bucket 5 long_split=9999\n")  # out of range: ignored
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = "import paper_1708_06127_amd as vc; print(vc.tuning_get())"
+    p = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120,
+                       env=dict(os.environ, VIECUT_TUNING=str(f)))
+    assert p.returncode == 0, p.stderr
+    lines = [l for l in p.stdout.splitlines() if l.startswith("bucket")]
+    assert lines[0].startswith("bucket 5 ") and "long_split=512" in lines[0]
+    assert lines[1].startswith("bucket 1000000 ") and "long_split=320" in lines[1] and "emit_wave=0" in lines[1]
+    assert lines[2].startswith("bucket -1 ") and "radix_large_from=123" in lines[2]
+    assert str(f) in p.stdout

@@ -379,12 +379,50 @@ struct Engine {
     drained = cnt;
     t_drain_read += now_ms() - t0;
 
-    // exact solve on the last level of graphs that left the loop unsolved
-    std::vector<int32_t> solve;
+    // exact solve on the last level of graphs that left the loop unsolved:
+    // kernel graphs of at most kDenseMax vertices on the device, one wave
+    // each, in place; larger ones gathered and solved on host threads
+    std::vector<int32_t> solve, dense;
     for (int32_t i = 0; i < m; i++)
-      if (he[i].fin == FIN_SOLVE && he[i].k >= 2 && he[i].lam_hat > 0) solve.push_back(i);
+      if (he[i].fin == FIN_SOLVE && he[i].k >= 2 && he[i].lam_hat > 0)
+        (he[i].k <= kDenseMax ? dense : solve).push_back(i);
     std::vector<int64_t> lk(m, INT64_MAX);
     std::vector<int64_t> foff(m, -1);
+    int64_t fdev = 0;  // flags written by the device solve come first
+    if (!dense.empty()) {
+      static_assert(sizeof(SwDesc) <= sizeof(GatherDesc), "descriptor staging");
+      static_assert(sizeof(long long) <= sizeof(SideDesc), "cut staging");
+      t0 = now_ms();
+      SwDesc *sd = h_gdesc.as<SwDesc>();
+      int32_t kmax = 2;
+      for (size_t j = 0; j < dense.size(); j++) {
+        const GStat &e = he[dense[j]];
+        SwDesc d{};
+        d.rp = w.rp[e.buf];
+        d.col = w.col[e.buf];
+        d.w = w.w[e.buf];
+        d.base = e.base;
+        d.k = e.k;
+        d.foff = (int32_t)fdev;
+        fdev += e.k;
+        kmax = std::max(kmax, e.k);
+        sd[j] = d;
+      }
+      if (fdev > (int64_t)cap.n + 1) return VIECUT_EDEVICE;  // one level holds them all
+      // the side descriptors' buffers are free until the side step below
+      long long *dcut = (long long *)d_sdesc, *hcut = h_sdesc.as<long long>();
+      VC_TRY(hipMemcpyAsync(d_gdesc, sd, sizeof(SwDesc) * dense.size(), hipMemcpyHostToDevice, s));
+      VC_TRY(exact_dense_batch((const SwDesc *)d_gdesc, (int32_t)dense.size(), kmax, w.flags8, dcut, s));
+      VC_TRY(hipMemcpyAsync(hcut, dcut, sizeof(long long) * dense.size(), hipMemcpyDeviceToHost, s));
+      VC_TRY(hipStreamSynchronize(s));
+      for (size_t j = 0; j < dense.size(); j++) {
+        const int32_t i = dense[j];
+        lk[i] = hcut[j];
+        if (hcut[j] < he[i].lam_hat) foff[i] = sd[j].foff;
+      }
+      n_solved += (int64_t)dense.size();
+      t_solve += now_ms() - t0;
+    }
     std::vector<uint8_t> flags;
     size_t pos = 0;
     while (pos < solve.size()) {  // in groups that fit the staging buffers
@@ -456,7 +494,7 @@ struct Engine {
         const int32_t i = solve[pos + j];
         lk[i] = kcut[j];
         if (kcut[j] < he[i].lam_hat) {
-          foff[i] = (int64_t)flags.size();
+          foff[i] = fdev + (int64_t)flags.size();
           flags.insert(flags.end(), kside[j].begin(), kside[j].end());
         }
       }
@@ -466,10 +504,10 @@ struct Engine {
     // sides and results
     t0 = now_ms();
     if (!flags.empty()) {
-      if (flags.size() > (size_t)cap.n + 1) return VIECUT_EDEVICE;  // one level holds them all
+      if (fdev + flags.size() > (size_t)cap.n + 1) return VIECUT_EDEVICE;  // one level holds them all
       if (!h_flags.ensure(flags.size())) return VIECUT_ENOMEM;
       std::memcpy(h_flags.p, flags.data(), flags.size());
-      VC_TRY(hipMemcpyAsync(w.flags8, h_flags.p, flags.size(), hipMemcpyHostToDevice, s));
+      VC_TRY(hipMemcpyAsync(w.flags8 + fdev, h_flags.p, flags.size(), hipMemcpyHostToDevice, s));
     }
     SideDesc *sd = h_sdesc.as<SideDesc>();
     int32_t wsum = 0;

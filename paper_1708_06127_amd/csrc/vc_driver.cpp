@@ -551,7 +551,17 @@ struct Solver {
     int64_t cut = st.lam_hat;
     int32_t out_level = st.wit_level;
     bool from_kernel = false;
-    if (!done && !(status & (ST_COLLAPSED | ST_DISCONNECTED)) && G.n >= 2) {
+    if (!done && !(status & (ST_COLLAPSED | ST_DISCONNECTED)) && G.n >= 2 && G.n <= kDenseMax) {
+      // small kernel graph: solved on the device, no hand-off to the host
+      VC_TRY(exact_dense(G, w, side, s));
+      rc = sync_status();
+      if (rc) return rc;
+      if (st.sw_cut < cut) {
+        cut = st.sw_cut;
+        out_level = -1;
+      }
+      from_kernel = true;  // the side is written
+    } else if (!done && !(status & (ST_COLLAPSED | ST_DISCONNECTED)) && G.n >= 2) {
       const size_t b_rp = sizeof(int32_t) * ((size_t)G.n + 1), b_arc = sizeof(int32_t) * (size_t)G.nnz;
       char *stg = pinned ? pinned_stage(b_rp + 2 * b_arc) : nullptr;
       std::vector<int32_t> rp, col, ww;

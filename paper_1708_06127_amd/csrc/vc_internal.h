@@ -71,7 +71,12 @@ struct Status {
   unsigned long long tile_arcs;  // arcs covered by the arc tiles of the current level
   int32_t pr_rows[2];          // rows marked with an LDS table of their row (short / long tables)
   unsigned long long fix_delta;  // correcting step: minimum weighted degree of the contracted graph
+  long long sw_cut;            // device exact solve: the kernel graph's minimum cut
 };
+
+// Kernel graphs of at most this many vertices are solved on the device (dense
+// Stoer-Wagner in LDS, one wave per graph) instead of on the host.
+constexpr int kDenseMax = 128;
 
 // ------------------------------------------------------------ batched solves
 // Many graphs are solved as one disjoint union: their CSRs are concatenated
@@ -126,6 +131,14 @@ struct GatherDesc {
   int32_t base, k, aoff, nnz;    // its vertex and arc ranges there
   int32_t drp, darc;             // destination offsets in the staging arrays
   int32_t rchunk0, achunk0;      // first row chunk / arc chunk of the copy work
+};
+
+// A finished graph's last level for the device exact solve (read in place).
+struct SwDesc {
+  const int32_t *rp, *col, *w;   // union buffer holding that level
+  int32_t base, k;               // its vertex range there
+  int32_t foff;                  // its side flags at flags + foff
+  int32_t pad;
 };
 
 // Side bitmap of a finished graph.
@@ -249,6 +262,14 @@ hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s
 hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s);
 hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStream_t s);
 hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s);
+// exact solve of the graph g (g.n <= kDenseMax) on the device: the cut into
+// st->sw_cut, the kernel side flags into w.flags8; then the input side: the
+// kernel side through the map if it beats lambda-hat, else the witness
+hipError_t exact_dense(const DGraph &g, Work &w, uint64_t *side, hipStream_t s);
+// batched: one wave per listed graph (every k <= kmax <= kDenseMax); cuts[i]
+// and the flags of graph i at flags + d[i].foff
+hipError_t exact_dense_batch(const SwDesc *d, int32_t count, int32_t kmax, uint8_t *flags, long long *cuts,
+                             hipStream_t s);
 
 // ---- batched-solve launchers (see the kernels for what each does)
 hipError_t b_gs_init(GStat *gs, const GDesc *d, int32_t count, int32_t buf, hipStream_t s);
@@ -291,7 +312,7 @@ struct ProfScope {
 };
 void prof_collect();  // after a synchronisation: fold finished records into the totals
 // An event-timed span on a stream whose algorithmic bytes the host knows only
-// later (the round-1 label-propagation + contraction sweep): begin returns a
+// later (label propagation + contraction of the first contraction round): begin returns a
 // record id (-1 when timing is off), end records the closing event, and
 // prof_span_bytes sets the record's bytes once they are known.
 int prof_span_begin(ProfKind kind, hipStream_t s);

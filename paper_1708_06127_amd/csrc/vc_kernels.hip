@@ -2990,6 +2990,127 @@ __global__ void k_side_witness(const unsigned long long *wit, int32_t n_in, unsi
   }
 }
 
+// ------------------------------------------------------------ device exact solve
+// Stoer-Wagner on a kernel graph of k <= kDenseMax vertices with the tie
+// rules of the host solver (every phase starts at the smallest surviving id;
+// the most tightly connected vertex is added next, ties to the smallest id;
+// the last vertex t of a phase is merged into the second-to-last s, which
+// keeps its id; the side is the set of vertices merged into t at the first
+// phase whose cut-of-the-phase is strictly smaller than all before). One wave
+// per graph: the weight matrix sits in LDS (rows of odd stride, so column
+// walks hit distinct banks), lane l holds vertices l and l + 64 (connection
+// weight, membership as a 128-bit set), and each step's selection is one
+// wave maximum of (1, conn, 255 - id).
+__device__ __forceinline__ unsigned long long sw_key(bool cand, unsigned long long conn, int32_t v) {
+  return cand ? (1ull << 62) | (conn << 8) | (uint64_t)(255 - v) : 0ull;
+}
+// rp: the k + 1 row pointers of the graph (absolute arc indices into col
+// and w); columns are vertex ids + cbase. Returns the cut, writes the side
+// flags of the k vertices.
+__device__ unsigned long long sw_dense_solve(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                             const int32_t *__restrict__ w, int32_t k, int32_t cbase, uint32_t *A,
+                                             uint8_t *flags) {
+  const int lane = threadIdx.x;
+  const int32_t P = k | 1;
+  for (int32_t i = lane; i < k * P; i += 64) A[i] = 0;
+  __syncthreads();
+  for (int32_t v = 0; v < k; v++)
+    for (int32_t a = rp[v] + lane; a < rp[v + 1]; a += 64) A[v * P + col[a] - cbase] = (uint32_t)w[a];
+  __syncthreads();
+  const int32_t v0 = lane, v1 = lane + 64;
+  bool alive0 = v0 < k, alive1 = v1 < k;
+  unsigned long long m0lo = v0 < k ? 1ull << v0 : 0ull, m0hi = 0ull;
+  unsigned long long m1lo = 0ull, m1hi = v1 < k ? 1ull << (v1 - 64) : 0ull;
+  unsigned long long best = ~0ull, blo = 0ull, bhi = 0ull;
+  for (int32_t remaining = k; remaining > 1; remaining--) {
+    const unsigned long long b0 = __ballot(alive0), b1 = __ballot(alive1);
+    const int32_t start = b0 ? __ffsll((long long)b0) - 1 : 64 + __ffsll((long long)b1) - 1;
+    bool in0 = v0 == start, in1 = v1 == start;
+    unsigned long long c0 = alive0 && !in0 ? A[start * P + v0] : 0ull;
+    unsigned long long c1 = alive1 && !in1 ? A[start * P + v1] : 0ull;
+    int32_t s = start, t = start;
+    unsigned long long cut_phase = 0;
+    for (int32_t added = 1; added < remaining; added++) {
+      const unsigned long long key =
+          umax64(sw_key(alive0 && !in0, c0, v0), sw_key(alive1 && !in1, c1, v1));
+      const unsigned long long top = grp_max<64>(key);
+      const int32_t x = 255 - (int32_t)(top & 0xFFull);
+      s = t;
+      t = x;
+      cut_phase = (top >> 8) & ((1ull << 54) - 1);
+      in0 = in0 || v0 == x;
+      in1 = in1 || v1 == x;
+      if (alive0 && !in0) c0 += A[x * P + v0];
+      if (alive1 && !in1) c1 += A[x * P + v1];
+    }
+    // members of t (from the lane that holds it)
+    const int32_t tl = t & 63;
+    const unsigned long long tlo = t < 64 ? __shfl(m0lo, tl, 64) : __shfl(m1lo, tl, 64);
+    const unsigned long long thi = t < 64 ? __shfl(m0hi, tl, 64) : __shfl(m1hi, tl, 64);
+    if (cut_phase < best) {
+      best = cut_phase;
+      blo = tlo;
+      bhi = thi;
+    }
+    // merge t into s: row and column s gain t's weights (diagonal left 0)
+    __syncthreads();
+    if (alive0 && v0 != s && v0 != t) {
+      A[s * P + v0] += A[t * P + v0];
+      A[v0 * P + s] += A[v0 * P + t];
+    }
+    if (alive1 && v1 != s && v1 != t) {
+      A[s * P + v1] += A[t * P + v1];
+      A[v1 * P + s] += A[v1 * P + t];
+    }
+    __syncthreads();
+    if (v0 == s) { m0lo |= tlo; m0hi |= thi; }
+    if (v1 == s) { m1lo |= tlo; m1hi |= thi; }
+    if (v0 == t) alive0 = false;
+    if (v1 == t) alive1 = false;
+  }
+  if (v0 < k) flags[v0] = (uint8_t)((blo >> v0) & 1ull);
+  if (v1 < k) flags[v1] = (uint8_t)((bhi >> (v1 - 64)) & 1ull);
+  return best;
+}
+__global__ __launch_bounds__(64) void k_sw_dense(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                  const int32_t *__restrict__ w, int32_t k, Status *st,
+                                                  uint8_t *flags) {
+  extern __shared__ uint32_t A[];
+  const unsigned long long best = sw_dense_solve(rp, col, w, k, 0, A, flags);
+  if (threadIdx.x == 0) st->sw_cut = (long long)best;
+}
+// batched: one wave per finished graph, read in place from the union's level
+__global__ __launch_bounds__(64) void k_sw_dense_batch(const SwDesc *d, uint8_t *flags, long long *cuts) {
+  extern __shared__ uint32_t A[];
+  const SwDesc &g = d[blockIdx.x];
+  const unsigned long long best = sw_dense_solve(g.rp + g.base, g.col, g.w, g.k, g.base, A, flags + g.foff);
+  if (threadIdx.x == 0) cuts[blockIdx.x] = (long long)best;
+}
+// input side after the device exact solve: the kernel side through the map
+// when it beats lambda-hat (ties keep lambda-hat), else the witness
+__global__ void k_side_exact(const int32_t *map, const uint8_t *flags, const unsigned long long *wit, int32_t n_in,
+                             const Status *st, unsigned long long *side) {
+  const bool use_flags = st->sw_cut < st->lam_hat;
+  if (use_flags) {
+    const uint8_t f0 = flags[map[0]];
+    for (int64_t base = blockIdx.x * (int64_t)kBlock; base < n_in; base += (int64_t)gridDim.x * kBlock) {
+      const int64_t u = base + threadIdx.x;
+      const bool b = u < n_in && (flags[map[u]] != f0);
+      const unsigned long long bal = __ballot(b);
+      if ((threadIdx.x & 63) == 0 && (base + (threadIdx.x & ~63)) < n_in) side[(base + threadIdx.x) >> 6] = bal;
+    }
+  } else {
+    const bool flip = wit[0] & 1ull;
+    const int32_t words = (n_in + 63) / 64;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < words; i += (int64_t)gridDim.x * kBlock) {
+      unsigned long long x = wit[i] ^ (flip ? ~0ull : 0ull);
+      const int32_t rem = n_in - (int32_t)i * 64;
+      if (rem < 64) x &= (1ull << rem) - 1;
+      side[i] = x;
+    }
+  }
+}
+
 // ------------------------------------------------------------ batched solves
 // SplitMix64 output number `index` (1-based) for a state starting at `seed`
 // (Steele, Lea, Flood 2014), as on the host.
@@ -3753,6 +3874,42 @@ hipError_t side_from_flags(Work &w, const uint8_t *flags, uint64_t *side, hipStr
 
 hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s) {
   k_side_witness<<<grid_for((w.n_in + 63) / 64), kBlock, 0, s>>>(w.witness, w.n_in, (unsigned long long *)side);
+  return hipGetLastError();
+}
+
+namespace {
+// the largest matrix (128 x 129 words) needs more than 64 KB of LDS
+hipError_t allow_dense_lds() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  const int bytes = (int)(sizeof(uint32_t) * kDenseMax * (kDenseMax | 1));
+  hipError_t e = hipFuncSetAttribute((const void *)k_sw_dense, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_sw_dense_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+}  // namespace
+
+hipError_t exact_dense_batch(const SwDesc *d, int32_t count, int32_t kmax, uint8_t *flags, long long *cuts,
+                             hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (kmax < 2 || kmax > kDenseMax) return hipErrorInvalidValue;
+  hipError_t e = allow_dense_lds();
+  if (e != hipSuccess) return e;
+  k_sw_dense_batch<<<count, 64, sizeof(uint32_t) * (size_t)kmax * (size_t)(kmax | 1), s>>>(d, flags, cuts);
+  return hipGetLastError();
+}
+
+hipError_t exact_dense(const DGraph &g, Work &w, uint64_t *side, hipStream_t s) {
+  if (g.n < 2 || g.n > kDenseMax) return hipErrorInvalidValue;
+  const int32_t P = g.n | 1;
+  const size_t lds = sizeof(uint32_t) * (size_t)g.n * (size_t)P;
+  hipError_t e = allow_dense_lds();
+  if (e != hipSuccess) return e;
+  k_sw_dense<<<1, 64, lds, s>>>(g.row_ptr, g.col, g.w, g.n, w.st, w.flags8);
+  k_side_exact<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.flags8, w.witness, w.n_in, w.st,
+                                                   (unsigned long long *)side);
   return hipGetLastError();
 }
 

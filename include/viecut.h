@@ -321,7 +321,9 @@ int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
  * element (compact_direct_max), the union tile count from which batched PR
  * marking of short rows merges rows from global memory (pr_merge_tiles), the
  * row length splitting the 1024- and 2048-slot long-row LP classes
- * (long_split, 256..512), and the long-row emission variant (emit_wave, 0/1).
+ * (long_split, 256..512), the long-row emission variant (emit_wave, 0/1),
+ * and the tiles of at most 256 arcs that one label-propagation workgroup
+ * takes (lp_group, 1..4).
  * The library keeps one set per size bucket (arcs of the level being worked
  * on, at most max_arcs; max_arcs < 0: no bound) and reads the table at load
  * time from the file named by the environment variable VIECUT_TUNING, else

@@ -390,7 +390,7 @@ def profile_read():
                                    "bytes": float(out[i].bytes)} for i in range(k)}
 
 
-TUNING_KEYS = ("radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave")
+TUNING_KEYS = ("radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave", "lp_group")
 
 
 def tuning_set(max_arcs: int, key: str, value: int):

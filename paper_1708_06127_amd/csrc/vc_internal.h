@@ -336,6 +336,7 @@ struct Tuning {
   int64_t pr_merge_tiles = 16384;        // batch unions: tiles from which short rows merge from global memory
   int64_t long_split = 512;              // long rows below this many arcs take the 1024-slot LDS class
   int64_t emit_wave = 1;                 // rows of 256..1023 arcs emitted by a wave per row (0: a workgroup)
+  int64_t lp_group = 2;                  // tiles of at most 256 arcs per LP workgroup (1..4)
 };
 Tuning tuning_for(int64_t arcs);
 

@@ -60,11 +60,20 @@ __device__ __forceinline__ int32_t key_label(unsigned long long key, uint32_t sa
   return (int32_t)(fmix32_inv_dev(~(uint32_t)(key & 0xFFFFFFFFull)) ^ salt);
 }
 __device__ __forceinline__ uint32_t slot_hash(int32_t x) { return (uint32_t)x * 2654435761u; }
+// Low 32 bits of the product of the low 24 bits of x and the golden-ratio
+// constant 0x9E3779, as the full-rate 24-bit multiply: written out because
+// the compiler otherwise prefers the quarter-rate 32-bit multiply when only
+// the low product bits are used.
+__device__ __forceinline__ uint32_t mul24_golden(uint32_t x) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, 0x9e3779, %1" : "=v"(r) : "v"(x));
+  return r;
+}
 // Slot in [0, size) for size < 2^9, from 24-bit multiplies only (full rate):
 // a 16-bit hash scaled by size. Every product stays below 2^31 (hipcc turns a
 // logical right shift of a 24-bit product into an arithmetic one).
 __device__ __forceinline__ uint32_t region_slot(int32_t x, uint32_t size) {
-  const uint32_t h = (__umul24((uint32_t)x ^ ((uint32_t)x >> 16), 0x9E3779u) >> 8) & 0xFFFFu;
+  const uint32_t h = (mul24_golden((uint32_t)x ^ ((uint32_t)x >> 16)) >> 8) & 0xFFFFu;
   return __umul24(h, size) >> 16;
 }
 // Element i of an array addressed with a 32-bit byte offset from its base,
@@ -736,26 +745,56 @@ __device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8)
   s_row8[lane] = out;
 }
 
-// LDS of one tile whose threads take NQ arcs each: the hash table holds two
-// slots per arc of the tile.
+// Row-start marks of a tile's arcs: one byte per arc, lane l's NQ arcs in
+// its own word.
 template <int NQ>
-struct LpTileShared {
+struct MarkWord;
+template <>
+struct MarkWord<4> {
+  using T = uint32_t;
+};
+template <>
+struct MarkWord<8> {
+  using T = unsigned long long;
+};
+
+// Row (tile-local index) of each of a lane's NQ arcs: the running maximum of
+// the marks within the lane's word, then the maximum over all earlier lanes
+// (a DPP scan), since a row's index is marked at its first arc and rows
+// grow with the arc position.
+template <int NQ>
+__device__ __forceinline__ void lane_rows(typename MarkWord<NQ>::T v, int32_t (&rw)[NQ]) {
+  uint32_t b[NQ], run = 0;
+#pragma unroll
+  for (int k = 0; k < NQ; k++) {
+    run = max(run, (uint32_t)(v >> (8 * k)) & 0xFFu);
+    b[k] = run;
+  }
+  const uint32_t carry =
+      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wave_incl_max(run), 0x138, 0xF, 0xF, false);  // wave_shr:1
+#pragma unroll
+  for (int k = 0; k < NQ; k++) rw[k] = (int32_t)max(b[k], carry);
+}
+
+// LDS of one tile whose threads take NQ arcs each. Row j: (first arc |
+// arc count << 16, own label) and its best key; the hash table interleaves
+// (label, weight sum) and holds two slots per arc of the tile.
+template <int NQ>
+struct alignas(16) LpTileShared {
   static constexpr int kSlots = 2 * NQ * kTB;
-  int32_t rp[kTile + 1];
-  int32_t own[kTile];
   // 8-arc tiles: a sink slot per lane takes the updates of inactive lanes
   // (no branches); the 4-arc kernel masks them instead and keeps its LDS
   // small enough for more resident workgroups
   static constexpr int kSinks = NQ == kPerThread ? kTB : 0;
+  uint2 row[kTile];
   unsigned long long best[kTile + kSinks];
-  int32_t tkey[kSlots + kSinks];
-  uint32_t tval[kSlots + kSinks];
-  unsigned long long row8[kTileArcs / 8];
+  uint2 slot[kSlots + kSinks];
+  typename MarkWord<NQ>::T mark[kTB];
 };
 
 // Registers of one tile, fetched ahead of its processing: per thread NQ arcs
 // (neighbour, then its label, and weight) and the tile's row data, one entry
-// per 64 rows.
+// per 64 rows (only the entries below the tile's row count are loaded).
 constexpr int kRowRegs = kTile / kTB;  // row-offset registers per lane (rows <= kTile)
 
 template <bool B, int NQ>
@@ -768,6 +807,8 @@ struct LpFetch {
   uint32_t saltv[B ? kRowRegs : 1];
 };
 
+// Lane l takes the tile's arcs [NQ l, NQ l + NQ) (clamped loads: lanes past
+// the end repeat the last arc and are masked later).
 template <bool B, int NQ>
 __device__ __forceinline__ void lp_fetch_loads(LpFetch<B, NQ> &f, int4 m, const int32_t *__restrict__ rp,
                                                const int32_t *__restrict__ col, const int32_t *__restrict__ w,
@@ -776,25 +817,25 @@ __device__ __forceinline__ void lp_fetch_loads(LpFetch<B, NQ> &f, int4 m, const 
   const int lane = threadIdx.x;
   f.m = m;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-  const int32_t q = (acnt + kTB - 1) / kTB;
-  const int32_t i0 = (int32_t)__umul24((uint32_t)lane, (uint32_t)q);
-  const int32_t iend = min(i0 + q, acnt);
-  const int32_t ilast = iend > i0 ? iend - 1 : acnt - 1;  // threads past the end repeat the tile's last arc
 #pragma unroll
   for (int k = 0; k < NQ; k++) f.xs[k] = f.cs[k] = 0;
   if (acnt > 0) {
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
-      const uint32_t i = (uint32_t)min(i0 + k, ilast);
+      const uint32_t i = (uint32_t)min(NQ * lane + k, acnt - 1);
       f.xs[k] = at32(col + a0, i);
       f.cs[k] = at32(w + a0, i);
     }
   }
 #pragma unroll
-  for (int r = 0; r <= kRowRegs; r++) f.rpv[r] = at32(rp + r0, (uint32_t)min(lane + kTB * r, rows));
+  for (int r = 0; r <= kRowRegs; r++) {
+    f.rpv[r] = 0;
+    if (r == 0 || kTB * r <= rows) f.rpv[r] = at32(rp + r0, (uint32_t)min(lane + kTB * r, rows));
+  }
   if (rows > 0) {
 #pragma unroll
     for (int r = 0; r < kRowRegs; r++) {
+      if (r > 0 && kTB * r >= rows) break;
       const uint32_t j = (uint32_t)min(lane + kTB * r, rows - 1);
       f.ownv[r] = at32(Lin + r0, j);
       if constexpr (B) {
@@ -820,87 +861,79 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
                                             LpTileShared<NQ> &sh, int32_t *s_base, uint32_t *s_salt, Hook hook) {
   const int lane = threadIdx.x;
   const int32_t r0 = f.m.x, rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
-  const int32_t q = (acnt + kTB - 1) / kTB;
-  const int32_t i0 = (int32_t)__umul24((uint32_t)lane, (uint32_t)q);
-  const int32_t iend = min(i0 + q, acnt);
-  const int32_t ilast = iend > i0 ? iend - 1 : acnt - 1;
-  const uint8_t *s_row = reinterpret_cast<const uint8_t *>(sh.row8);
-#pragma unroll
-  for (int r = 0; r <= kRowRegs; r++)
-    if (lane + kTB * r <= rows) sh.rp[lane + kTB * r] = f.rpv[r] - a0;
+  uint8_t *s_mark = reinterpret_cast<uint8_t *>(sh.mark);
+  sh.mark[lane] = 0;
+  // rows: packed (first arc, count) and own label; marks at first arcs
+  int32_t cnt[kRowRegs];
 #pragma unroll
   for (int r = 0; r < kRowRegs; r++) {
+    cnt[r] = 0;
+    if (r > 0 && kTB * r >= rows) break;
     const int j = lane + kTB * r;
+    // row j + 1 starts where lane + 1 holds it; lane 63 takes lane 0 of the next register
+    const int32_t nxt = r + 1 <= kRowRegs ? __builtin_amdgcn_readlane(f.rpv[r + 1], 0) : 0;
+    const int32_t hi = __builtin_amdgcn_update_dpp(nxt, f.rpv[r], 0x130, 0xF, 0xF, false) - a0;  // wave_shl:1
+    const int32_t lo = f.rpv[r] - a0;
+    cnt[r] = hi - lo;
     if (j < rows) {
-      sh.own[j] = f.ownv[r];
+      sh.row[j] = make_uint2((uint32_t)lo | ((uint32_t)cnt[r] << 16), (uint32_t)f.ownv[r]);
       sh.best[j] = 0;
       if constexpr (B) {
         s_base[j] = f.basev[r];
         s_salt[j] = f.saltv[r];
       }
+      if (cnt[r] > 0) s_mark[lo] = (uint8_t)j;
     }
   }
-  for (int e = lane; e < 2 * acnt; e += kTB) {
-    sh.tkey[e] = -1;
-    sh.tval[e] = 0;
+  // the table: two slots per arc, cleared 16 bytes (two slots) per lane and store
+#pragma unroll
+  for (int i = 0; i < NQ; i++) {
+    if (kTB * i >= acnt) break;
+    const int e = lane + kTB * i;
+    if (e < acnt) reinterpret_cast<uint4 *>(sh.slot)[e] = make_uint4(~0u, 0u, ~0u, 0u);
   }
-  sh.row8[lane] = 0;
-  __syncthreads();
-  for (int j = lane; j < rows; j += kTB)
-    if (sh.rp[j + 1] > sh.rp[j]) reinterpret_cast<uint8_t *>(sh.row8)[sh.rp[j]] = (uint8_t)j;
-  __syncthreads();
-  tile_rows_prefix_max(sh.row8);
   __syncthreads();
   if (acnt > 0) {
-    int32_t rw[NQ], ow[NQ], bj[NQ], hb[NQ], hsz[NQ], old[NQ];
-    uint32_t sj[NQ], hh[NQ], cc[NQ];
+    int32_t rw[NQ], hb[NQ], hsz[NQ], ow[NQ], bj[NQ];
+    uint32_t sj[NQ], hh[NQ], cc[NQ], old[NQ];
     bool real[NQ], ok[NQ];
-    // every LDS read first, so that they are in flight together
+    lane_rows<NQ>(sh.mark[lane], rw);
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
-      real[k] = i0 + k < iend;
-      rw[k] = s_row[min(i0 + k, ilast)];
-    }
-#pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      const int32_t lo = sh.rp[rw[k]], hi = sh.rp[rw[k] + 1];
-      hb[k] = 2 * lo;
-      hsz[k] = 2 * (hi - lo);
-      ow[k] = sh.own[rw[k]];
+      real[k] = NQ * lane + k < acnt;
+      const uint2 ri = sh.row[rw[k]];
+      hb[k] = 2 * (int32_t)(ri.x & 0xFFFFu);
+      hsz[k] = 2 * (int32_t)(ri.x >> 16);
+      ow[k] = (int32_t)ri.y;
       bj[k] = 0;
       sj[k] = salt;
       if constexpr (B) { bj[k] = s_base[rw[k]]; sj[k] = s_salt[rw[k]]; }
     }
-    // fold the thread's arcs of equal (row, label) into the first of them
-    // (register work instead of LDS atomics, which bound this kernel)
+    // fold runs of adjacent arcs of equal (row, label) into their first arc
+    // (register work instead of LDS atomics)
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
-      ok[k] = real[k];
       cc[k] = (uint32_t)f.cs[k];
+      ok[k] = real[k] && !(k > 0 && real[k - 1] && rw[k] == rw[k - 1] && f.xs[k] == f.xs[k - 1]);
     }
 #pragma unroll
-    for (int k = 1; k < NQ; k++) {
-#pragma unroll
-      for (int k1 = 0; k1 < k; k1++)
-        if (ok[k] && ok[k1] && rw[k] == rw[k1] && f.xs[k] == f.xs[k1]) {
-          cc[k1] += cc[k];
-          ok[k] = false;
-        }
-    }
+    for (int k = NQ - 1; k > 0; k--)
+      if (real[k] && !ok[k]) cc[k - 1] += cc[k];
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       hh[k] = region_slot(f.xs[k], (uint32_t)hsz[k]);
       if constexpr (LpTileShared<NQ>::kSinks > 0)
-        old[k] = atomicCAS(&sh.tkey[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane], -1, f.xs[k]);
+        old[k] = atomicCAS(&sh.slot[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane].x, ~0u,
+                           (uint32_t)f.xs[k]);
       else
-        old[k] = ok[k] ? atomicCAS(&sh.tkey[hb[k] + (int32_t)hh[k]], -1, f.xs[k]) : -1;
+        old[k] = ok[k] ? atomicCAS(&sh.slot[hb[k] + (int32_t)hh[k]].x, ~0u, (uint32_t)f.xs[k]) : ~0u;
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       if (!ok[k]) continue;
-      while (old[k] != -1 && old[k] != f.xs[k]) {  // taken by another label
+      while (old[k] != ~0u && old[k] != (uint32_t)f.xs[k]) {  // taken by another label
         hh[k] = (hh[k] + 1 == (uint32_t)hsz[k]) ? 0 : hh[k] + 1;
-        old[k] = atomicCAS(&sh.tkey[hb[k] + hh[k]], -1, f.xs[k]);
+        old[k] = atomicCAS(&sh.slot[hb[k] + (int32_t)hh[k]].x, ~0u, (uint32_t)f.xs[k]);
       }
     }
     // add the run weights: the returned partial sum plus the run's weight is
@@ -913,14 +946,12 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
 #pragma unroll
     for (int k = 0; k < NQ; k++)
       if constexpr (LpTileShared<NQ>::kSinks > 0)
-        old[k] = (int32_t)atomicAdd(&sh.tval[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane], cc[k]);
+        old[k] = atomicAdd(&sh.slot[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane].y, cc[k]);
       else
-        old[k] = ok[k] ? (int32_t)atomicAdd(&sh.tval[hb[k] + (int32_t)hh[k]], cc[k]) : 0;
+        old[k] = ok[k] ? atomicAdd(&sh.slot[hb[k] + (int32_t)hh[k]].y, cc[k]) : 0u;
 #pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      const uint32_t S = (uint32_t)old[k] + cc[k];
-      key[k] = ok[k] ? own_key(S, f.xs[k] == ow[k], f.xs[k] - bj[k], sj[k]) : 0ull;
-    }
+    for (int k = 0; k < NQ; k++)
+      key[k] = ok[k] ? own_key(old[k] + cc[k], f.xs[k] == ow[k], f.xs[k] - bj[k], sj[k]) : 0ull;
     // fold per row piece of this thread, one update per piece
     bool head[NQ];
 #pragma unroll
@@ -941,24 +972,35 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
   }
   hook();
   __syncthreads();
-  for (int j = lane; j < rows; j += kTB) {
-    const int32_t own = sh.own[j];
-    if (sh.rp[j + 1] == sh.rp[j]) { Lout[r0 + j] = own; continue; }
-    const unsigned long long b = sh.best[j];
-    int32_t bjj = 0;
-    uint32_t sjj = salt;
-    if constexpr (B) { bjj = s_base[j]; sjj = s_salt[j]; }
-    Lout[r0 + j] = ((b >> 32) & 1) ? own : key_label(b, sjj) + bjj;
+#pragma unroll
+  for (int r = 0; r < kRowRegs; r++) {
+    if (r > 0 && kTB * r >= rows) break;
+    const int j = lane + kTB * r;
+    if (j < rows) {
+      const int32_t own = f.ownv[r];
+      int32_t out = own;
+      if (cnt[r] > 0) {
+        const unsigned long long b = sh.best[j];
+        int32_t bjj = 0;
+        uint32_t sjj = salt;
+        if constexpr (B) { bjj = f.basev[r]; sjj = f.saltv[r]; }
+        if (!((b >> 32) & 1)) out = key_label(b, sjj) + bjj;
+      }
+      Lout[r0 + j] = out;
+    }
   }
   __syncthreads();
 }
 
-// The tiles of at most 4 * 64 arcs, 4 arcs per thread, one tile per
-// workgroup in the XCD-aware order (the hardware keeps enough of these small
-// workgroups in flight to hide the load latency, which measured faster than
-// a persistent loop with the next tile's loads in flight). The tiles of more
-// than 256 arcs are left to k_lp_tile_big.
-template <bool B>
+// The tiles of at most 4 * 64 arcs, 4 arcs per thread. A workgroup (one
+// wave) takes TP consecutive tiles of the XCD-aware order: it issues the
+// loads of all of them, then all their label gathers, and only then runs
+// their LDS phases one after the other, so TP tiles' memory latency is
+// paid once (the kernel is bound by the latency of these dependent loads
+// times the number of resident waves, not by bytes). Short-lived
+// workgroups leave the balancing to the hardware. The tiles of more than
+// 256 arcs are left to k_lp_tile_big.
+template <bool B, int TP>
 __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                      const int32_t *__restrict__ w, const int32_t *__restrict__ Lin,
                                                      int32_t *__restrict__ Lout, const int4 *__restrict__ meta,
@@ -970,20 +1012,25 @@ __global__ __launch_bounds__(kTB) void k_lp_tile(const int32_t *__restrict__ rp,
   prof_snapshot(prof, st);
   if (!B && st->err) return;
   constexpr int32_t kSmall = 4 * kTB;
-  XcdWalk xw(ntiles);
-  // this workgroup's next small tile from the walk's position on (-1: none)
-  auto next_small = [&](int4 &m) {
-    for (; xw.ok(); xw.next()) {
-      m = meta[xw.tile()];
-      if (m.w <= kSmall) return xw.tile();
+  XcdWalk xw((ntiles + TP - 1) / TP);
+  for (; xw.ok(); xw.next()) {
+    const int32_t t0 = xw.tile() * TP;
+    int4 m[TP];
+    bool use[TP];
+#pragma unroll
+    for (int u = 0; u < TP; u++) {
+      m[u] = t0 + u < ntiles ? meta[t0 + u] : make_int4(0, 0, 0, 0);
+      use[u] = m[u].w <= kSmall && (m[u].y > 0 || m[u].w > 0);
+      if (!use[u]) m[u] = make_int4(m[u].x, 0, 0, 0);  // nothing to load beyond row pointer r0
     }
-    return (int32_t)-1;
-  };
-  for (int4 m; next_small(m) >= 0; xw.next()) {
-    LpFetch<B, 4> cur;
-    lp_fetch_loads(cur, m, rp, col, w, Lin, gv, gs);
-    lp_fetch_gather(cur, Lin);
-    lp_tile_run<B, 4>(cur, Lout, salt, sh, s_base, s_salt, []() {});
+    LpFetch<B, 4> f[TP];
+#pragma unroll
+    for (int u = 0; u < TP; u++) lp_fetch_loads(f[u], m[u], rp, col, w, Lin, gv, gs);
+#pragma unroll
+    for (int u = 0; u < TP; u++) lp_fetch_gather(f[u], Lin);
+#pragma unroll
+    for (int u = 0; u < TP; u++)
+      if (use[u]) lp_tile_run<B, 4>(f[u], Lout, salt, sh, s_base, s_salt, []() {});
   }
 }
 
@@ -2623,7 +2670,7 @@ __device__ __forceinline__ int row16_or(int v) {
 }
 // Slot of key u in a power-of-two table (24-bit multiplies: full rate).
 __device__ __forceinline__ uint32_t pr_slot(int32_t u, uint32_t mask) {
-  return (__umul24((uint32_t)u ^ ((uint32_t)u >> 16), 0x9E3779u) >> 8) & mask;
+  return (mul24_golden((uint32_t)u ^ ((uint32_t)u >> 16)) >> 8) & mask;
 }
 __device__ __forceinline__ int32_t clamp_i32(long long x) {
   return x > INT32_MAX ? INT32_MAX : x < -1 ? -1 : (int32_t)x;
@@ -3609,20 +3656,43 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
 }
 
 
+template <bool B>
+void launch_lp_small(int tp, const DGraph &g, Work &w, const int32_t *Lin, int32_t *Lout, uint32_t salt,
+                     const int32_t *gv, const GStat *gs, int32_t *prof, hipStream_t s) {
+  const int64_t groups = (w.ntiles + tp - 1) / tp;
+  const unsigned grid = xcd_grid(grid_for(groups, 1, 1u << 20));
+  switch (tp) {
+    case 2:
+      k_lp_tile<B, 2><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv,
+                                           gs, prof);
+      break;
+    case 3:
+      k_lp_tile<B, 3><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv,
+                                           gs, prof);
+      break;
+    case 4:
+      k_lp_tile<B, 4><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv,
+                                           gs, prof);
+      break;
+    default:
+      k_lp_tile<B, 1><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv,
+                                           gs, prof);
+  }
+}
+
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
                    hipStream_t s, const BatchView *bv) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
   {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
+    const int tp = (int)tuning_for(g.nnz).lp_group;
     if (bv) {
-      k_lp_tile<true><<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(
-          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, gv, gs, ps.dev);
+      launch_lp_small<true>(tp, g, w, Lin, Lout, salt, gv, gs, ps.dev, s);
       k_lp_tile_big<true><<<resident_grid(k_lp_tile_big<true>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, gv, gs);
     } else {
-      k_lp_tile<false><<<xcd_grid(grid_for(w.ntiles, 1, 1u << 20)), kTB, 0, s>>>(
-          g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.ntiles, salt, w.st, nullptr, nullptr, ps.dev);
+      launch_lp_small<false>(tp, g, w, Lin, Lout, salt, nullptr, nullptr, ps.dev, s);
       k_lp_tile_big<false><<<resident_grid(k_lp_tile_big<false>, kTB, w.ntiles), kTB, 0, s>>>(
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);
     }

@@ -22,6 +22,8 @@ _lib = None
 
 EV_LP, EV_CONTRACT, EV_BOUND, EV_PR, EV_UF, EV_FIX = 1, 2, 3, 4, 5, 6
 F_CORRECT = 1
+F_CONVERGE = 2
+F_RESTRICT = 4
 ST_COLLAPSED, ST_DISCONNECTED, ST_NO_PROGRESS, ST_MAX_ROUNDS = 1, 2, 4, 8
 
 
@@ -147,9 +149,11 @@ def fix_misplaced(row_ptr, col, w, labels):
 
 
 def mincut(row_ptr, col, w, lp_iters: int = 2, n0: int = 10000, max_rounds: int = 64, seed: int = 0,
-           trace: bool = False, correct: bool = False) -> Result:
+           trace: bool = False, correct: bool = False, converge: bool = False, restrict: bool = False) -> Result:
     """Run the whole method on a host CSR. With ``trace`` every intermediate
-    state is recorded as a dict in ``Result.events``."""
+    state is recorded as a dict in ``Result.events``. ``correct``,
+    ``converge`` and ``restrict`` turn on the correcting step, the
+    convergence stop and the first-iteration restriction."""
     rp, c, ww = _csr_args(row_ptr, col, w)
     n = rp.size - 1
     words = max((n + 63) // 64, 1)
@@ -183,7 +187,9 @@ def mincut(row_ptr, col, w, lp_iters: int = 2, n0: int = 10000, max_rounds: int 
 
     cb = _TRACE_FN(on_event) if trace else _TRACE_FN()
     rc = _load().oracle_mincut(n, rp.ctypes.data, c.ctypes.data, ww.ctypes.data, int(lp_iters), int(n0),
-                               int(max_rounds), int(seed) & (2**64 - 1), F_CORRECT if correct else 0,
+                               int(max_rounds), int(seed) & (2**64 - 1),
+                               (F_CORRECT if correct else 0) | (F_CONVERGE if converge else 0) |
+                               (F_RESTRICT if restrict else 0),
                                ctypes.addressof(cut), side.ctypes.data,
                                info.ctypes.data, cb, None)
     if rc:

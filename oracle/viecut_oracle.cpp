@@ -47,6 +47,19 @@
 //     the contracted graph without any correction. The removed vertex becomes
 //     a singleton cluster with label n + v, so coarse ids follow the ordinary
 //     labels first and then the corrected vertices in ascending id.
+//   * Label-propagation variants (Section 4.1 and appendix D, "Algorithm
+//     Configuration"), each only when asked for:
+//     - convergence stop (flag 2): iteration t is the last one when at most
+//       floor(n / 10000) vertices (n: vertices of the current graph) got a
+//       label different from the one they had before iteration t, else the
+//       iterations run on up to l;
+//     - first-iteration restriction (flag 4), a synchronous reading of the
+//       rule that a vertex may not leave its block once another vertex has
+//       moved into it: after the first iteration of a round, every vertex
+//       that some other vertex chose (as its new label) keeps its own label;
+//       the others keep their choice. Unlike the sequential rule this does
+//       not bound the cluster count by n / 2 (two vertices that choose each
+//       other both stay).
 //   * The exact solve is Stoer-Wagner: every phase starts at the smallest
 //     surviving id, maximum-adjacency ties go to the smallest id, the last
 //     vertex t is merged into the second-to-last s (s keeps its id), and the
@@ -73,7 +86,7 @@ enum {
 };
 enum { ST_COLLAPSED = 1, ST_DISCONNECTED = 2, ST_NO_PROGRESS = 4, ST_MAX_ROUNDS = 8 };
 enum { EV_LP = 1, EV_CONTRACT = 2, EV_BOUND = 3, EV_PR = 4, EV_UF = 5, EV_FIX = 6 };
-enum { F_CORRECT = 1 };
+enum { F_CORRECT = 1, F_CONVERGE = 2, F_RESTRICT = 4 };
 
 }  // namespace
 
@@ -145,8 +158,9 @@ std::vector<int64_t> degrees(const Graph &g) {
 }
 
 // Synchronous label propagation (Section 4.1): l iterations, each computing
-// every vertex's new label from the previous iteration's labels only.
-std::vector<int32_t> label_propagation(const Graph &g, int32_t iters, uint64_t seed, int32_t round,
+// every vertex's new label from the previous iteration's labels only; the
+// variants of the flags as read in the file header.
+std::vector<int32_t> label_propagation(const Graph &g, int32_t iters, uint64_t seed, int32_t round, uint32_t flags,
                                        oracle_trace_fn cb, void *user) {
   std::vector<int32_t> L(g.n), Lnew(g.n);
   for (int32_t v = 0; v < g.n; v++) L[v] = v;  // every vertex starts in its own cluster
@@ -170,12 +184,23 @@ std::vector<int32_t> label_propagation(const Graph &g, int32_t iters, uint64_t s
       }
       Lnew[v] = best;
     }
+    if (t == 1 && (flags & F_RESTRICT)) {
+      // a vertex chosen by another vertex stays where it is
+      std::vector<char> chosen(g.n, 0);
+      for (int32_t u = 0; u < g.n; u++)
+        if (Lnew[u] != L[u]) chosen[Lnew[u]] = 1;  // L is the identity here
+      for (int32_t v = 0; v < g.n; v++)
+        if (chosen[v]) Lnew[v] = L[v];
+    }
+    int64_t changed = 0;
+    for (int32_t v = 0; v < g.n; v++) changed += Lnew[v] != L[v];
     L.swap(Lnew);
     if (cb) {
       oracle_event ev{};
       ev.kind = EV_LP; ev.round = round; ev.iter = t; ev.n = g.n; ev.a = L.data();
       cb(user, &ev);
     }
+    if ((flags & F_CONVERGE) && changed <= g.n / 10000) break;
   }
   return L;
 }
@@ -520,7 +545,7 @@ int oracle_mincut(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
     int32_t r = rounds++;
     int32_t n_start = g.n;
     if (lp_iters > 0) {
-      std::vector<int32_t> L = label_propagation(g, lp_iters, seed, r, cb, user);
+      std::vector<int32_t> L = label_propagation(g, lp_iters, seed, r, flags, cb, user);
       if (flags & F_CORRECT) {
         L = fix_misplaced(g, L);
         if (cb) {

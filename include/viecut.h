@@ -73,12 +73,20 @@ enum {
 /* params.flags */
 enum {
   VIECUT_F_VALIDATE = 1, /* check symmetry (w(u,v) == w(v,u)) and strictly increasing rows (O(nnz log d)) */
-  VIECUT_F_CORRECT = 2   /* the correcting step after label propagation (Section 4.1's correcting algorithm,
+  VIECUT_F_CORRECT = 2,  /* the correcting step after label propagation (Section 4.1's correcting algorithm,
                             fixMisplacedVertices in Algorithm 1): in every cluster of 2 to floor(log2 n)
                             vertices, the vertex whose removal leaves the cluster the smallest weighted
                             degree in the contracted graph becomes a singleton if that degree is below the
                             contracted graph's minimum weighted degree. Single-graph calls only: batches and
                             sessions return VIECUT_EINVAL. */
+  VIECUT_F_CONVERGE = 4, /* label-propagation convergence stop (appendix D, "Algorithm Configuration"): the
+                            iterations of a round end after the first one in which at most floor(n / 10000)
+                            vertices (n: vertices of the current graph) changed their label, else after
+                            lp_iters. Costs one status read per iteration. Single-graph calls only. */
+  VIECUT_F_RESTRICT = 8  /* first-iteration restriction (Section 4.1), read synchronously: after the first
+                            label-propagation iteration of a round, every vertex chosen by another vertex
+                            keeps its own label. Unlike the sequential rule it does not bound the cluster
+                            count by n / 2. Single-graph calls only. */
 };
 
 /* Input graph: a symmetric CSR. Row v lists the neighbours of v.
@@ -323,7 +331,7 @@ int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
  * row length splitting the 1024- and 2048-slot long-row LP classes
  * (long_split, 256..512), the long-row emission variant (emit_wave, 0/1),
  * and the tiles of at most 256 arcs that one label-propagation workgroup
- * takes (lp_group, 1..4).
+ * takes (lp_group, 1..4) and one emission workgroup takes (emit_group, 1..2).
  * The library keeps one set per size bucket (arcs of the level being worked
  * on, at most max_arcs; max_arcs < 0: no bound) and reads the table at load
  * time from the file named by the environment variable VIECUT_TUNING, else

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libviecut.so")
 OK, EINVAL, EWEIGHT, EOVERFLOW, ENOMEM, EDEVICE, ENOTSYM, EBUDGET, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8
 NOALLOC_SCRATCH_BYTES = 64 << 20  # VIECUT_NOALLOC_SCRATCH_BYTES
 ST_COLLAPSED, ST_DISCONNECTED, ST_NO_PROGRESS, ST_MAX_ROUNDS = 1, 2, 4, 8
-F_VALIDATE, F_CORRECT = 1, 2
+F_VALIDATE, F_CORRECT, F_CONVERGE, F_RESTRICT = 1, 2, 4, 8
 EXPORTED = ["viecut_default_params", "viecut_workspace_bytes", "viecut_mincut", "viecut_mincut_noalloc",
             "viecut_mincut_trace",
             "viecut_validate", "viecut_batch_workspace_bytes", "viecut_mincut_batch", "viecut_session_create",
@@ -148,12 +148,14 @@ def _check(code: int):
         raise ViecutError(code, strerror(code))
 
 
-def params(lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, correct=False) -> Params:
+def params(lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, correct=False, converge=False,
+           restrict=False) -> Params:
     p = Params()
     load().viecut_default_params(ctypes.byref(p))
     p.lp_iters, p.n0, p.max_rounds = int(lp_iters), int(n0), int(max_rounds)
     p.seed = int(seed) & (2**64 - 1)
-    p.flags = (F_VALIDATE if validate else 0) | (F_CORRECT if correct else 0)
+    p.flags = ((F_VALIDATE if validate else 0) | (F_CORRECT if correct else 0) | (F_CONVERGE if converge else 0) |
+               (F_RESTRICT if restrict else 0))
     return p
 
 
@@ -227,12 +229,15 @@ def _event_dict(ev):
 
 
 def mincut(row_ptr, col, w, *, lp_iters=2, n0=10000, max_rounds=64, seed=0, validate=False, correct=False,
-           ws=None, side=None, stream=None, trace=False):
-    """Solve one graph given as int32 CUDA tensors. Returns (cut, side, info)."""
+           converge=False, restrict=False, ws=None, side=None, stream=None, trace=False):
+    """Solve one graph given as int32 CUDA tensors. Returns (cut, side, info).
+    ``correct``, ``converge`` and ``restrict`` turn on the correcting step,
+    the label-propagation convergence stop and the first-iteration
+    restriction (VIECUT_F_CORRECT / _CONVERGE / _RESTRICT)."""
     torch = _torch()
     lib = load()
     g = csr(row_ptr, col, w)
-    p = params(lp_iters, n0, max_rounds, seed, validate, correct)
+    p = params(lp_iters, n0, max_rounds, seed, validate, correct, converge, restrict)
     words = (g.n + 63) // 64
     if side is None:
         side = torch.empty(max(words, 1), dtype=torch.int64, device=row_ptr.device)
@@ -390,7 +395,8 @@ def profile_read():
                                    "bytes": float(out[i].bytes)} for i in range(k)}
 
 
-TUNING_KEYS = ("radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave", "lp_group")
+TUNING_KEYS = ("radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave", "lp_group",
+               "emit_group")
 
 
 def tuning_set(max_arcs: int, key: str, value: int):

@@ -4,7 +4,8 @@ Some launch shapes change no result, only speed (see viecut_tuning_set in
 include/viecut.h): the radix block size threshold, the compaction variant,
 the PR short-row variant on batch unions, the split between the two smaller
 long-row label-propagation classes, the long-row emission variant and the
-number of short-row tiles one label-propagation workgroup takes. The
+numbers of short-row tiles one label-propagation and one emission workgroup
+take. The
 library keeps one set per size bucket (arcs of the level being worked on).
 
 This tuner measures, for each bucket, a coordinate descent over those
@@ -40,9 +41,10 @@ CANDIDATES = {
     "long_split": [256, 320, 384, 448, 512],
     "emit_wave": [0, 1],
     "lp_group": [1, 2, 3, 4],
+    "emit_group": [1, 2],
 }
 DEFAULTS = {"radix_large_from": 1 << 22, "compact_direct_max": 1 << 20, "pr_merge_tiles": 16384,
-            "long_split": 512, "emit_wave": 1, "lp_group": 2}
+            "long_split": 512, "emit_wave": 1, "lp_group": 2, "emit_group": 2}
 
 
 def log(*a):

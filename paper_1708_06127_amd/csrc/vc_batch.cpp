@@ -808,7 +808,8 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
   if (!gs || !p || !outs || !sides || count < 0) return VIECUT_EINVAL;
   viecut_params q = *p;
   if (q.lp_iters < 0 || q.n0 < 0 || q.max_rounds < 0) return VIECUT_EINVAL;
-  if (q.flags & VIECUT_F_CORRECT) return VIECUT_EINVAL;  // the correcting step runs on the single path only
+  // the correcting step and the label-propagation variants run on the single path only
+  if (q.flags & (VIECUT_F_CORRECT | VIECUT_F_CONVERGE | VIECUT_F_RESTRICT)) return VIECUT_EINVAL;
   vc::Caps c;
   for (int32_t i = 0; i < count; i++) {
     const int rc = vc::check_args(&gs[i], p);
@@ -847,7 +848,8 @@ int viecut_mincut_batch(const viecut_csr *gs, int32_t count, const viecut_params
 int viecut_session_create(size_t hbm_budget, const viecut_params *p, void *stream, viecut_session **out) {
   if (!p || !out) return VIECUT_EINVAL;
   if (p->lp_iters < 0 || p->n0 < 0 || p->max_rounds < 0) return VIECUT_EINVAL;
-  if (p->flags & VIECUT_F_CORRECT) return VIECUT_EINVAL;  // the correcting step runs on the single path only
+  // the correcting step and the label-propagation variants run on the single path only
+  if (p->flags & (VIECUT_F_CORRECT | VIECUT_F_CONVERGE | VIECUT_F_RESTRICT)) return VIECUT_EINVAL;
   // a quarter of the budget for the small lane, the rest for the large one;
   // a budget whose quarter cannot hold a small-lane request keeps one lane
   vc::Caps cs = vc::caps_for_budget(hbm_budget / 4);

@@ -509,11 +509,29 @@ struct Solver {
         auto tl = std::chrono::steady_clock::now();
         int32_t *Lc = w.La, *Lo = w.Lb;
         if (!(r == 0 && do_lp)) VC_TRY(lp_first(G, w, known, Lc, salt(r, 1), false, s));
+        if (p.flags & VIECUT_F_RESTRICT) VC_TRY(restrict_first(G, w, Lc, s));
         trace_labels(r, 1, Lc, G.n);
-        for (int32_t t = 2; t <= p.lp_iters; t++) {
+        // convergence stop: the iterations end after one that changed at
+        // most floor(n / 10000) labels
+        const bool conv = (p.flags & VIECUT_F_CONVERGE) != 0;
+        auto converged = [&](const int32_t *prev, const int32_t *cur, bool &stop) -> int {
+          stop = false;
+          if (!conv) return VIECUT_OK;
+          VC_TRY(count_changed(prev, cur, G.n, w, s));
+          const int rc2 = sync_status();
+          if (rc2) return rc2;
+          stop = st.lp_changed <= G.n / 10000;
+          return VIECUT_OK;
+        };
+        bool stop_lp = false;
+        rc = converged(nullptr, Lc, stop_lp);
+        if (rc) return rc;
+        for (int32_t t = 2; t <= p.lp_iters && !stop_lp; t++) {
           VC_TRY(lp_iter(G, w, known, Lc, Lo, salt(r, t), s));
           std::swap(Lc, Lo);
           trace_labels(r, t, Lc, G.n);
+          rc = converged(Lo, Lc, stop_lp);
+          if (rc) return rc;
         }
         int64_t lspace = -1;
         if (p.flags & VIECUT_F_CORRECT) {  // misplaced vertices become singletons (labels n + v)

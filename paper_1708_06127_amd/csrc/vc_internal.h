@@ -72,6 +72,8 @@ struct Status {
   int32_t pr_rows[2];          // rows marked with an LDS table of their row (short / long tables)
   unsigned long long fix_delta;  // correcting step: minimum weighted degree of the contracted graph
   long long sw_cut;            // device exact solve: the kernel graph's minimum cut
+  int32_t lp_changed;          // labels changed by the last counted LP iteration
+  int32_t pad1;
 };
 
 // Kernel graphs of at most this many vertices are solved on the device (dense
@@ -248,6 +250,11 @@ hipError_t relabel(const int32_t *L, int32_t n, Work &w, hipStream_t s, const Ba
 // correcting step on the labels L of the graph g (single solve): a misplaced
 // vertex v gets label n + v (labels then range over [0, 2n))
 hipError_t fix_misplaced(const DGraph &g, Work &w, int32_t *L, hipStream_t s);
+// first-iteration restriction: vertices chosen by another vertex keep their
+// own label (L holds iteration 1's labels; uses flags8 as scratch)
+hipError_t restrict_first(const DGraph &g, Work &w, int32_t *L, hipStream_t s);
+// st->lp_changed = #{v : cur[v] != prev[v]} (prev == nullptr: the identity)
+hipError_t count_changed(const int32_t *prev, const int32_t *cur, int32_t n, Work &w, hipStream_t s);
 hipError_t init_map(Work &w, hipStream_t s);
 // contraction: inter-cluster triples packed into buffer 1 (count -> st->ax, key bits from st->k)
 hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);
@@ -337,6 +344,7 @@ struct Tuning {
   int64_t long_split = 512;              // long rows below this many arcs take the 1024-slot LDS class
   int64_t emit_wave = 1;                 // rows of 256..1023 arcs emitted by a wave per row (0: a workgroup)
   int64_t lp_group = 2;                  // tiles of at most 256 arcs per LP workgroup (1..4)
+  int64_t emit_group = 2;                // tiles of at most 256 arcs per emission workgroup (1..2)
 };
 Tuning tuning_for(int64_t arcs);
 

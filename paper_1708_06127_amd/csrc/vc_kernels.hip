@@ -1732,106 +1732,147 @@ __device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus
 // The occupied slots are then written in slot order, 64 at a time.
 constexpr int kCombSlots = kTileArcs;  // > arcs of a tile, so probing ends
 constexpr unsigned long long kNoPair = ~0ull;
-struct EmitTileShared {
-  int32_t rp[kTile + 1];
-  int32_t cl[kTile];
+struct alignas(16) EmitTileShared {
+  int32_t rcl[kTile];                  // cluster of each row
   unsigned long long tkey[kCombSlots];
   uint32_t tval[kCombSlots];
-  unsigned long long row8[kTileArcs / 8];
+  unsigned long long mark[kTB];        // row-start marks, NQ bytes per lane
+};
+
+// Registers of one emission tile: lane l's arcs [NQ l, NQ l + NQ) (their
+// neighbours' clusters and weights) and the rows' first arcs and clusters,
+// one entry per 64 rows (only entries below the row count are loaded).
+template <int NQ>
+struct EmitFetch {
+  int4 m;
+  int32_t cus[NQ], cs[NQ];
+  int32_t rpv[kRowRegs + 1];
+  int32_t clv[kRowRegs];
 };
 
 template <int NQ>
-__device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                              const int32_t *__restrict__ w, const int32_t *__restrict__ cl, int4 m,
-                                              int32_t t, int key_bits, unsigned long long *__restrict__ keys,
-                                              int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                              int32_t *__restrict__ cnt,
-                                              EmitTileShared &sh) {
-  // table slots: twice the arcs of the largest tile (a half-size table for
-  // the small tiles measured slower on inputs with many distinct pairs)
-  constexpr int kSlots = kCombSlots;
+__device__ __forceinline__ void emit_fetch_loads(EmitFetch<NQ> &f, int4 m, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const int32_t *__restrict__ w,
+                                                 const int32_t *__restrict__ cl) {
   const int lane = threadIdx.x;
+  f.m = m;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-  const int32_t q = (acnt + kTB - 1) / kTB;
-  const int32_t i0 = lane * q;
-  const int32_t iend = min(i0 + q, acnt);
-  const int32_t ilast = iend > i0 ? iend - 1 : acnt - 1;
-  const uint8_t *s_row = reinterpret_cast<const uint8_t *>(sh.row8);
-  int32_t cus[NQ], cs[NQ];
 #pragma unroll
-  for (int k = 0; k < NQ; k++) cus[k] = cs[k] = 0;
+  for (int k = 0; k < NQ; k++) f.cus[k] = f.cs[k] = 0;
   if (acnt > 0) {
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
-      const int32_t i = a0 + min(i0 + k, ilast);
-      cus[k] = col[i];
-      cs[k] = w[i];
+      const uint32_t i = (uint32_t)min(NQ * lane + k, acnt - 1);
+      f.cus[k] = at32(col + a0, i);
+      f.cs[k] = at32(w + a0, i);
     }
-#pragma unroll
-    for (int k = 0; k < NQ; k++) cus[k] = cl[cus[k]];
   }
-  for (int j = lane; j <= rows; j += kTB) sh.rp[j] = rp[r0 + j] - a0;
-  for (int j = lane; j < rows; j += kTB) sh.cl[j] = cl[r0 + j];
-  for (int e = lane; e < kSlots; e += kTB) {
-    sh.tkey[e] = kNoPair;
-    sh.tval[e] = 0;
+#pragma unroll
+  for (int r = 0; r <= kRowRegs; r++) {
+    f.rpv[r] = 0;
+    if (r == 0 || kTB * r <= rows) f.rpv[r] = at32(rp + r0, (uint32_t)min(lane + kTB * r, rows));
   }
-  sh.row8[lane] = 0;
-  __syncthreads();
-  for (int j = lane; j < rows; j += kTB)
-    if (sh.rp[j + 1] > sh.rp[j]) reinterpret_cast<uint8_t *>(sh.row8)[sh.rp[j]] = (uint8_t)j;
-  __syncthreads();
-  tile_rows_prefix_max(sh.row8);
-  __syncthreads();
-  if (acnt > 0) {
-    int32_t cv[NQ];
-    bool ok[NQ];
-    uint32_t cc[NQ], hh[NQ];
-    unsigned long long key[NQ], old[NQ];
 #pragma unroll
-    for (int k = 0; k < NQ; k++) cv[k] = s_row[min(i0 + k, ilast)];
+  for (int r = 0; r < kRowRegs; r++) {
+    f.clv[r] = 0;
+    if (rows > 0 && (r == 0 || kTB * r < rows)) f.clv[r] = at32(cl + r0, (uint32_t)min(lane + kTB * r, rows - 1));
+  }
+}
+template <int NQ>
+__device__ __forceinline__ void emit_fetch_gather(EmitFetch<NQ> &f, const int32_t *__restrict__ cl) {
+  if (f.m.w > 0) {
 #pragma unroll
-    for (int k = 0; k < NQ; k++) cv[k] = sh.cl[cv[k]];
+    for (int k = 0; k < NQ; k++) f.cus[k] = at32(cl, (uint32_t)f.cus[k]);
+  }
+}
+
+// Emission of one tile: its arcs between different clusters become (cluster
+// of the row, cluster of the neighbour) pairs, summed per distinct pair in
+// an LDS table sized for the tile's inter-cluster arcs (twice their count,
+// a power of two), and written in slot order into the tile's arc range.
+// Tiles with no such arc write an empty segment and skip the table.
+template <int NQ>
+__device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, int32_t t, int key_bits,
+                                              unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
+                                              int32_t *__restrict__ first, int32_t *__restrict__ cnt,
+                                              EmitTileShared &sh) {
+  using MW = typename MarkWord<NQ>::T;
+  const int lane = threadIdx.x;
+  const int32_t rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
+  MW *mark = reinterpret_cast<MW *>(sh.mark);
+  uint8_t *s_mark = reinterpret_cast<uint8_t *>(sh.mark);
+  mark[lane] = 0;
 #pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      ok[k] = i0 + k < iend && cus[k] != cv[k];
-      key[k] = ((unsigned long long)(uint32_t)cv[k] << key_bits) | (uint32_t)cus[k];
-      cc[k] = (uint32_t)cs[k];
+  for (int r = 0; r < kRowRegs; r++) {
+    if (r > 0 && kTB * r >= rows) break;
+    const int j = lane + kTB * r;
+    const int32_t nxt = __builtin_amdgcn_readlane(f.rpv[r + 1], 0);
+    const int32_t hi = __builtin_amdgcn_update_dpp(nxt, f.rpv[r], 0x130, 0xF, 0xF, false);  // wave_shl:1
+    if (j < rows) {
+      sh.rcl[j] = f.clv[r];
+      if (hi > f.rpv[r]) s_mark[f.rpv[r] - a0] = (uint8_t)j;
     }
-    // fold runs of equal pairs into their first arc
+  }
+  __syncthreads();
+  int32_t rw[NQ];
+  lane_rows<NQ>(mark[lane], rw);
+  bool ok[NQ];
+  uint32_t cc[NQ];
+  unsigned long long key[NQ];
 #pragma unroll
-    for (int k = NQ - 1; k > 0; k--)
-      if (ok[k] && ok[k - 1] && key[k] == key[k - 1]) {
-        cc[k - 1] += cc[k];
-        ok[k] = false;
-      }
+  for (int k = 0; k < NQ; k++) {
+    const int32_t cv = sh.rcl[rw[k]];
+    ok[k] = NQ * lane + k < acnt && f.cus[k] != cv;
+    key[k] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)f.cus[k];
+    cc[k] = (uint32_t)f.cs[k];
+  }
+  // fold runs of equal pairs into their first arc
+#pragma unroll
+  for (int k = NQ - 1; k > 0; k--)
+    if (ok[k] && ok[k - 1] && key[k] == key[k - 1]) {
+      cc[k - 1] += cc[k];
+      ok[k] = false;
+    }
+  int32_t e = 0;
+#pragma unroll
+  for (int k = 0; k < NQ; k++) e += __popcll(__ballot(ok[k]));
+  int32_t tot = 0;
+  if (e > 0) {
+    // table of T = pow2 >= 2e slots (64 .. kCombSlots)
+    int32_t tb = 6;
+    while ((1 << tb) < 2 * e && (1 << tb) < kCombSlots) tb++;
+    const int32_t T = 1 << tb;
+    const uint32_t msk = (uint32_t)T - 1;
+    for (int i = lane; i < T; i += kTB) {
+      sh.tkey[i] = kNoPair;
+      sh.tval[i] = 0;
+    }
+    __syncthreads();
+    uint32_t hh[NQ];
+    unsigned long long old[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       const uint32_t fold = (uint32_t)key[k] ^ (uint32_t)(key[k] >> 32);
-      hh[k] = (fold * 2654435761u) & (kSlots - 1);
+      hh[k] = (mul24_golden(fold ^ (fold >> 16)) >> 8) & msk;
       old[k] = ok[k] ? atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]) : kNoPair;
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
       if (!ok[k]) continue;
       while (old[k] != kNoPair && old[k] != key[k]) {  // taken by another pair
-        hh[k] = (hh[k] + 1) & (kSlots - 1);
+        hh[k] = (hh[k] + 1) & msk;
         old[k] = atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]);
       }
     }
 #pragma unroll
     for (int k = 0; k < NQ; k++)
       if (ok[k]) atomicAdd(&sh.tval[hh[k]], cc[k]);
-  }
-  __syncthreads();
-  // write the distinct pairs into the tile's region, in slot order
-  int32_t tot = 0;
-  if (acnt > 0) {
-#pragma unroll
-    for (int k = 0; k < kSlots / kTB; k++) {
-      const int e = k * kTB + lane;
-      const unsigned long long kk = sh.tkey[e];
-      const uint32_t vv = sh.tval[e];
+    __syncthreads();
+    // write the distinct pairs into the tile's region, in slot order
+    for (int i0 = 0; i0 < T; i0 += kTB) {
+      const int i = i0 + lane;
+      const unsigned long long kk = sh.tkey[i];
+      const uint32_t vv = sh.tval[i];
       const bool occ = kk != kNoPair;
       const unsigned long long bal = __ballot(occ);
       if (occ) {
@@ -1849,6 +1890,10 @@ __device__ __forceinline__ void emit_tile_one(const int32_t *__restrict__ rp, co
   __syncthreads();
 }
 
+// Tiles of at most 256 arcs, TP consecutive tiles per workgroup (one wave):
+// the loads and cluster gathers of all of them are issued before any is
+// processed. Tiles of more than 256 arcs are left to k_emit_tile_big.
+template <int TP>
 __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
                                                        const int4 *__restrict__ meta, int32_t ntiles,
@@ -1857,12 +1902,48 @@ __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ r
                                                        int32_t *__restrict__ cnt) {
   __shared__ EmitTileShared sh;
   const int key_bits = bits_for(st->k);
-  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int4 m = meta[t];
-    if (m.w <= 4 * kTB)
-      emit_tile_one<4>(rp, col, w, cl, m, t, key_bits, keys, vals, first, cnt, sh);
-    else
-      emit_tile_one<kPerThread>(rp, col, w, cl, m, t, key_bits, keys, vals, first, cnt, sh);
+  const int32_t groups = (ntiles + TP - 1) / TP;
+  for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+    int4 m[TP];
+    bool use[TP];
+#pragma unroll
+    for (int u = 0; u < TP; u++) {
+      const int32_t t = g * TP + u;
+      m[u] = t < ntiles ? meta[t] : make_int4(0, 0, 0, 0);
+      use[u] = t < ntiles && m[u].w <= 4 * kTB;
+      if (!use[u]) m[u] = make_int4(m[u].x, 0, 0, 0);
+    }
+    EmitFetch<4> f[TP];
+#pragma unroll
+    for (int u = 0; u < TP; u++) emit_fetch_loads(f[u], m[u], rp, col, w, cl);
+#pragma unroll
+    for (int u = 0; u < TP; u++) emit_fetch_gather(f[u], cl);
+#pragma unroll
+    for (int u = 0; u < TP; u++)
+      if (use[u]) emit_tile_run<4>(f[u], g * TP + u, key_bits, keys, vals, first, cnt, sh);
+  }
+}
+
+// The listed tiles of more than 256 arcs, 8 arcs per lane (as many
+// workgroups as fit, striding over the list).
+__global__ __launch_bounds__(kTB) void k_emit_tile_big(const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           const int32_t *__restrict__ w,
+                                                           const int32_t *__restrict__ cl,
+                                                           const int4 *__restrict__ meta,
+                                                           const int32_t *__restrict__ big, const Status *st,
+                                                           unsigned long long *__restrict__ keys,
+                                                           int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                                           int32_t *__restrict__ cnt) {
+  __shared__ EmitTileShared sh;
+  const int key_bits = bits_for(st->k);
+  const int32_t nb = st->big_tiles;
+  for (int32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    const int32_t t = big[i];
+    EmitFetch<kPerThread> f;
+    emit_fetch_loads(f, meta[t], rp, col, w, cl);
+    emit_fetch_gather(f, cl);
+    emit_tile_run<kPerThread>(f, t, key_bits, keys, vals, first, cnt, sh);
   }
 }
 
@@ -3751,6 +3832,50 @@ __global__ void k_init_map(int32_t *map, int32_t n, unsigned long long *lb_state
   if (blockIdx.x == 0 && threadIdx.x == 0) *lb_ticket = 0;
 }
 
+// ------------------------------------------------------------ LP variants
+// First-iteration restriction (Section 4.1, read synchronously): a vertex
+// that another vertex chose in iteration 1 keeps its own label.
+__global__ void k_restrict_clear(uint8_t *chosen, int32_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+    chosen[v] = 0;
+}
+__global__ void k_restrict_mark(const int32_t *__restrict__ L, int32_t n, uint8_t *chosen) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+    const int32_t x = L[v];
+    if (x != (int32_t)v) chosen[x] = 1;  // iteration 1 starts from the identity
+  }
+}
+__global__ void k_restrict_apply(int32_t *L, int32_t n, const uint8_t *chosen) {
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+    if (chosen[v]) L[v] = (int32_t)v;
+}
+// Labels that differ between two iterations (prev == nullptr: the identity).
+__global__ void k_count_changed(const int32_t *__restrict__ prev, const int32_t *__restrict__ cur, int32_t n,
+                                Status *st) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  unsigned long long c = 0;
+  for (int64_t v = blockIdx.x * (int64_t)kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock)
+    c += cur[v] != (prev ? prev[v] : (int32_t)v);
+  c = block_sum(c, sh);
+  if (threadIdx.x == 0 && c) atomicAdd(&st->lp_changed, (int32_t)c);
+}
+
+hipError_t restrict_first(const DGraph &g, Work &w, int32_t *L, hipStream_t s) {
+  if (g.n <= 0) return hipSuccess;
+  const unsigned grid = grid_for(g.n);
+  k_restrict_clear<<<grid, kBlock, 0, s>>>(w.flags8, g.n);
+  k_restrict_mark<<<grid, kBlock, 0, s>>>(L, g.n, w.flags8);
+  k_restrict_apply<<<grid, kBlock, 0, s>>>(L, g.n, w.flags8);
+  return hipGetLastError();
+}
+
+hipError_t count_changed(const int32_t *prev, const int32_t *cur, int32_t n, Work &w, hipStream_t s) {
+  hipError_t e = fill_i32(&w.st->lp_changed, 0, 1, s);
+  if (e != hipSuccess || n <= 0) return e;
+  k_count_changed<<<grid_for(n), kBlock, 0, s>>>(prev, cur, n, w.st);
+  return hipGetLastError();
+}
+
 hipError_t fix_misplaced(const DGraph &g, Work &w, int32_t *L, hipStream_t s) {
   const int32_t n = g.n;
   if (n <= 0) return hipSuccess;
@@ -3779,8 +3904,18 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
   // long-row segments beyond the device-side row counts stay empty
   hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, kLong * long_max, s);
   if (e != hipSuccess) return e;
-  k_emit_tile<<<grid_for(w.ntiles, 1, 1u << 20), kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles,
-                                                                 w.st, w.keys[0], w.vals[0], w.seg, w.seg_cnt);
+  {
+    const int tp = (int)tuning_for(g.nnz).emit_group;
+    const unsigned grid = grid_for((w.ntiles + tp - 1) / tp, 1, 1u << 20);
+    if (tp == 2)
+      k_emit_tile<2><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles, w.st, w.keys[0],
+                                          w.vals[0], w.seg, w.seg_cnt);
+    else
+      k_emit_tile<1><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles, w.st, w.keys[0],
+                                          w.vals[0], w.seg, w.seg_cnt);
+    k_emit_tile_big<<<resident_grid(k_emit_tile_big, kTB, w.ntiles), kTB, 0, s>>>(
+        g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.big_tiles, w.st, w.keys[0], w.vals[0], w.seg, w.seg_cnt);
+  }
   for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;

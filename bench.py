@@ -202,8 +202,9 @@ COPY_PROBE_BYTES = 256 << 20  # the --copy-probe device copy: 64 Mi int32 read a
 # a timed unit of the library's kernel timer and the device kernels it covers
 # (the LP iteration t >= 2 runs the tiles of at most 256 arcs and the larger
 # tiles in two launches, timed together)
-TIMED_UNITS = {"k_lp_tile": ["k_lp_tile", "k_lp_tile_big"], "k_first_tile": ["k_first_tile"],
-               "k_first_tile_level0": ["k_first_tile"]}
+TIMED_UNITS = {"k_lp_tile": ["k_lp_tile", "k_lp_tile_big"],
+               "k_first_tile": ["k_first_tile", "k_first_tile_big", "k_first_tile_each"],
+               "k_first_tile_level0": ["k_first_tile", "k_first_tile_big", "k_first_tile_each"]}
 
 
 def record_traffic(fetch_csv, write_csv, kernel, workload, command):

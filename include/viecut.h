@@ -331,7 +331,10 @@ int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
  * row length splitting the 1024- and 2048-slot long-row LP classes
  * (long_split, 256..512), the long-row emission variant (emit_wave, 0/1),
  * and the tiles of at most 256 arcs that one label-propagation workgroup
- * takes (lp_group, 1..4) and one emission workgroup takes (emit_group, 1..2).
+ * takes (lp_group, 1..4) and one emission workgroup takes (emit_group, 1..2),
+ * and the launch shape of label-propagation iteration 1 (first_group: 1 = a
+ * workgroup per tile, 2 = two short-row tiles per workgroup plus a
+ * persistent kernel for the tiles of more than 256 arcs).
  * The library keeps one set per size bucket (arcs of the level being worked
  * on, at most max_arcs; max_arcs < 0: no bound) and reads the table at load
  * time from the file named by the environment variable VIECUT_TUNING, else

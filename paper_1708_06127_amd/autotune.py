@@ -5,7 +5,7 @@ include/viecut.h): the radix block size threshold, the compaction variant,
 the PR short-row variant on batch unions, the split between the two smaller
 long-row label-propagation classes, the long-row emission variant and the
 numbers of short-row tiles one label-propagation and one emission workgroup
-take. The
+take, and the launch shape of the first label-propagation iteration. The
 library keeps one set per size bucket (arcs of the level being worked on).
 
 This tuner measures, for each bucket, a coordinate descent over those
@@ -42,9 +42,11 @@ CANDIDATES = {
     "emit_wave": [0, 1],
     "lp_group": [1, 2, 3, 4],
     "emit_group": [1, 2],
+    "first_group": [1, 2],
 }
 DEFAULTS = {"radix_large_from": 1 << 22, "compact_direct_max": 1 << 20, "pr_merge_tiles": 16384,
-            "long_split": 512, "emit_wave": 1, "lp_group": 2, "emit_group": 2}
+            "long_split": 512, "emit_wave": 1, "lp_group": 2, "emit_group": 2,
+            "first_group": 1}
 
 
 def log(*a):

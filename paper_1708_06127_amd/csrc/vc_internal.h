@@ -345,6 +345,8 @@ struct Tuning {
   int64_t emit_wave = 1;                 // rows of 256..1023 arcs emitted by a wave per row (0: a workgroup)
   int64_t lp_group = 2;                  // tiles of at most 256 arcs per LP workgroup (1..4)
   int64_t emit_group = 2;                // tiles of at most 256 arcs per emission workgroup (1..2)
+  int64_t first_group = 1;               // LP iteration 1: 1 = a workgroup per tile, 2 = two short-row tiles per
+                                         // workgroup plus a persistent kernel for the others
 };
 Tuning tuning_for(int64_t arcs);
 

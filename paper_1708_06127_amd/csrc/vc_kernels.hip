@@ -22,6 +22,8 @@
 // split into 4096-arc chunks handled by many workgroups that share a
 // global-memory table per row.
 #include <mutex>
+#include <utility>
+#include <vector>
 
 #include "vc_internal.h"
 
@@ -565,120 +567,6 @@ __device__ __forceinline__ void prof_snapshot(int32_t *prof, const Status *st) {
 // LDS; the row of each arc is then found by one binary search and a forward
 // walk.
 
-// Iteration 1 on a tile: running (w, -prio) maximum and weight sum per row
-// run, flushed to per-row LDS slots; one thread per row writes the label. At
-// level 0 the pass also validates arcs and yields degrees, and each block
-// leaves its minimum-degree key, weight sum and error bits in `part`.
-template <bool L0, bool B>
-__global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ rp,
-                                                        const int32_t *__restrict__ col,
-                                                        const int32_t *__restrict__ w, int32_t n,
-                                                        const int4 *__restrict__ meta, int32_t ntiles,
-                                                        int32_t *__restrict__ L, long long *__restrict__ deg,
-                                                        uint32_t salt, const Status *st,
-                                                        unsigned long long *__restrict__ part,
-                                                        const int32_t *__restrict__ gv, GStat *gs, int32_t *prof) {
-  __shared__ int32_t s_rp[kTile + 1];
-  __shared__ unsigned long long s_best[kTile];
-  prof_snapshot(prof, st);
-  __shared__ unsigned long long s_sum[kTile];
-  // batched: graph-local id offset and salt of each row
-  __shared__ int32_t s_base[B ? kTile : 1];
-  __shared__ uint32_t s_salt[B ? kTile : 1];
-  const bool bad = !B && st->err != 0;
-  unsigned long long mykey = ~0ull, mysum = 0;
-  int myerr = 0;
-  for (int32_t t = blockIdx.x; t < ntiles && !bad; t += gridDim.x) {
-    const int4 m = meta[t];
-    const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
-    const int32_t q = (acnt + kTB - 1) / kTB;
-    const int32_t i0 = threadIdx.x * q;
-    int32_t xs[kPerThread], cs[kPerThread];
-#pragma unroll
-    for (int k = 0; k < kPerThread; k++) {
-      const bool ok = k < q && i0 + k < acnt;
-      xs[k] = ok ? col[a0 + i0 + k] : 0;
-      cs[k] = ok ? w[a0 + i0 + k] : 0;
-    }
-    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
-    for (int j = threadIdx.x; j < rows; j += kTB) {
-      s_best[j] = 0;
-      s_sum[j] = 0;
-      if constexpr (B) {
-        const GStat &g = gs[gv[r0 + j]];
-        s_base[j] = g.base;
-        s_salt[j] = g.salt;
-      }
-    }
-    __syncthreads();
-    if (i0 < acnt) {
-      int32_t j = row_of(s_rp, rows, i0);
-      int32_t bj = 0;
-      uint32_t sj = salt;
-      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
-      unsigned long long best = 0, sum = 0;
-      int32_t next = s_rp[j + 1];  // end of row j, in a register: read again only when a row ends
-#pragma unroll
-      for (int k = 0; k < kPerThread; k++) {
-        const int32_t i = i0 + k;
-        if (k < q && i < acnt) {
-          if (i >= next) {
-            atomicMax(&s_best[j], best);
-            if (L0) atomicAdd(&s_sum[j], sum);
-            best = 0;
-            sum = 0;
-            do { j++; next = s_rp[j + 1]; } while (i >= next);
-            if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
-          }
-          const int32_t x = xs[k], c = cs[k];
-          if (L0) {
-            int e = 0;
-            if (x < 0 || x >= n) e |= ERR_COL;
-            if (x == r0 + j) e |= ERR_SELF;
-            if (c < 1) e |= ERR_WEIGHT;
-            if constexpr (B) {
-              if (e) atomicOr(&gs[gv[r0 + j]].err, e);  // rare: straight to the graph's flags
-            } else {
-              myerr |= e;
-            }
-            sum += (unsigned long long)(uint32_t)c;
-          }
-          best = umax64(best, cand_key((uint32_t)c, x - bj, sj));
-        }
-      }
-      atomicMax(&s_best[j], best);
-      if (L0) atomicAdd(&s_sum[j], sum);
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < rows; j += kTB) {
-      const int32_t v = r0 + j;
-      int32_t bj = 0;
-      uint32_t sj = salt;
-      if constexpr (B) { bj = s_base[j]; sj = s_salt[j]; }
-      L[v] = s_rp[j + 1] > s_rp[j] ? key_label(s_best[j], sj) + bj : v;
-      if (L0) {
-        const unsigned long long d = s_sum[j];
-        deg[v] = (long long)d;
-        if constexpr (!B) {
-          mykey = umin64(mykey, ((d > 0xFFFFFFFFull ? 0xFFFFFFFFull : d) << 32) | (uint32_t)v);
-          mysum += d;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if constexpr (L0 && !B) {
-    const unsigned long long k = grp_min<64>(mykey);
-    const unsigned long long sm = grp_sum<64>(mysum);
-    const int e = grp_or<64>(myerr);
-    if (threadIdx.x == 0) {
-      part[3 * (int64_t)blockIdx.x] = k;
-      part[3 * (int64_t)blockIdx.x + 1] = sm;
-      part[3 * (int64_t)blockIdx.x + 2] = (unsigned long long)e;
-    }
-  }
-}
-
 // combine per-block (min key, weight sum, error bits) into the status
 __global__ void k_reduce_parts(const unsigned long long *part, int32_t count, Status *st) {
   __shared__ unsigned long long red[kBlock / 64];
@@ -942,33 +830,26 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
     // updates of a row is the maximum over its labels' final sums
     // The key (S, own, -prio) orders by sum, then the own label first, then
     // the smaller prio, so the row maximum decides the update rule at once.
-    unsigned long long key[NQ];
 #pragma unroll
     for (int k = 0; k < NQ; k++)
       if constexpr (LpTileShared<NQ>::kSinks > 0)
         old[k] = atomicAdd(&sh.slot[ok[k] ? hb[k] + (int32_t)hh[k] : LpTileShared<NQ>::kSlots + lane].y, cc[k]);
       else
         old[k] = ok[k] ? atomicAdd(&sh.slot[hb[k] + (int32_t)hh[k]].y, cc[k]) : 0u;
-#pragma unroll
-    for (int k = 0; k < NQ; k++)
-      key[k] = ok[k] ? own_key(old[k] + cc[k], f.xs[k] == ow[k], f.xs[k] - bj[k], sj[k]) : 0ull;
-    // fold per row piece of this thread, one update per piece
-    bool head[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; k++) head[k] = real[k];
-#pragma unroll
-    for (int k = NQ - 1; k > 0; k--)
-      if (real[k] && real[k - 1] && rw[k] == rw[k - 1]) {
-        key[k - 1] = umax64(key[k - 1], key[k]);
-        head[k] = false;
-      }
+    // running maximum per row piece of this thread, one update per piece
+    unsigned long long run = 0;
+    int32_t cur = rw[0];
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
-      if constexpr (LpTileShared<NQ>::kSinks > 0)
-        atomicMax(&sh.best[head[k] ? rw[k] : kTile + lane], key[k]);
-      else if (head[k])
-        atomicMax(&sh.best[rw[k]], key[k]);
+      if (!real[k]) break;
+      if (rw[k] != cur) {
+        atomicMax(&sh.best[cur], run);
+        run = 0;
+        cur = rw[k];
+      }
+      if (ok[k]) run = umax64(run, own_key(old[k] + cc[k], f.xs[k] == ow[k], f.xs[k] - bj[k], sj[k]));
     }
+    if (real[0]) atomicMax(&sh.best[cur], run);
   }
   hook();
   __syncthreads();
@@ -1071,6 +952,288 @@ __global__ __launch_bounds__(kTB) void k_lp_tile_big(const int32_t *__restrict__
     i = in;
     cur = nxt;
   }
+}
+
+// ------------------------------------------------------------ LP iteration 1 on tiles
+// Identity labels: S(x) = w(v, x), so a row's new label is the argmax of
+// (w, -prio) over its arcs, and no label is gathered. At level 0 the same
+// pass validates every arc and sums the weighted degree, and each workgroup
+// leaves its minimum-degree key, weight sum and error bits in `part`.
+// Lane l takes the tile's arcs [NQ l, NQ l + NQ); rows come from the marks
+// (lane_rows); each thread folds its keys and sums per row piece and makes
+// one LDS update per piece.
+template <bool L0, bool B, int NQ>
+struct alignas(16) FirstShared {
+  unsigned long long best[kTile];
+  unsigned long long sum[L0 ? kTile : 1];
+  int32_t base[B ? kTile : 1];
+  uint32_t salt[B ? kTile : 1];
+  typename MarkWord<NQ>::T mark[kTB];
+};
+
+template <bool B, int NQ>
+struct FirstFetch {
+  int4 m;
+  int32_t xs[NQ], cs[NQ];
+  int32_t rpv[kRowRegs + 1];
+  int32_t basev[B ? kRowRegs : 1];
+  uint32_t saltv[B ? kRowRegs : 1];
+};
+
+template <bool B, int NQ>
+__device__ __forceinline__ void first_fetch(FirstFetch<B, NQ> &f, int4 m, const int32_t *__restrict__ rp,
+                                            const int32_t *__restrict__ col, const int32_t *__restrict__ w,
+                                            const int32_t *__restrict__ gv, const GStat *gs) {
+  const int lane = threadIdx.x;
+  f.m = m;
+  const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
+#pragma unroll
+  for (int k = 0; k < NQ; k++) f.xs[k] = f.cs[k] = 0;
+  if (acnt > 0) {
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const uint32_t i = (uint32_t)min(NQ * lane + k, acnt - 1);
+      f.xs[k] = at32(col + a0, i);
+      f.cs[k] = at32(w + a0, i);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r <= kRowRegs; r++) {
+    f.rpv[r] = 0;
+    if (r == 0 || kTB * r <= rows) f.rpv[r] = at32(rp + r0, (uint32_t)min(lane + kTB * r, rows));
+  }
+  if constexpr (B) {
+    if (rows > 0) {
+#pragma unroll
+      for (int r = 0; r < kRowRegs; r++) {
+        if (r > 0 && kTB * r >= rows) break;
+        const GStat &g = gs[at32(gv + r0, (uint32_t)min(lane + kTB * r, rows - 1))];
+        f.basev[r] = g.base;
+        f.saltv[r] = g.salt;
+      }
+    }
+  }
+}
+
+// Level-0 accumulators of a workgroup (single solves only).
+struct FirstAcc {
+  unsigned long long key = ~0ull, sum = 0;
+  int err = 0;
+};
+
+template <bool L0, bool B, int NQ>
+__device__ __forceinline__ void first_tile_run(const FirstFetch<B, NQ> &f, int32_t n, int32_t *__restrict__ L,
+                                               long long *__restrict__ deg, uint32_t salt,
+                                               const int32_t *__restrict__ gv, GStat *gs, FirstShared<L0, B, NQ> &sh,
+                                               FirstAcc &acc) {
+  using MW = typename MarkWord<NQ>::T;
+  const int lane = threadIdx.x;
+  const int32_t r0 = f.m.x, rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
+  uint8_t *s_mark = reinterpret_cast<uint8_t *>(sh.mark);
+  sh.mark[lane] = 0;
+  int32_t cnt[kRowRegs];
+#pragma unroll
+  for (int r = 0; r < kRowRegs; r++) {
+    cnt[r] = 0;
+    if (r > 0 && kTB * r >= rows) break;
+    const int j = lane + kTB * r;
+    const int32_t nxt = __builtin_amdgcn_readlane(f.rpv[r + 1], 0);
+    cnt[r] = __builtin_amdgcn_update_dpp(nxt, f.rpv[r], 0x130, 0xF, 0xF, false) - f.rpv[r];  // wave_shl:1
+    if (j < rows) {
+      sh.best[j] = 0;
+      if constexpr (L0) sh.sum[j] = 0;
+      if constexpr (B) {
+        sh.base[j] = f.basev[r];
+        sh.salt[j] = f.saltv[r];
+      }
+      if (cnt[r] > 0) s_mark[f.rpv[r] - a0] = (uint8_t)j;
+    }
+  }
+  __syncthreads();
+  if (acnt > 0) {
+    int32_t rw[NQ];
+    lane_rows<NQ>(sh.mark[lane], rw);
+    // running maximum and weight sum per row piece, one LDS update per piece
+    unsigned long long best = 0, sum = 0;
+    int32_t cur = rw[0], bj = 0;
+    uint32_t sj = salt;
+    if constexpr (B) { bj = sh.base[cur]; sj = sh.salt[cur]; }
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      if (NQ * lane + k >= acnt) break;
+      if (rw[k] != cur) {
+        atomicMax(&sh.best[cur], best);
+        if constexpr (L0) atomicAdd(&sh.sum[cur], sum);
+        best = sum = 0;
+        cur = rw[k];
+        if constexpr (B) { bj = sh.base[cur]; sj = sh.salt[cur]; }
+      }
+      const int32_t x = f.xs[k], c = f.cs[k];
+      best = umax64(best, cand_key((uint32_t)c, x - bj, sj));
+      if constexpr (L0) {
+        sum += (unsigned long long)(uint32_t)c;
+        int e = 0;
+        if (x < 0 || x >= n) e |= ERR_COL;
+        if (x == r0 + cur) e |= ERR_SELF;
+        if (c < 1) e |= ERR_WEIGHT;
+        if constexpr (B) {
+          if (e) atomicOr(&gs[gv[r0 + cur]].err, e);  // rare: straight to the graph's flags
+        } else {
+          acc.err |= e;
+        }
+      }
+    }
+    if (NQ * lane < acnt) {
+      atomicMax(&sh.best[cur], best);
+      if constexpr (L0) atomicAdd(&sh.sum[cur], sum);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRowRegs; r++) {
+    if (r > 0 && kTB * r >= rows) break;
+    const int j = lane + kTB * r;
+    if (j < rows) {
+      const int32_t v = r0 + j;
+      int32_t bj = 0;
+      uint32_t sj = salt;
+      if constexpr (B) { bj = f.basev[r]; sj = f.saltv[r]; }
+      L[v] = cnt[r] > 0 ? key_label(sh.best[j], sj) + bj : v;
+      if constexpr (L0) {
+        const unsigned long long d = sh.sum[j];
+        const unsigned long long dd = cnt[r] > 0 ? d : 0ull;
+        deg[v] = (long long)dd;
+        if constexpr (!B) {
+          acc.key = umin64(acc.key, ((dd > 0xFFFFFFFFull ? 0xFFFFFFFFull : dd) << 32) | (uint32_t)v);
+          acc.sum += dd;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <bool L0, bool B>
+__device__ __forceinline__ void first_acc_flush(const FirstAcc &acc, unsigned long long *part, int32_t slot) {
+  if constexpr (L0 && !B) {
+    const unsigned long long k = grp_min<64>(acc.key);
+    const unsigned long long sm = grp_sum<64>(acc.sum);
+    const int e = grp_or<64>(acc.err);
+    if (threadIdx.x == 0) {
+      part[3 * (int64_t)slot] = k;
+      part[3 * (int64_t)slot + 1] = sm;
+      part[3 * (int64_t)slot + 2] = (unsigned long long)e;
+    }
+  }
+}
+
+// Tiles of at most 256 arcs, TP consecutive tiles per workgroup step (all
+// their loads in flight together); tiles of more than 256 arcs are left to
+// k_first_tile_big. Workgroup i writes part entry i.
+template <bool L0, bool B, int TP>
+__global__ __launch_bounds__(kTB) void k_first_tile(const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ col,
+                                                        const int32_t *__restrict__ w, int32_t n,
+                                                        const int4 *__restrict__ meta, int32_t ntiles,
+                                                        int32_t *__restrict__ L, long long *__restrict__ deg,
+                                                        uint32_t salt, const Status *st,
+                                                        unsigned long long *__restrict__ part,
+                                                        const int32_t *__restrict__ gv, GStat *gs, int32_t *prof) {
+  __shared__ FirstShared<L0, B, 4> sh;
+  prof_snapshot(prof, st);
+  FirstAcc acc;
+  if (B || !st->err) {
+    const int32_t groups = (ntiles + TP - 1) / TP;
+    for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
+      int4 m[TP];
+      bool use[TP];
+#pragma unroll
+      for (int u = 0; u < TP; u++) {
+        const int32_t t = g * TP + u;
+        m[u] = t < ntiles ? meta[t] : make_int4(0, 0, 0, 0);
+        use[u] = t < ntiles && m[u].w <= 4 * kTB;
+        if (!use[u]) m[u] = make_int4(m[u].x, 0, 0, 0);
+      }
+      FirstFetch<B, 4> f[TP];
+#pragma unroll
+      for (int u = 0; u < TP; u++) first_fetch(f[u], m[u], rp, col, w, gv, gs);
+#pragma unroll
+      for (int u = 0; u < TP; u++)
+        if (use[u]) first_tile_run<L0, B, 4>(f[u], n, L, deg, salt, gv, gs, sh, acc);
+    }
+  }
+  first_acc_flush<L0, B>(acc, part, (int32_t)blockIdx.x);
+}
+
+// Every tile, one per workgroup (4 or 8 arcs per lane by the tile's size):
+// the hardware keeps many of these short-lived workgroups in flight instead
+// of a workgroup holding several tiles' loads. Workgroup i writes part
+// entry i.
+template <bool L0, bool B>
+__global__ __launch_bounds__(kTB) void k_first_tile_each(const int32_t *__restrict__ rp,
+                                                             const int32_t *__restrict__ col,
+                                                             const int32_t *__restrict__ w, int32_t n,
+                                                             const int4 *__restrict__ meta, int32_t ntiles,
+                                                             int32_t *__restrict__ L, long long *__restrict__ deg,
+                                                             uint32_t salt, const Status *st,
+                                                             unsigned long long *__restrict__ part,
+                                                             const int32_t *__restrict__ gv, GStat *gs,
+                                                             int32_t *prof) {
+  __shared__ FirstShared<L0, B, kPerThread> sh8;
+  prof_snapshot(prof, st);
+  FirstAcc acc;
+  if (B || !st->err) {
+    for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      const int4 m = meta[t];
+      if (m.w <= 4 * kTB) {
+        FirstFetch<B, 4> f;
+        first_fetch(f, m, rp, col, w, gv, gs);
+        first_tile_run<L0, B, 4>(f, n, L, deg, salt, gv, gs, *reinterpret_cast<FirstShared<L0, B, 4> *>(&sh8),
+                                 acc);
+      } else {
+        FirstFetch<B, kPerThread> f;
+        first_fetch(f, m, rp, col, w, gv, gs);
+        first_tile_run<L0, B, kPerThread>(f, n, L, deg, salt, gv, gs, sh8, acc);
+      }
+    }
+  }
+  first_acc_flush<L0, B>(acc, part, (int32_t)blockIdx.x);
+}
+
+// The listed tiles of more than 256 arcs, 8 arcs per lane. Persistent (as
+// many workgroups as fit, striding over the list), with the next tile's
+// loads issued before this tile's LDS phases; workgroup i writes part entry
+// part_base + i.
+template <bool L0, bool B>
+__global__ __launch_bounds__(kTB) void k_first_tile_big(const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const int32_t *__restrict__ w, int32_t n,
+                                                            const int4 *__restrict__ meta,
+                                                            const int32_t *__restrict__ big,
+                                                            int32_t *__restrict__ L, long long *__restrict__ deg,
+                                                            uint32_t salt, const Status *st,
+                                                            unsigned long long *__restrict__ part, int32_t part_base,
+                                                            const int32_t *__restrict__ gv, GStat *gs) {
+  __shared__ FirstShared<L0, B, kPerThread> sh;
+  FirstAcc acc;
+  if (B || !st->err) {
+    const int32_t nb = st->big_tiles;
+    int32_t i = (int32_t)blockIdx.x;
+    if (i < nb) {
+      FirstFetch<B, kPerThread> cur;
+      first_fetch(cur, meta[big[i]], rp, col, w, gv, gs);
+      while (true) {
+        const int32_t in = i + (int32_t)gridDim.x;
+        FirstFetch<B, kPerThread> nxt;
+        if (in < nb) first_fetch(nxt, meta[big[in]], rp, col, w, gv, gs);
+        first_tile_run<L0, B, kPerThread>(cur, n, L, deg, salt, gv, gs, sh, acc);
+        if (in >= nb) break;
+        i = in;
+        cur = nxt;
+      }
+    }
+  }
+  first_acc_flush<L0, B>(acc, part, part_base + (int32_t)blockIdx.x);
 }
 
 // ------------------------------------------------------------ huge rows
@@ -1924,8 +2087,9 @@ __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ r
   }
 }
 
-// The listed tiles of more than 256 arcs, 8 arcs per lane (as many
-// workgroups as fit, striding over the list).
+// The listed tiles of more than 256 arcs, 8 arcs per lane. Persistent (as
+// many workgroups as fit, striding over the list), with the next tile's
+// loads and gathers issued before this tile's LDS phases.
 __global__ __launch_bounds__(kTB) void k_emit_tile_big(const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ col,
                                                            const int32_t *__restrict__ w,
@@ -1938,12 +2102,25 @@ __global__ __launch_bounds__(kTB) void k_emit_tile_big(const int32_t *__restrict
   __shared__ EmitTileShared sh;
   const int key_bits = bits_for(st->k);
   const int32_t nb = st->big_tiles;
-  for (int32_t i = blockIdx.x; i < nb; i += gridDim.x) {
-    const int32_t t = big[i];
-    EmitFetch<kPerThread> f;
-    emit_fetch_loads(f, meta[t], rp, col, w, cl);
-    emit_fetch_gather(f, cl);
-    emit_tile_run<kPerThread>(f, t, key_bits, keys, vals, first, cnt, sh);
+  int32_t i = (int32_t)blockIdx.x;
+  if (i >= nb) return;
+  int32_t t = big[i];
+  EmitFetch<kPerThread> cur;
+  emit_fetch_loads(cur, meta[t], rp, col, w, cl);
+  emit_fetch_gather(cur, cl);
+  while (true) {
+    const int32_t in = i + (int32_t)gridDim.x;
+    const int32_t tn = in < nb ? big[in] : 0;
+    EmitFetch<kPerThread> nxt;
+    if (in < nb) {
+      emit_fetch_loads(nxt, meta[tn], rp, col, w, cl);
+      emit_fetch_gather(nxt, cl);
+    }
+    emit_tile_run<kPerThread>(cur, t, key_bits, keys, vals, first, cnt, sh);
+    if (in >= nb) break;
+    i = in;
+    t = tn;
+    cur = nxt;
   }
 }
 
@@ -3677,15 +3854,31 @@ void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int
 
 // Grid of a persistent kernel: as many workgroups as fit on the device at
 // once (at least one), capped by the work items.
+// (the occupancy query is made once per kernel and device and kept: it costs
+// host time on every launch otherwise)
 template <class K>
 unsigned resident_grid(K kernel, int block, int64_t items) {
-  int dev = 0, per_cu = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    per_cu = cus = 1;
-  const int64_t g = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)std::max(per_cu, 1) * std::max(cus, 1)));
-  return (unsigned)g;
+  static std::mutex mu;
+  static std::vector<std::pair<std::pair<const void *, int>, int64_t>> known;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  const std::pair<const void *, int> key((const void *)kernel, dev * 4096 + block);
+  int64_t full = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto &e : known)
+      if (e.first == key) full = e.second;
+  }
+  if (full == 0) {
+    int per_cu = 0, cus = 0;
+    if (dev < 0 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      per_cu = cus = 1;
+    full = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+    std::lock_guard<std::mutex> lk(mu);
+    known.push_back({key, full});
+  }
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, full));
 }
 
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
@@ -3693,25 +3886,53 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   const int l0 = level0 ? 1 : 0;
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
-  const unsigned tg = grid_for(w.ntiles, 1, 1u << 20);
-  {
+  constexpr int kTP = 2;  // tiles per workgroup step of the small-tile kernel
+  const bool each = tuning_for(g.nnz).first_group == 1;
+  const unsigned tg = each ? grid_for(w.ntiles, 1, 1u << 20) : grid_for((w.ntiles + kTP - 1) / kTP, 1, 1u << 20);
+  const unsigned tb = each ? 0u : resident_grid(k_first_tile_big<true, false>, kTB, w.ntiles);
+  if (each) {
     ProfScope ps(level0 ? PROF_FIRST_TILE_L0 : PROF_FIRST_TILE, s, w.st, w.ntiles);
     if (bv) {
       if (level0)
-        k_first_tile<true, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                       salt, w.st, w.part, gv, gs, ps.dev);
+        k_first_tile_each<true, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                         w.deg, salt, w.st, w.part, gv, gs, ps.dev);
       else
-        k_first_tile<false, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                        salt, w.st, w.part, gv, gs, ps.dev);
+        k_first_tile_each<false, true><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                          w.deg, salt, w.st, w.part, gv, gs, ps.dev);
     } else if (level0) {
-      k_first_tile<true, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                      salt, w.st, w.part, nullptr, nullptr, ps.dev);
+      k_first_tile_each<true, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                        w.deg, salt, w.st, w.part, nullptr, nullptr, ps.dev);
     } else {
-      k_first_tile<false, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L, w.deg,
-                                                       salt, w.st, w.part, nullptr, nullptr, ps.dev);
+      k_first_tile_each<false, false><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                         w.deg, salt, w.st, w.part, nullptr, nullptr, ps.dev);
+    }
+  } else {
+    ProfScope ps(level0 ? PROF_FIRST_TILE_L0 : PROF_FIRST_TILE, s, w.st, w.ntiles);
+    if (bv) {
+      if (level0) {
+        k_first_tile<true, true, kTP><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                         w.deg, salt, w.st, w.part, gv, gs, ps.dev);
+        k_first_tile_big<true, true><<<tb, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.big_tiles, L,
+                                                        w.deg, salt, w.st, w.part, (int32_t)tg, gv, gs);
+      } else {
+        k_first_tile<false, true, kTP><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                          w.deg, salt, w.st, w.part, gv, gs, ps.dev);
+        k_first_tile_big<false, true><<<tb, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.big_tiles, L,
+                                                         w.deg, salt, w.st, w.part, (int32_t)tg, gv, gs);
+      }
+    } else if (level0) {
+      k_first_tile<true, false, kTP><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                        w.deg, salt, w.st, w.part, nullptr, nullptr, ps.dev);
+      k_first_tile_big<true, false><<<tb, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.big_tiles, L,
+                                                       w.deg, salt, w.st, w.part, (int32_t)tg, nullptr, nullptr);
+    } else {
+      k_first_tile<false, false, kTP><<<tg, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.ntiles, L,
+                                                         w.deg, salt, w.st, w.part, nullptr, nullptr, ps.dev);
+      k_first_tile_big<false, false><<<tb, kTB, 0, s>>>(g.row_ptr, g.col, g.w, g.n, w.tile_meta, w.big_tiles, L,
+                                                        w.deg, salt, w.st, w.part, (int32_t)tg, nullptr, nullptr);
     }
   }
-  if (!bv && level0) k_reduce_parts<<<grid_for(tg, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)tg, w.st);
+  if (!bv && level0) k_reduce_parts<<<grid_for(tg + tb, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)(tg + tb), w.st);
   // long rows: a wave per row up to 4096 arcs, chunked beyond
   for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;

@@ -334,7 +334,9 @@ int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
  * takes (lp_group, 1..4) and one emission workgroup takes (emit_group, 1..2),
  * and the launch shape of label-propagation iteration 1 (first_group: 1 = a
  * workgroup per tile, 2 = two short-row tiles per workgroup plus a
- * persistent kernel for the tiles of more than 256 arcs).
+ * persistent kernel for the tiles of more than 256 arcs), and the table of
+ * label propagation on rows of more than 4096 arcs (huge_part: 1 = label
+ * partitions in LDS, 0 = a global hash table per row).
  * The library keeps one set per size bucket (arcs of the level being worked
  * on, at most max_arcs; max_arcs < 0: no bound) and reads the table at load
  * time from the file named by the environment variable VIECUT_TUNING, else

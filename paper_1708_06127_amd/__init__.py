@@ -396,7 +396,7 @@ def profile_read():
 
 
 TUNING_KEYS = ("radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave", "lp_group",
-               "emit_group", "first_group")
+               "emit_group", "first_group", "huge_part")
 
 
 def tuning_set(max_arcs: int, key: str, value: int):

@@ -43,10 +43,11 @@ CANDIDATES = {
     "lp_group": [1, 2, 3, 4],
     "emit_group": [1, 2],
     "first_group": [1, 2],
+    "huge_part": [0, 1],
 }
 DEFAULTS = {"radix_large_from": 1 << 22, "compact_direct_max": 1 << 20, "pr_merge_tiles": 16384,
             "long_split": 512, "emit_wave": 1, "lp_group": 2, "emit_group": 2,
-            "first_group": 1}
+            "first_group": 1, "huge_part": 1}
 
 
 def log(*a):

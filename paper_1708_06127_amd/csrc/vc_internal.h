@@ -19,6 +19,7 @@ constexpr size_t kScratchBytes = VIECUT_NOALLOC_SCRATCH_BYTES;
 constexpr int kMaxScratchDevices = 64;
 constexpr int kBins = 8;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
+constexpr int kPartSlots = 16384;  // LDS table slots of one huge-row label partition (128 KB)
 // Row-aligned arc tiles: tile t holds the rows v with rp[v] + v in
 // [t*kTile, (t+1)*kTile). A row with d >= kTile arcs is always the last row of
 // its tile and is left to the long-row kernels; the short rows of a tile then
@@ -73,6 +74,8 @@ struct Status {
   unsigned long long fix_delta;  // correcting step: minimum weighted degree of the contracted graph
   long long sw_cut;            // device exact solve: the kernel graph's minimum cut
   int32_t lp_changed;          // labels changed by the last counted LP iteration
+  int32_t huge_ticket;         // next work item of the huge-row label partitions
+  int32_t huge_overflow;       // a huge-row label partition filled its table (the global-table path runs)
   int32_t pad1;
 };
 
@@ -345,6 +348,8 @@ struct Tuning {
   int64_t emit_wave = 1;                 // rows of 256..1023 arcs emitted by a wave per row (0: a workgroup)
   int64_t lp_group = 2;                  // tiles of at most 256 arcs per LP workgroup (1..4)
   int64_t emit_group = 2;                // tiles of at most 256 arcs per emission workgroup (1..2)
+  int64_t huge_part = 1;                 // LP t >= 2 on rows of more than 4096 arcs: 1 = label partitions in LDS,
+                                         // 0 = one global hash table per row
   int64_t first_group = 1;               // LP iteration 1: 1 = a workgroup per tile, 2 = two short-row tiles per
                                          // workgroup plus a persistent kernel for the others
 };

@@ -1247,6 +1247,7 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
   __shared__ int64_t sh_c[kBlock], sh_t[kBlock];
   __shared__ int64_t carry_c, carry_t;
   if (st->err) return;
+  if (with_table == 1 && !st->huge_overflow) return;  // the global-table path is the fallback only
   const int32_t cnt = *cnt_p;
   if (threadIdx.x == 0) { carry_c = 0; carry_t = 0; }
   __syncthreads();
@@ -1257,7 +1258,8 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
       int32_t v = list[i];
       int32_t d = rp[v + 1] - rp[v];
       c = (d + kHugeChunk - 1) / kHugeChunk;
-      if (with_table) { t = 1; while (t < 2 * (int64_t)d) t <<= 1; }
+      if (with_table == 1) { t = 1; while (t < 2 * (int64_t)d) t <<= 1; }
+      if (with_table == 2) { c = (2 * (int64_t)d + kPartSlots - 1) / kPartSlots; t = c; }  // label partitions
       best[i] = 0;
       if (deg_zero) deg_zero[v] = 0;
     }
@@ -1274,7 +1276,7 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
     }
     if (i < cnt) {
       meta[3 * (int64_t)i] = (int32_t)(carry_c + sh_c[threadIdx.x] - c);
-      meta[3 * (int64_t)i + 1] = (int32_t)(carry_t + sh_t[threadIdx.x] - t);
+      meta[3 * (int64_t)i + 1] = with_table == 2 ? (int32_t)t : (int32_t)(carry_t + sh_t[threadIdx.x] - t);
       meta[3 * (int64_t)i + 2] = (int32_t)t;
     }
     __syncthreads();
@@ -1283,8 +1285,13 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
   }
   if (threadIdx.x == 0) {
     st->huge_items = (int32_t)carry_c;
-    st->huge_slots = (int32_t)carry_t;
-    if (carry_t > cap) atomicOr(&st->err, ERR_ROWPTR);  // cannot happen: sum of 2^ceil(log2 2d) <= 4 nnz
+    if (with_table == 2) {  // the partition count of row i sits in meta[3i + 1]
+      st->huge_ticket = 0;
+      st->huge_overflow = 0;
+    } else {
+      st->huge_slots = (int32_t)carry_t;
+      if (carry_t > cap) atomicOr(&st->err, ERR_ROWPTR);  // cannot happen: sum of 2^ceil(log2 2d) <= 4 nnz
+    }
   }
 }
 
@@ -1298,7 +1305,7 @@ __device__ __forceinline__ int32_t huge_find(const int32_t *meta, int32_t cnt, i
 }
 
 __global__ void k_huge_clear(int32_t *tk, uint32_t *tv, const Status *st) {
-  if (st->err) return;
+  if (st->err || !st->huge_overflow) return;  // fallback only
   const int64_t slots = st->huge_slots;
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kBlock) {
     tk[i] = -1;
@@ -1388,7 +1395,7 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
   __shared__ int32_t lk[kHugeLocal];
   __shared__ uint32_t lv[kHugeLocal];
   __shared__ unsigned long long red[kBlock / 64];
-  if (!gv && st->err) return;
+  if ((!gv && st->err) || !st->huge_overflow) return;  // fallback only
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
   constexpr uint32_t lmask = kHugeLocal - 1;
@@ -1469,6 +1476,110 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
       if (xs[u] >= 0) key = umax64(key, own_key((uint32_t)old[u] + add[u], xs[u] == own, xs[u] - b0, sl));
     key = block_max(key, red);
     if (threadIdx.x == 0 && key) atomicMax(&best[i], key);
+    __syncthreads();
+  }
+}
+
+// LP iterations t >= 2 on huge rows without a global table: the labels of
+// row i are split into P_i = ceil(2 d / kPartSlots) parts by a hash, and one
+// work item (row, part) sums the weights of its part's labels in an LDS
+// table of kPartSlots slots, so every label's whole sum is in one table
+// (expected load <= 1/2). Each item reads the whole row (neighbour and its
+// label) and loads the weight only for the arcs of its part. The returned
+// partial sum plus the weight bounds the label's final sum from below and
+// the last update sees it, so the item's best key (S, own, -prio) is the
+// maximum over its updates; one atomicMax per wave merges the items of a
+// row. Items are taken by ticket. A table that fills up (a probe sequence
+// longer than the table) sets huge_overflow, and the global-table kernels
+// then redo the whole bin.
+constexpr int kPartThreads = 1024;
+constexpr int kPartBatch = 4;
+__device__ __forceinline__ uint32_t part_of(int32_t x, uint32_t parts) {
+  uint32_t h = ((uint32_t)x ^ 0x5BD1E995u) * 0x2C1B3C6Du;
+  h ^= h >> 15;
+  return __umulhi(h, parts);
+}
+__global__ __launch_bounds__(kPartThreads) void k_huge_part(const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const int32_t *__restrict__ w, const int32_t *list,
+                                                            const int32_t *cnt_p, const int32_t *meta,
+                                                            const int32_t *__restrict__ Lin,
+                                                            unsigned long long *best, uint32_t salt, Status *st,
+                                                            const int32_t *__restrict__ gv, const GStat *gs) {
+  extern __shared__ uint32_t part_lds[];
+  int32_t *tk = reinterpret_cast<int32_t *>(part_lds);
+  uint32_t *tv = part_lds + kPartSlots;
+  __shared__ int32_t s_item;
+  if (!gv && st->err) return;
+  const int32_t cnt = *cnt_p;
+  const int32_t items = st->huge_items;
+  constexpr uint32_t mask = kPartSlots - 1;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&st->huge_ticket, 1);
+    __syncthreads();
+    const int32_t p = s_item;
+    if (p >= items) break;
+    const int32_t i = huge_find(meta, cnt, p, 0);
+    const int32_t v = list[i];
+    const uint32_t parts = (uint32_t)meta[3 * (int64_t)i + 1];
+    const uint32_t mine = (uint32_t)(p - meta[3 * (int64_t)i]);
+    const int32_t beg = rp[v], end = rp[v + 1];
+    const int32_t own = Lin[v];
+    int32_t b0 = 0;
+    uint32_t sl = salt;
+    if (gv) {
+      const GStat &g = gs[gv[v]];
+      b0 = g.base;
+      sl = g.salt;
+    }
+    for (int e = threadIdx.x; e < kPartSlots; e += kPartThreads) {
+      tk[e] = -1;
+      tv[e] = 0;
+    }
+    __syncthreads();
+    unsigned long long key = 0;
+    bool full = false;
+    for (int32_t a0 = beg + threadIdx.x; a0 < end; a0 += kPartThreads * kPartBatch) {
+      int32_t xs[kPartBatch], cs[kPartBatch], h[kPartBatch], old[kPartBatch];
+      bool m[kPartBatch];
+#pragma unroll
+      for (int u = 0; u < kPartBatch; u++) xs[u] = col[min(a0 + u * kPartThreads, end - 1)];
+#pragma unroll
+      for (int u = 0; u < kPartBatch; u++) xs[u] = Lin[xs[u]];
+#pragma unroll
+      for (int u = 0; u < kPartBatch; u++) {
+        m[u] = a0 + u * kPartThreads < end && (parts == 1 || part_of(xs[u], parts) == mine);
+        cs[u] = m[u] ? w[a0 + u * kPartThreads] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kPartBatch; u++) {
+        h[u] = (int32_t)((mul24_golden((uint32_t)xs[u] ^ ((uint32_t)xs[u] >> 16)) >> 8) & mask);
+        old[u] = m[u] ? atomicCAS(&tk[h[u]], -1, xs[u]) : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kPartBatch; u++) {
+        if (!m[u]) continue;
+        int32_t probes = 0;
+        while (old[u] != -1 && old[u] != xs[u]) {  // taken by another label: probe on
+          if (++probes >= kPartSlots) {            // the table is full
+            full = true;
+            m[u] = false;
+            break;
+          }
+          h[u] = (h[u] + 1) & (int32_t)mask;
+          old[u] = atomicCAS(&tk[h[u]], -1, xs[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kPartBatch; u++)
+        if (m[u]) {
+          const uint32_t S = atomicAdd(&tv[h[u]], (uint32_t)cs[u]) + (uint32_t)cs[u];
+          key = umax64(key, own_key(S, xs[u] == own, xs[u] - b0, sl));
+        }
+    }
+    if (full) st->huge_overflow = 1;
+    key = grp_max<64>(key);
+    if ((threadIdx.x & 63) == 0 && key) atomicMax(&best[i], key);
     __syncthreads();
   }
 }
@@ -4005,6 +4116,22 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   if (bin_items(known, kBinHuge, 1) <= 0) return hipGetLastError();
   const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
   const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
+  // label partitions in LDS; the global-table kernels run only if a partition overflowed
+  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 2, w.huge_cap, w.st, nullptr);
+  if (!tuning_for(g.nnz).huge_part) {  // the global-table path for every huge row
+    const hipError_t e = fill_i32(&w.st->huge_overflow, 1, 1, s);
+    if (e != hipSuccess) return e;
+  } else {
+    static bool attr = false;
+    if (!attr) {
+      const hipError_t e = hipFuncSetAttribute((const void *)k_huge_part, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(8 * kPartSlots));
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    k_huge_part<<<resident_grid(k_huge_part, kPartThreads, 1 << 20), kPartThreads, 8 * kPartSlots, s>>>(
+        g.row_ptr, g.col, g.w, list6, cnt6, w.huge_meta, Lin, w.huge_best, salt, w.st, gv, gs);
+  }
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st, nullptr);
   k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);
   k_huge_insert<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, list6, cnt6,

@@ -49,10 +49,11 @@ int64_t *field(Tuning &t, const char *key) {
   if (!std::strcmp(key, "lp_group")) return &t.lp_group;
   if (!std::strcmp(key, "emit_group")) return &t.emit_group;
   if (!std::strcmp(key, "first_group")) return &t.first_group;
+  if (!std::strcmp(key, "huge_part")) return &t.huge_part;
   return nullptr;
 }
 const char *kKeys[] = {"radix_large_from", "compact_direct_max", "pr_merge_tiles", "long_split", "emit_wave",
-                       "lp_group", "emit_group", "first_group"};
+                       "lp_group", "emit_group", "first_group", "huge_part"};
 
 bool valid(const char *key, int64_t v) {
   if (!std::strcmp(key, "long_split")) return v >= kTile && v <= 512;  // the 1024-slot class holds d < 512
@@ -60,6 +61,7 @@ bool valid(const char *key, int64_t v) {
   if (!std::strcmp(key, "lp_group")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "emit_group")) return v == 1 || v == 2;
   if (!std::strcmp(key, "first_group")) return v == 1 || v == 2;
+  if (!std::strcmp(key, "huge_part")) return v == 0 || v == 1;
   return v >= 0;
 }
 

@@ -1485,7 +1485,8 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
 // work item (row, part) sums the weights of its part's labels in an LDS
 // table of kPartSlots slots, so every label's whole sum is in one table
 // (expected load <= 1/2). Each item reads the whole row (neighbour and its
-// label) and loads the weight only for the arcs of its part. The returned
+// label, 8 arcs per thread in flight) and loads the weight only for the arcs
+// of its part. The returned
 // partial sum plus the weight bounds the label's final sum from below and
 // the last update sees it, so the item's best key (S, own, -prio) is the
 // maximum over its updates; one atomicMax per wave merges the items of a
@@ -1493,7 +1494,7 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
 // longer than the table) sets huge_overflow, and the global-table kernels
 // then redo the whole bin.
 constexpr int kPartThreads = 1024;
-constexpr int kPartBatch = 4;
+constexpr int kPartBatch = 8;
 __device__ __forceinline__ uint32_t part_of(int32_t x, uint32_t parts) {
   uint32_t h = ((uint32_t)x ^ 0x5BD1E995u) * 0x2C1B3C6Du;
   h ^= h >> 15;

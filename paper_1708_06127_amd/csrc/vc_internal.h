@@ -20,6 +20,8 @@ constexpr int kMaxScratchDevices = 64;
 constexpr int kBins = 8;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
 constexpr int kPartSlots = 16384;  // LDS table slots of one huge-row label partition (128 KB)
+constexpr int kPartDistinct = 4;   // pass 1 plans room for d / kPartDistinct distinct labels of a huge row
+constexpr int kPartProbe = 64;     // pass 1: a longer probe run sends the row to pass 2
 // Row-aligned arc tiles: tile t holds the rows v with rp[v] + v in
 // [t*kTile, (t+1)*kTile). A row with d >= kTile arcs is always the last row of
 // its tile and is left to the long-row kernels; the short rows of a tile then
@@ -75,8 +77,8 @@ struct Status {
   long long sw_cut;            // device exact solve: the kernel graph's minimum cut
   int32_t lp_changed;          // labels changed by the last counted LP iteration
   int32_t huge_ticket;         // next work item of the huge-row label partitions
-  int32_t huge_overflow;       // a huge-row label partition filled its table (the global-table path runs)
-  int32_t pad1;
+  int32_t huge_overflow;       // a huge-row label partition of pass 1 overflowed (its row runs again)
+  int32_t huge_fallback;       // a pass-2 partition filled its table (the global-table path runs)
 };
 
 // Kernel graphs of at most this many vertices are solved on the device (dense

@@ -1238,8 +1238,17 @@ __global__ __launch_bounds__(kTB) void k_first_tile_big(const int32_t *__restric
 
 // ------------------------------------------------------------ huge rows
 // Rows longer than 4096 arcs: split into chunks; one workgroup per chunk.
-// plan: per huge vertex i, meta[3i] = first chunk, meta[3i+1] = table offset,
-// meta[3i+2] = table size (power of two >= 2 d, or 0 without a table).
+// plan, per huge vertex i by mode:
+//  0: meta[3i] = first chunk (chunks of kHugeChunk arcs);
+//  1: the same plus meta[3i+1] = table offset, meta[3i+2] = table size
+//     (power of two >= 2 d) of the global-table path (runs only when
+//     huge_fallback is set);
+//  2: label partitions: meta[3i] = first work item, meta[3i+1] = parts
+//     P = ceil(2 d / (kPartDistinct kPartSlots)) (room for d / kPartDistinct
+//     distinct labels at load 1/2), meta[3i+2] = 0 (the row's overflow flag);
+//  3: (only when huge_overflow is set) the rows whose flag is set get
+//     P = ceil(2 d / kPartSlots) (room for d distinct labels) and a cleared
+//     best key; the others get no item and keep their key.
 // (deg_zero, at level 0: the huge rows' degree accumulators, zeroed here)
 __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_t *cnt_p, int32_t *meta,
                             unsigned long long *best, int with_table, int64_t cap, Status *st,
@@ -1247,7 +1256,8 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
   __shared__ int64_t sh_c[kBlock], sh_t[kBlock];
   __shared__ int64_t carry_c, carry_t;
   if (st->err) return;
-  if (with_table == 1 && !st->huge_overflow) return;  // the global-table path is the fallback only
+  if (with_table == 1 && !st->huge_fallback) return;  // the global-table path is the fallback only
+  if (with_table == 3 && !st->huge_overflow) return;  // no partition overflowed
   const int32_t cnt = *cnt_p;
   if (threadIdx.x == 0) { carry_c = 0; carry_t = 0; }
   __syncthreads();
@@ -1259,8 +1269,12 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
       int32_t d = rp[v + 1] - rp[v];
       c = (d + kHugeChunk - 1) / kHugeChunk;
       if (with_table == 1) { t = 1; while (t < 2 * (int64_t)d) t <<= 1; }
-      if (with_table == 2) { c = (2 * (int64_t)d + kPartSlots - 1) / kPartSlots; t = c; }  // label partitions
-      best[i] = 0;
+      if (with_table == 2) {
+        constexpr int64_t room = (int64_t)kPartDistinct * kPartSlots;
+        c = t = (2 * (int64_t)d + room - 1) / room;
+      }
+      if (with_table == 3) c = t = meta[3 * (int64_t)i + 2] ? (2 * (int64_t)d + kPartSlots - 1) / kPartSlots : 0;
+      if (with_table != 3 || c > 0) best[i] = 0;
       if (deg_zero) deg_zero[v] = 0;
     }
     sh_c[threadIdx.x] = c;
@@ -1276,8 +1290,8 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
     }
     if (i < cnt) {
       meta[3 * (int64_t)i] = (int32_t)(carry_c + sh_c[threadIdx.x] - c);
-      meta[3 * (int64_t)i + 1] = with_table == 2 ? (int32_t)t : (int32_t)(carry_t + sh_t[threadIdx.x] - t);
-      meta[3 * (int64_t)i + 2] = (int32_t)t;
+      meta[3 * (int64_t)i + 1] = with_table >= 2 ? (int32_t)t : (int32_t)(carry_t + sh_t[threadIdx.x] - t);
+      if (with_table != 3) meta[3 * (int64_t)i + 2] = with_table == 2 ? 0 : (int32_t)t;
     }
     __syncthreads();
     if (threadIdx.x == kBlock - 1) { carry_c += sh_c[kBlock - 1]; carry_t += sh_t[kBlock - 1]; }
@@ -1285,9 +1299,12 @@ __global__ void k_huge_plan(const int32_t *rp, const int32_t *list, const int32_
   }
   if (threadIdx.x == 0) {
     st->huge_items = (int32_t)carry_c;
-    if (with_table == 2) {  // the partition count of row i sits in meta[3i + 1]
+    if (with_table >= 2) {  // the partition count of row i sits in meta[3i + 1]
       st->huge_ticket = 0;
-      st->huge_overflow = 0;
+      if (with_table == 2) {
+        st->huge_overflow = 0;
+        st->huge_fallback = 0;
+      }
     } else {
       st->huge_slots = (int32_t)carry_t;
       if (carry_t > cap) atomicOr(&st->err, ERR_ROWPTR);  // cannot happen: sum of 2^ceil(log2 2d) <= 4 nnz
@@ -1305,7 +1322,7 @@ __device__ __forceinline__ int32_t huge_find(const int32_t *meta, int32_t cnt, i
 }
 
 __global__ void k_huge_clear(int32_t *tk, uint32_t *tv, const Status *st) {
-  if (st->err || !st->huge_overflow) return;  // fallback only
+  if (st->err || !st->huge_fallback) return;  // fallback only
   const int64_t slots = st->huge_slots;
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < slots; i += (int64_t)gridDim.x * kBlock) {
     tk[i] = -1;
@@ -1395,7 +1412,7 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
   __shared__ int32_t lk[kHugeLocal];
   __shared__ uint32_t lv[kHugeLocal];
   __shared__ unsigned long long red[kBlock / 64];
-  if ((!gv && st->err) || !st->huge_overflow) return;  // fallback only
+  if ((!gv && st->err) || !st->huge_fallback) return;  // fallback only
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
   constexpr uint32_t lmask = kHugeLocal - 1;
@@ -1481,18 +1498,20 @@ __global__ __launch_bounds__(kBlock) void k_huge_insert(const int32_t *__restric
 }
 
 // LP iterations t >= 2 on huge rows without a global table: the labels of
-// row i are split into P_i = ceil(2 d / kPartSlots) parts by a hash, and one
-// work item (row, part) sums the weights of its part's labels in an LDS
-// table of kPartSlots slots, so every label's whole sum is in one table
-// (expected load <= 1/2). Each item reads the whole row (neighbour and its
+// row i are split into P_i parts by a hash (as planned by k_huge_plan modes 2
+// and 3), and one work item (row, part) sums the weights of its part's labels
+// in an LDS table of kPartSlots slots, so every label's whole sum is in one
+// table. Each item reads the whole row (neighbour and its
 // label, 8 arcs per thread in flight) and loads the weight only for the arcs
 // of its part. The returned
 // partial sum plus the weight bounds the label's final sum from below and
 // the last update sees it, so the item's best key (S, own, -prio) is the
 // maximum over its updates; one atomicMax per wave merges the items of a
-// row. Items are taken by ticket. A table that fills up (a probe sequence
-// longer than the table) sets huge_overflow, and the global-table kernels
-// then redo the whole bin.
+// row. Items are taken by ticket. Pass 1 plans room for a quarter of the
+// arcs as distinct labels; a probe run longer than kPartProbe flags the row
+// and sets huge_overflow, and pass 2 redoes the flagged rows with room for
+// every arc. A table that fills up in pass 2 sets huge_fallback, and the
+// global-table kernels (which otherwise exit at once) redo the whole bin.
 constexpr int kPartThreads = 1024;
 constexpr int kPartBatch = 8;
 __device__ __forceinline__ uint32_t part_of(int32_t x, uint32_t parts) {
@@ -1506,12 +1525,15 @@ __global__ __launch_bounds__(kPartThreads) void k_huge_part(const int32_t *__res
                                                             const int32_t *cnt_p, const int32_t *meta,
                                                             const int32_t *__restrict__ Lin,
                                                             unsigned long long *best, uint32_t salt, Status *st,
-                                                            const int32_t *__restrict__ gv, const GStat *gs) {
+                                                            const int32_t *__restrict__ gv, const GStat *gs,
+                                                            int32_t *row_flag, int pass) {
   extern __shared__ uint32_t part_lds[];
   int32_t *tk = reinterpret_cast<int32_t *>(part_lds);
   uint32_t *tv = part_lds + kPartSlots;
   __shared__ int32_t s_item;
   if (!gv && st->err) return;
+  if (pass == 2 && !st->huge_overflow) return;
+  const int32_t max_probe = pass == 1 ? kPartProbe : kPartSlots;
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
   constexpr uint32_t mask = kPartSlots - 1;
@@ -1562,7 +1584,7 @@ __global__ __launch_bounds__(kPartThreads) void k_huge_part(const int32_t *__res
         if (!m[u]) continue;
         int32_t probes = 0;
         while (old[u] != -1 && old[u] != xs[u]) {  // taken by another label: probe on
-          if (++probes >= kPartSlots) {            // the table is full
+          if (++probes >= max_probe) {             // too full for this row's parts
             full = true;
             m[u] = false;
             break;
@@ -1578,7 +1600,14 @@ __global__ __launch_bounds__(kPartThreads) void k_huge_part(const int32_t *__res
           key = umax64(key, own_key(S, xs[u] == own, xs[u] - b0, sl));
         }
     }
-    if (full) st->huge_overflow = 1;
+    if (full) {
+      if (pass == 1) {
+        row_flag[3 * (int64_t)i + 2] = 1;
+        st->huge_overflow = 1;
+      } else {
+        st->huge_fallback = 1;
+      }
+    }
     key = grp_max<64>(key);
     if ((threadIdx.x & 63) == 0 && key) atomicMax(&best[i], key);
     __syncthreads();
@@ -4120,7 +4149,7 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
   // label partitions in LDS; the global-table kernels run only if a partition overflowed
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 2, w.huge_cap, w.st, nullptr);
   if (!tuning_for(g.nnz).huge_part) {  // the global-table path for every huge row
-    const hipError_t e = fill_i32(&w.st->huge_overflow, 1, 1, s);
+    const hipError_t e = fill_i32(&w.st->huge_fallback, 1, 1, s);
     if (e != hipSuccess) return e;
   } else {
     static bool attr = false;
@@ -4130,8 +4159,13 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
       if (e != hipSuccess) return e;
       attr = true;
     }
-    k_huge_part<<<resident_grid(k_huge_part, kPartThreads, 1 << 20), kPartThreads, 8 * kPartSlots, s>>>(
-        g.row_ptr, g.col, g.w, list6, cnt6, w.huge_meta, Lin, w.huge_best, salt, w.st, gv, gs);
+    const unsigned pg = resident_grid(k_huge_part, kPartThreads, 1 << 20);
+    k_huge_part<<<pg, kPartThreads, 8 * kPartSlots, s>>>(g.row_ptr, g.col, g.w, list6, cnt6, w.huge_meta, Lin,
+                                                         w.huge_best, salt, w.st, gv, gs, w.huge_meta, 1);
+    // flagged rows again with room for every arc (both launches exit at once without a flag)
+    k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 3, w.huge_cap, w.st, nullptr);
+    k_huge_part<<<pg, kPartThreads, 8 * kPartSlots, s>>>(g.row_ptr, g.col, g.w, list6, cnt6, w.huge_meta, Lin,
+                                                         w.huge_best, salt, w.st, gv, gs, w.huge_meta, 2);
   }
   k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 1, w.huge_cap, w.st, nullptr);
   k_huge_clear<<<2048, kBlock, 0, s>>>(w.huge_tab_key, w.huge_tab_val, w.st);

@@ -113,6 +113,19 @@ def hub_graph(seed, hub_deg):
     return gg.from_edges(n, e, rng.integers(1, 5, len(e)))
 
 
+@pytest.mark.parametrize("leaves", [6000, 20000, 70000])
+def test_huge_row_of_distinct_labels(leaves):
+    """A hub joined (weight 1) to leaves that each have a private partner
+    (weight 10): after iteration 1 every leaf holds its partner's label, so
+    the hub's row (more than 4096 arcs) sees as many distinct labels as arcs
+    in iteration 2 - more than the first partition pass plans room for, so
+    the hub goes through the second pass (with 70,000 leaves: several
+    partitions of the full-size table)."""
+    e = [(0, i) for i in range(1, leaves + 1)] + [(i, leaves + i) for i in range(1, leaves + 1)]
+    g = gg.from_edges(2 * leaves + 1, e, [1] * leaves + [10] * leaves)
+    compare(g, "distinct%d" % leaves, trace=True, lp_iters=3, n0=16, seed=1)
+
+
 @pytest.mark.parametrize("hub_deg", [100, 700, 3000, 9000, 40000])
 def test_degree_classes(hub_deg):
     g = hub_graph(hub_deg, hub_deg)

@@ -61,6 +61,8 @@ def _load():
         lib.gg_planted.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_int32, ctypes.c_uint64]
         lib.gg_rhg.restype = vp
+        lib.gg_clustered_er.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_uint64]
+        lib.gg_clustered_er.restype = vp
         lib.gg_rhg.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_uint64, ctypes.c_int32]
         lib.gg_rmat.restype = vp
@@ -126,6 +128,14 @@ def planted(n: int, d: float, kx: int, wlo: int = 1, whi: int = 1, seed: int = 0
     [wlo, whi]."""
     p = _load().gg_planted(int(n), float(d), int(kx), int(wlo), int(whi), int(seed) & (2**64 - 1))
     return _take(p, "planted(n=%d,d=%g,kx=%d,w=[%d,%d],seed=%d)" % (n, d, kx, wlo, whi, seed), ("kx",))
+
+
+def clustered_er(n: int, d: float, k: int, seed: int = 0) -> Graph:
+    """Clustered Erdos-Renyi graph: each pair is an edge with probability
+    d / 100, weights uniform in [1, 100], multiplied by n inside a cluster;
+    k balanced clusters from a seeded permutation."""
+    p = _load().gg_clustered_er(int(n), float(d), int(k), int(seed) & (2**64 - 1))
+    return _take(p, "clustered_er(n=%d,d=%g,k=%d,seed=%d)" % (n, d, k, seed), ("k",))
 
 
 def rhg(n: int, avg_deg: float, gamma: float = 5.0, seed: int = 0, wlo: int = 1, whi: int = 1,

@@ -269,6 +269,31 @@ Csr planted(int32_t n, double d, int32_t kx, int32_t wlo, int32_t whi, uint64_t 
   return build_csr(n, edges);
 }
 
+// ------------------------------------------------------ clustered ER ----
+// Clustered Erdos-Renyi graph (the paper's appendix on instances): every
+// unordered pair is an edge with probability d / 100 (so m has mean
+// n (n - 1) / 2 * d / 100), its weight is uniform in [1, 100] and multiplied
+// by n when both ends are in the same cluster. The k clusters are balanced:
+// a seeded random permutation deals the vertices round-robin.
+Csr clustered_er(int32_t n, double d, int32_t k, uint64_t seed) {
+  Rng rng(seed, 1);
+  std::vector<int32_t> perm(n), cluster(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  for (int32_t i = n - 1; i > 0; i--) std::swap(perm[i], perm[rng.below(i + 1)]);
+  for (int32_t i = 0; i < n; i++) cluster[perm[i]] = k > 0 ? i % k : 0;
+  const double p = d / 100.0;
+  Rng er(seed, 2), wr(seed, 3);
+  std::vector<Edge> edges;
+  for (int32_t u = 0; u < n; u++)
+    for (int32_t v = u + 1; v < n; v++) {
+      if (er.uniform() >= p) continue;
+      int64_t w = 1 + (int64_t)wr.below(100);
+      if (cluster[u] == cluster[v]) w *= n;
+      edges.push_back({u, v, (int32_t)std::min<int64_t>(w, INT32_MAX)});
+    }
+  return build_csr(n, edges);
+}
+
 // ----------------------------------------------------------------- RHG ----
 // Threshold random hyperbolic graph: points in a disk of radius R, angle
 // uniform, radius with density alpha*sinh(alpha r)/(cosh(alpha R)-1),
@@ -480,6 +505,12 @@ extern "C" {
 void *gg_planted(int32_t n, double d, int32_t kx, int32_t wlo, int32_t whi, uint64_t seed) {
   double info[1] = {(double)kx};
   return export_csr(planted(n, d, kx, wlo, whi, seed), info, 1);
+}
+
+// clustered Erdos-Renyi graph; info = {number of clusters}
+void *gg_clustered_er(int32_t n, double d, int32_t k, uint64_t seed) {
+  double info[1] = {(double)k};
+  return export_csr(clustered_er(n, d, k, seed), info, 1);
 }
 
 // random hyperbolic graph; info = {R, realised average degree, n before LCC}

@@ -219,3 +219,22 @@ def test_error_codes_and_recovery():
     ws = vc.workspace(ok.n, ok.nnz)
     cut, _, _ = vc.mincut(rp, col, w, ws=ws, n0=1)
     assert cut == 2
+
+
+@pytest.mark.parametrize("n,d,k", [(200, 40.0, 2), (300, 10.0, 5), (600, 15.0, 3), (900, 5.0, 8)])
+def test_clustered_er(n, d, k):
+    """The clustered Erdos-Renyi family (the paper's appendix on instances)
+    at sizes whose total weight fits int32 (intra-cluster weights are up to
+    100 n); traced parity with the oracle."""
+    g = gg.clustered_er(n, d, k, seed=n + k)
+    compare(g, "cer%d-%g-%d" % (n, d, k), trace=True, lp_iters=2, n0=16, seed=k)
+
+
+def test_clustered_er_beyond_int32_is_refused():
+    """At n = 2,000 and 10 % density the total weight passes INT32_MAX: the
+    library returns VIECUT_EOVERFLOW before any round (the int64-weight
+    variant the paper's sizes need is not built)."""
+    g = gg.clustered_er(2000, 10.0, 4, 1)
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(*to_dev(g), lp_iters=2, n0=64)
+    assert e.value.code == vc.EOVERFLOW

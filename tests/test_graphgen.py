@@ -80,3 +80,27 @@ def test_c4_params_ranges():
     ns = np.array([p[0] for p in ps])
     assert ns.min() >= 64 and ns.max() <= 8192
     assert all(8.0 <= p[1] <= 64.0 and 1 <= p[2] <= 20 for p in ps)
+
+
+@pytest.mark.parametrize("n,d,k", [(300, 20.0, 4), (500, 5.0, 3), (120, 100.0, 5)])
+def test_clustered_er_shape(n, d, k):
+    """Density d % (binomial edge count within 5 sigma), weights in [1, 100]
+    between clusters and in [n, 100 n] inside them, k balanced clusters
+    (the components of the heavy edges at full density), determinism."""
+    g = gg.clustered_er(n, d, k, seed=7)
+    well_formed(g)
+    assert np.array_equal(g.col, gg.clustered_er(n, d, k, seed=7).col)
+    pairs = n * (n - 1) / 2
+    m = g.nnz // 2
+    p = d / 100.0
+    assert abs(m - pairs * p) <= 5 * np.sqrt(pairs * p * (1 - p)) + 1
+    heavy = g.w >= n
+    assert np.all((g.w[~heavy] >= 1) & (g.w[~heavy] <= 100))
+    assert np.all((g.w[heavy] >= n) & (g.w[heavy] <= 100 * n) & (g.w[heavy] % n == 0))
+    if d == 100.0:
+        rows = np.repeat(np.arange(n), np.diff(g.row_ptr))
+        A = sp.csr_matrix((np.ones(heavy.sum()), (rows[heavy], g.col[heavy])), shape=(n, n))
+        nc, lab = connected_components(A, directed=False)
+        assert nc == k
+        sizes = np.bincount(lab)
+        assert sizes.max() - sizes.min() <= 1

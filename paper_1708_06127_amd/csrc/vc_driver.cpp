@@ -344,6 +344,34 @@ struct Solver {
     return (char *)buf;
   }
 
+  // A status read that lets work enqueued after it run while the host waits:
+  // status_begin queues the copy (into the page-locked buffer) and an event,
+  // status_end waits for the event only.
+  static hipEvent_t status_event() {
+    static thread_local hipEvent_t ev = nullptr;
+    static thread_local int ev_dev = -1;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (ev && ev_dev != dev) {
+      (void)hipEventDestroy(ev);
+      ev = nullptr;
+    }
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    ev_dev = ev ? dev : -1;
+    return ev;
+  }
+  int status_begin(hipEvent_t ev) {
+    VC_TRY(hipMemcpyAsync(pinned_status(), w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
+    VC_TRY(hipEventRecord(ev, s));
+    return VIECUT_OK;
+  }
+  int status_end(hipEvent_t ev) {
+    VC_TRY(hipEventSynchronize(ev));
+    st = *pinned_status();
+    if (st.err & ERR_DEVICE) return VIECUT_EDEVICE;
+    return VIECUT_OK;
+  }
+
   int sync_status() {
     Status *h = pinned ? pinned_status() : nullptr;
     VC_TRY(hipMemcpyAsync(h ? h : &st, w.st, sizeof(Status), hipMemcpyDeviceToHost, s));
@@ -481,7 +509,22 @@ struct Solver {
     VC_TRY(lp_first(G, w, nullptr, w.La, salt(0, 1), true, s));
     if (p.flags & VIECUT_F_VALIDATE) VC_TRY(validate_sym(G, w.st, s));
     VC_TRY(bound_level0(w, s));
-    int rc = sync_status();
+    // the arc tiles of LP iteration 2 need neither the level-0 status nor the
+    // long-row counts, so they run while the host waits for the status (they
+    // exit at once on an input error)
+    hipEvent_t ev = nullptr;
+    const bool early = pinned && !tr.fn && do_lp && p.lp_iters >= 2 &&
+                       !(p.flags & (VIECUT_F_RESTRICT | VIECUT_F_CONVERGE)) && pinned_status() &&
+                       (ev = status_event()) != nullptr;
+    int rc;
+    if (early) {
+      rc = status_begin(ev);
+      if (rc) return rc;
+      VC_TRY(lp_iter(G, w, nullptr, w.La, w.Lb, salt(0, 2), s, nullptr, 1));
+      rc = status_end(ev);
+    } else {
+      rc = sync_status();
+    }
     if (rc) return rc;
     if (st.err & (ERR_ROWPTR | ERR_COL | ERR_SELF)) return VIECUT_EINVAL;
     if (st.err & ERR_WEIGHT) return VIECUT_EWEIGHT;
@@ -527,7 +570,8 @@ struct Solver {
         rc = converged(nullptr, Lc, stop_lp);
         if (rc) return rc;
         for (int32_t t = 2; t <= p.lp_iters && !stop_lp; t++) {
-          VC_TRY(lp_iter(G, w, known, Lc, Lo, salt(r, t), s));
+          // (round 0, iteration 2 with the early tiles: only the long rows are left)
+          VC_TRY(lp_iter(G, w, known, Lc, Lo, salt(r, t), s, nullptr, (early && r == 0 && t == 2) ? 2 : 0));
           std::swap(Lc, Lo);
           trace_labels(r, t, Lc, G.n);
           rc = converged(Lo, Lc, stop_lp);

@@ -241,9 +241,11 @@ hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s);
 // with validation, the weighted degree and the minimum-degree key
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
                     hipStream_t s, const BatchView *bv = nullptr);
-// iteration t >= 2: neighbour-label weight sums in hash tables
+// iteration t >= 2: neighbour-label weight sums in hash tables; part 0: the
+// whole iteration, 1: only the arc tiles (rows of fewer than 256 arcs), 2:
+// only the long and huge rows
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
-                   hipStream_t s, const BatchView *bv = nullptr);
+                   hipStream_t s, const BatchView *bv = nullptr, int part = 0);
 hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchView *bv = nullptr);
 // relabel: ids = prefix sum of used label values, cl[v] = ids[L[v]], k -> st->k;
 // a single solve also composes map[u] <- cl[map[u]] in the same pass

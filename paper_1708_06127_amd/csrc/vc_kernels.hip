@@ -4124,10 +4124,10 @@ void launch_lp_small(int tp, const DGraph &g, Work &w, const int32_t *Lin, int32
 }
 
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
-                   hipStream_t s, const BatchView *bv) {
+                   hipStream_t s, const BatchView *bv, int part) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
-  {
+  if (part != 2) {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
     const int tp = (int)tuning_for(g.nnz).lp_group;
     if (bv) {
@@ -4140,6 +4140,7 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
           g.row_ptr, g.col, g.w, Lin, Lout, w.tile_meta, w.big_tiles, salt, w.st, nullptr, nullptr);
     }
   }
+  if (part == 1) return hipGetLastError();
   launch_tab<64, 1024>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<64, 2048>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<256, 8192>(g, w, 6, known, Lin, Lout, salt, s, gv, gs);

@@ -2044,12 +2044,14 @@ struct alignas(16) EmitTileShared {
 };
 
 // Registers of one emission tile: lane l's arcs [NQ l, NQ l + NQ) (their
-// neighbours' clusters and weights) and the rows' first arcs and clusters,
-// one entry per 64 rows (only entries below the row count are loaded).
+// neighbours' clusters) and the rows' first arcs and clusters, one entry per
+// 64 rows (only entries below the row count are loaded). Weights are loaded
+// later, for the arcs between clusters only (a few percent of the arcs after
+// label propagation).
 template <int NQ>
 struct EmitFetch {
   int4 m;
-  int32_t cus[NQ], cs[NQ];
+  int32_t cus[NQ];
   int32_t rpv[kRowRegs + 1];
   int32_t clv[kRowRegs];
 };
@@ -2062,14 +2064,10 @@ __device__ __forceinline__ void emit_fetch_loads(EmitFetch<NQ> &f, int4 m, const
   f.m = m;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
 #pragma unroll
-  for (int k = 0; k < NQ; k++) f.cus[k] = f.cs[k] = 0;
+  for (int k = 0; k < NQ; k++) f.cus[k] = 0;
   if (acnt > 0) {
 #pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      const uint32_t i = (uint32_t)min(NQ * lane + k, acnt - 1);
-      f.cus[k] = at32(col + a0, i);
-      f.cs[k] = at32(w + a0, i);
-    }
+    for (int k = 0; k < NQ; k++) f.cus[k] = at32(col + a0, (uint32_t)min(NQ * lane + k, acnt - 1));
   }
 #pragma unroll
   for (int r = 0; r <= kRowRegs; r++) {
@@ -2096,10 +2094,10 @@ __device__ __forceinline__ void emit_fetch_gather(EmitFetch<NQ> &f, const int32_
 // a power of two), and written in slot order into the tile's arc range.
 // Tiles with no such arc write an empty segment and skip the table.
 template <int NQ>
-__device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, int32_t t, int key_bits,
-                                              unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
-                                              int32_t *__restrict__ first, int32_t *__restrict__ cnt,
-                                              EmitTileShared &sh) {
+__device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, const int32_t *__restrict__ w, int32_t t,
+                                              int key_bits, unsigned long long *__restrict__ keys,
+                                              int32_t *__restrict__ vals, int32_t *__restrict__ first,
+                                              int32_t *__restrict__ cnt, EmitTileShared &sh) {
   using MW = typename MarkWord<NQ>::T;
   const int lane = threadIdx.x;
   const int32_t rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
@@ -2128,8 +2126,9 @@ __device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, int32_t t,
     const int32_t cv = sh.rcl[rw[k]];
     ok[k] = NQ * lane + k < acnt && f.cus[k] != cv;
     key[k] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)f.cus[k];
-    cc[k] = (uint32_t)f.cs[k];
   }
+#pragma unroll
+  for (int k = 0; k < NQ; k++) cc[k] = ok[k] ? (uint32_t)at32(w + a0, (uint32_t)(NQ * lane + k)) : 0u;
   // fold runs of equal pairs into their first arc
 #pragma unroll
   for (int k = NQ - 1; k > 0; k--)
@@ -2224,7 +2223,7 @@ __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ r
     for (int u = 0; u < TP; u++) emit_fetch_gather(f[u], cl);
 #pragma unroll
     for (int u = 0; u < TP; u++)
-      if (use[u]) emit_tile_run<4>(f[u], g * TP + u, key_bits, keys, vals, first, cnt, sh);
+      if (use[u]) emit_tile_run<4>(f[u], w, g * TP + u, key_bits, keys, vals, first, cnt, sh);
   }
 }
 
@@ -2257,7 +2256,7 @@ __global__ __launch_bounds__(kTB) void k_emit_tile_big(const int32_t *__restrict
       emit_fetch_loads(nxt, meta[tn], rp, col, w, cl);
       emit_fetch_gather(nxt, cl);
     }
-    emit_tile_run<kPerThread>(cur, t, key_bits, keys, vals, first, cnt, sh);
+    emit_tile_run<kPerThread>(cur, w, t, key_bits, keys, vals, first, cnt, sh);
     if (in >= nb) break;
     i = in;
     t = tn;

@@ -15,12 +15,12 @@
 //
 // Work is cut by arc count: rows of fewer than 256 arcs are processed on
 // row-aligned arc tiles (tile t holds the rows v with row_ptr[v] + v in
-// [256 t, 256 (t + 1)), one 64-lane workgroup per tile, each row owning a
-// region of an LDS hash table keyed by neighbour label). Longer rows are
-// listed per level: a wave per row with an LDS table up to 1023 arcs, a
-// workgroup per row with an LDS table up to 4096 arcs, and beyond that rows
-// split into 4096-arc chunks handled by many workgroups that share a
-// global-memory table per row.
+// [256 t, 256 (t + 1)), one 64-lane wave per tile, each row owning a region
+// of an LDS hash table keyed by neighbour label). Longer rows are listed per
+// level: a wave per row with an LDS table up to 1023 arcs, a workgroup per
+// row with an LDS table up to 4096 arcs, and beyond that 4096-arc chunks
+// (label propagation's first iteration, emission) or label partitions of the
+// row, each summed in its own 128 KB LDS table (later LP iterations).
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
 #pragma unroll
       for (int u = 0; u < kLoadBatch; u++) {  // claims first, all in flight
         real[u] = i0 + u * G < end;
-        hs[u] = slot_hash(xs[u]) & mask;
+        hs[u] = (mul24_golden((uint32_t)xs[u] ^ ((uint32_t)xs[u] >> 16)) >> 8) & mask;
         old[u] = real[u] ? atomicCAS(&tkey[gi][hs[u]], -1, xs[u]) : -1;
       }
 #pragma unroll
@@ -586,20 +586,20 @@ __global__ void k_reduce_parts(const unsigned long long *part, int32_t count, St
   }
 }
 
-// Iteration t >= 2 on a tile. Thread l takes the q = ceil(arcs / 64)
-// consecutive arcs [l*q, l*q + q) of the tile (q <= 8, and q <= 4 on tiles
-// of short rows, which get their own instantiation), so the arcs of a row
-// sit in one thread or a few. Loads use clamped indices instead of branches,
-// so all arc loads, and then all label gathers, are in flight together. The
-// row of each arc comes from a prefix maximum over row-start marks (s_row).
-// Row j owns the hash region [2*s_rp[j], 2*s_rp[j+1]) of the tile's LDS
-// table (twice its arc count, so probing always ends), keyed by neighbour
-// label and summing weights. Runs of equal (row, label) within a thread are
-// folded first; the claims of a thread are all issued before any result is
-// used. Each run then adds its weight with a returning atomic, and the
-// candidate keys (sum, -prio) of a thread's runs are folded per row piece
-// into one maximum update per piece, so no pass over the table is needed.
-// Lanes without work aim their LDS operations at per-lane sink entries.
+// Iteration t >= 2 on a tile. Lane l takes the tile's arcs [NQ l, NQ l + NQ)
+// (NQ = 4 on tiles of at most 256 arcs, 8 on the others), so the arcs of a
+// row sit in one lane or a few. Loads use clamped indices instead of
+// branches, so all arc loads, and then all label gathers, are in flight
+// together. The row data stays in registers (lane j: row j's first arc; the
+// next lane's register gives its end), and the row of each arc comes from a
+// running maximum over row-start marks (lane_rows). Row j owns the hash
+// region [2 first_j, 2 end_j) of the tile's LDS table (twice its arc count,
+// so probing always ends), keyed by neighbour label and summing weights.
+// Runs of adjacent arcs of equal (row, label) within a lane are folded
+// first; the claims of a lane are all issued before any result is used.
+// Each run then adds its weight with a returning atomic, and the candidate
+// keys (sum, own, -prio) of a lane's runs are folded per row piece into one
+// maximum update per piece, so no pass over the table is needed.
 // Inclusive maximum over lanes 0..lane of the wave, in DPP moves: shifts
 // by 1, 2, 4 and 8 within the 16-lane rows, then the broadcasts of lane 15
 // (to rows 1 and 3) and lane 31 (to rows 2 and 3). Lanes without a source
@@ -614,24 +614,6 @@ __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
   return x;
 }
 
-__device__ __forceinline__ void tile_rows_prefix_max(unsigned long long *s_row8) {
-  static_assert(kTileArcs / 8 == kTB, "one 8-byte word of marks per lane");
-  const int lane = threadIdx.x;
-  const unsigned long long v = s_row8[lane];
-  uint32_t b[8], run = 0;
-#pragma unroll
-  for (int k = 0; k < 8; k++) {
-    run = max(run, (uint32_t)(v >> (8 * k)) & 0xFFu);
-    b[k] = run;
-  }
-  // the maximum over the lanes before this one: inclusive scan moved up one lane
-  const uint32_t carry =
-      (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wave_incl_max(run), 0x138, 0xF, 0xF, false);  // wave_shr:1
-  unsigned long long out = 0;
-#pragma unroll
-  for (int k = 0; k < 8; k++) out |= (unsigned long long)max(b[k], carry) << (8 * k);
-  s_row8[lane] = out;
-}
 
 // Row-start marks of a tile's arcs: one byte per arc, lane l's NQ arcs in
 // its own word.

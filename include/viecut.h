@@ -329,7 +329,7 @@ int viecut_profile_read(viecut_kernel_stat *out, int32_t max);
  * element (compact_direct_max), the union tile count from which batched PR
  * marking of short rows merges rows from global memory (pr_merge_tiles), the
  * row length splitting the 1024- and 2048-slot long-row LP classes
- * (long_split, 256..512), the long-row emission variant (emit_wave, 0/1),
+ * (long_split, 256..768), the long-row emission variant (emit_wave, 0/1),
  * and the tiles of at most 256 arcs that one label-propagation workgroup
  * takes (lp_group, 1..4) and one emission workgroup takes (emit_group, 1..2),
  * and the launch shape of label-propagation iteration 1 (first_group: 1 = a

@@ -38,7 +38,7 @@ CANDIDATES = {
     "radix_large_from": [1 << 18, 1 << 20, 1 << 22, 1 << 24, 1 << 30],
     "compact_direct_max": [1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 30],
     "pr_merge_tiles": [1 << 12, 1 << 14, 1 << 16, 1 << 30],
-    "long_split": [256, 320, 384, 448, 512],
+    "long_split": [256, 320, 384, 448, 512, 640, 768],
     "emit_wave": [0, 1],
     "lp_group": [1, 2, 3, 4],
     "emit_group": [1, 2],

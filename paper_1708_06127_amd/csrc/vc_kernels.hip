@@ -329,7 +329,7 @@ __global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *m
       for (int64_t t = t_lo; t <= t_hi; t++) meta[t].x = (int32_t)v;
     }
     const int32_t d = v < n ? rp[v + 1] - rp[v] : 0;
-    // classes 4 and 5 split at long_split (<= 512) instead of degree_bin's 512
+    // classes 4 and 5 split at long_split (256..768) instead of degree_bin's 512
     const int cls = d < kTile ? -1 : d < long_split ? 0 : d < 1024 ? 1 : degree_bin(d) - 4;
     const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
     __syncthreads();

@@ -56,7 +56,8 @@ const char *kKeys[] = {"radix_large_from", "compact_direct_max", "pr_merge_tiles
                        "lp_group", "emit_group", "first_group", "huge_part"};
 
 bool valid(const char *key, int64_t v) {
-  if (!std::strcmp(key, "long_split")) return v >= kTile && v <= 512;  // the 1024-slot class holds d < 512
+  // the 1024-slot class holds rows of d < long_split arcs: at most 3/4 full
+  if (!std::strcmp(key, "long_split")) return v >= kTile && v <= 768;
   if (!std::strcmp(key, "emit_wave")) return v == 0 || v == 1;
   if (!std::strcmp(key, "lp_group")) return v >= 1 && v <= 4;
   if (!std::strcmp(key, "emit_group")) return v == 1 || v == 2;

@@ -117,7 +117,7 @@ def test_tuning_table_on_host(tmp_path):
     lines = [l for l in text.splitlines() if l.startswith("bucket")]
     assert [int(l.split()[1]) for l in lines] == [1 << 20, 1 << 26, -1]
     assert "long_split=384" in lines[1] and "radix_large_from=16777216" in lines[2] and "emit_wave=0" in lines[0]
-    for key, bad in [("long_split", 600), ("long_split", 100), ("emit_wave", 2), ("lp_group", 0), ("lp_group", 5),
+    for key, bad in [("long_split", 800), ("long_split", 100), ("emit_wave", 2), ("lp_group", 0), ("lp_group", 5),
                      ("emit_group", 0), ("emit_group", 3), ("first_group", 0), ("huge_part", 2),
                      ("nonsense", 1)]:
         with pytest.raises(vc.ViecutError):

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 EXTREMES = [
     {"radix_large_from": 0, "compact_direct_max": 0, "pr_merge_tiles": 0, "long_split": 256, "emit_wave": 0,
      "lp_group": 1, "emit_group": 1, "first_group": 2, "huge_part": 0},
-    {"radix_large_from": 1 << 40, "compact_direct_max": 1 << 40, "pr_merge_tiles": 1 << 40, "long_split": 384,
+    {"radix_large_from": 1 << 40, "compact_direct_max": 1 << 40, "pr_merge_tiles": 1 << 40, "long_split": 768,
      "emit_wave": 1, "lp_group": 3, "emit_group": 2, "first_group": 1},
     {"lp_group": 4},
 ]

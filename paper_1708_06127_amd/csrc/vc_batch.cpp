@@ -584,9 +584,9 @@ struct Engine {
     release.swap(zombie_slots);
     VC_TRY(relabel(L, G.n, w, s, &bv, gvb[gvc ^ 1]));
     free_slots.insert(free_slots.end(), release.begin(), release.end());
-    VC_TRY(b_gsizes(gs, cap.s, w.ids, mode, s));
+    VC_TRY(b_gsizes(gs, cap.s, w.ids, mode, w.st, s));
     VC_TRY(b_compose(w.map, w.cl, 64ll * cap.w, wg, gs, s));
-    VC_TRY(contract_emit(G, w, known, s));
+    VC_TRY(contract_emit(G, w, known, s, &bv));
     int rc = sync_status();
     if (rc) return rc;
     rc = drain();
@@ -600,11 +600,12 @@ struct Engine {
       tiles_valid = false;
       return VIECUT_OK;
     }
-    const int kb = bits_for_host(K);
+    // keys: (new vertex) << lb | (neighbour minus its graph's first new vertex)
+    const int kb = bits_for_host(K), lb = bits_for_host(hst()->kloc);
     int which = 1;
-    VC_TRY(radix_sort(w, ax, 2 * kb, which, s));
+    VC_TRY(radix_sort(w, ax, kb + lb, which, s));
     const int dst = cur ^ 1;
-    VC_TRY(contract_build(w, which, ax, kb, K, dst, 0, s, false));
+    VC_TRY(contract_build(w, which, ax, lb, K, dst, 0, s, false, gvb[gvc ^ 1], gs));
     gvc ^= 1;
     cur = dst;
     VC_TRY(b_gdeg(w.deg, 0, K, gvb[gvc], gs, false, s));

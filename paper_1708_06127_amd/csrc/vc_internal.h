@@ -79,6 +79,8 @@ struct Status {
   int32_t huge_ticket;         // next work item of the huge-row label partitions
   int32_t huge_overflow;       // a huge-row label partition of pass 1 overflowed (its row runs again)
   int32_t huge_fallback;       // a pass-2 partition filled its table (the global-table path runs)
+  int32_t kloc;                // (batched) largest vertex count of one graph at the level being built
+  int32_t pad2;
 };
 
 // Kernel graphs of at most this many vertices are solved on the device (dense
@@ -264,12 +266,16 @@ hipError_t restrict_first(const DGraph &g, Work &w, int32_t *L, hipStream_t s);
 hipError_t count_changed(const int32_t *prev, const int32_t *cur, int32_t n, Work &w, hipStream_t s);
 hipError_t init_map(Work &w, hipStream_t s);
 // contraction: inter-cluster triples packed into buffer 1 (count -> st->ax, key bits from st->k)
-hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s);
+hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s,
+                         const BatchView *bv = nullptr);
 // sorts the `count` triples held in buffer `which` (in/out: the buffer holding the result)
 hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStream_t s);
 // sorted triples -> CSR buffer `dst` with k rows, degrees, bound update at `level`, witness
+// key_bits: width of the keys' low part; gv_new / gs (batched): the low part
+// is the neighbour relative to the first vertex of its graph at the new level
 hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
-                          hipStream_t s, bool single_bound = true);
+                          hipStream_t s, bool single_bound = true, const int32_t *gv_new = nullptr,
+                          const GStat *gs = nullptr);
 hipError_t bound_level0(Work &w, hipStream_t s);
 // PR marks on the v < x arcs (st->nmarked != 0 iff some edge was marked)
 hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv = nullptr);
@@ -296,7 +302,7 @@ hipError_t b_gbound0(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t 
 hipError_t b_step_top(GStat *gs, int32_t slots, int32_t n0, int32_t max_rounds, Status *st, GStat *ring,
                       int32_t ring_cap, hipStream_t s);
 hipError_t b_step_end(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t ring_cap, hipStream_t s);
-hipError_t b_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, hipStream_t s);
+hipError_t b_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, Status *st, hipStream_t s);
 hipError_t b_gbound(GStat *gs, int32_t slots, const int32_t *rp, int32_t buf, Status *st, GStat *ring,
                     int32_t ring_cap, hipStream_t s);
 hipError_t b_gwitness(const int32_t *map, const int32_t *wg, const GStat *gs, int32_t words,

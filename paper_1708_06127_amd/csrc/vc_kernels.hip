@@ -1975,8 +1975,8 @@ __global__ void k_iota(int32_t *p, int32_t n) {
 // pairs written. A scan over the counts and k_compact then pack the segments.
 __device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus, const int32_t *cs, int q,
                                            int32_t i0, int32_t acnt, const int32_t *s_rp, int32_t rows,
-                                           const int32_t *s_cl, int32_t cl_row, int key_bits, int64_t out0,
-                                           unsigned long long *keys, int32_t *vals, int32_t *sh,
+                                           const int32_t *s_cl, int32_t cl_row, int32_t cl_base, int key_bits,
+                                           int64_t out0, unsigned long long *keys, int32_t *vals, int32_t *sh,
                                            int32_t &total) {
   unsigned long long k[kPerThread];
   uint32_t fl = 0;
@@ -1991,7 +1991,7 @@ __device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus
           while (i >= s_rp[j + 1]) j++;
         const int32_t cv = s_rp ? s_cl[j] : cl_row;
         if (cus[m] != cv) {
-          k[m] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cus[m];
+          k[m] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)(cus[m] - cl_base);
           fl |= 1u << m;
         }
       }
@@ -2016,10 +2016,21 @@ __device__ __forceinline__ void emit_chunk(const int32_t *xs, const int32_t *cus
 // together; rows from the prefix maximum of row-start marks; runs of equal
 // pairs folded in registers; all claims issued before any result is used.
 // The occupied slots are then written in slot order, 64 at a time.
+// Emission keys: (cluster of the row) << lo | low, where low is the
+// neighbour's cluster minus the first cluster of the row's graph in a batch
+// union (its clusters are contiguous and both ends lie in one graph, so lo =
+// bits of the largest graph's cluster count), or the neighbour's cluster
+// itself in a single solve (lo = bits of the cluster count).
+__device__ __forceinline__ int emit_lo_bits(const Status *st, const int32_t *gv) {
+  return bits_for(gv ? st->kloc : st->k);
+}
+
 constexpr int kCombSlots = kTileArcs;  // > arcs of a tile, so probing ends
 constexpr unsigned long long kNoPair = ~0ull;
+template <bool B>
 struct alignas(16) EmitTileShared {
   int32_t rcl[kTile];                  // cluster of each row
+  int32_t rbase[B ? kTile : 1];        // (batched) first cluster of the row's graph
   unsigned long long tkey[kCombSlots];
   uint32_t tval[kCombSlots];
   unsigned long long mark[kTB];        // row-start marks, NQ bytes per lane
@@ -2030,18 +2041,20 @@ struct alignas(16) EmitTileShared {
 // 64 rows (only entries below the row count are loaded). Weights are loaded
 // later, for the arcs between clusters only (a few percent of the arcs after
 // label propagation).
-template <int NQ>
+template <bool B, int NQ>
 struct EmitFetch {
   int4 m;
   int32_t cus[NQ];
   int32_t rpv[kRowRegs + 1];
   int32_t clv[kRowRegs];
+  int32_t basev[B ? kRowRegs : 1];
 };
 
-template <int NQ>
-__device__ __forceinline__ void emit_fetch_loads(EmitFetch<NQ> &f, int4 m, const int32_t *__restrict__ rp,
+template <bool B, int NQ>
+__device__ __forceinline__ void emit_fetch_loads(EmitFetch<B, NQ> &f, int4 m, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ col, const int32_t *__restrict__ w,
-                                                 const int32_t *__restrict__ cl) {
+                                                 const int32_t *__restrict__ cl, const int32_t *__restrict__ gv,
+                                                 const GStat *gs) {
   const int lane = threadIdx.x;
   f.m = m;
   const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
@@ -2059,11 +2072,16 @@ __device__ __forceinline__ void emit_fetch_loads(EmitFetch<NQ> &f, int4 m, const
 #pragma unroll
   for (int r = 0; r < kRowRegs; r++) {
     f.clv[r] = 0;
-    if (rows > 0 && (r == 0 || kTB * r < rows)) f.clv[r] = at32(cl + r0, (uint32_t)min(lane + kTB * r, rows - 1));
+    if constexpr (B) f.basev[r] = 0;
+    if (rows > 0 && (r == 0 || kTB * r < rows)) {
+      const uint32_t j = (uint32_t)min(lane + kTB * r, rows - 1);
+      f.clv[r] = at32(cl + r0, j);
+      if constexpr (B) f.basev[r] = gs[at32(gv + r0, j)].base;
+    }
   }
 }
-template <int NQ>
-__device__ __forceinline__ void emit_fetch_gather(EmitFetch<NQ> &f, const int32_t *__restrict__ cl) {
+template <bool B, int NQ>
+__device__ __forceinline__ void emit_fetch_gather(EmitFetch<B, NQ> &f, const int32_t *__restrict__ cl) {
   if (f.m.w > 0) {
 #pragma unroll
     for (int k = 0; k < NQ; k++) f.cus[k] = at32(cl, (uint32_t)f.cus[k]);
@@ -2075,11 +2093,11 @@ __device__ __forceinline__ void emit_fetch_gather(EmitFetch<NQ> &f, const int32_
 // an LDS table sized for the tile's inter-cluster arcs (twice their count,
 // a power of two), and written in slot order into the tile's arc range.
 // Tiles with no such arc write an empty segment and skip the table.
-template <int NQ>
-__device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, const int32_t *__restrict__ w, int32_t t,
+template <bool B, int NQ>
+__device__ __forceinline__ void emit_tile_run(const EmitFetch<B, NQ> &f, const int32_t *__restrict__ w, int32_t t,
                                               int key_bits, unsigned long long *__restrict__ keys,
                                               int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                              int32_t *__restrict__ cnt, EmitTileShared &sh) {
+                                              int32_t *__restrict__ cnt, EmitTileShared<B> &sh) {
   using MW = typename MarkWord<NQ>::T;
   const int lane = threadIdx.x;
   const int32_t rows = f.m.y, a0 = f.m.z, acnt = f.m.w;
@@ -2094,6 +2112,7 @@ __device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, const int3
     const int32_t hi = __builtin_amdgcn_update_dpp(nxt, f.rpv[r], 0x130, 0xF, 0xF, false);  // wave_shl:1
     if (j < rows) {
       sh.rcl[j] = f.clv[r];
+      if constexpr (B) sh.rbase[j] = f.basev[r];
       if (hi > f.rpv[r]) s_mark[f.rpv[r] - a0] = (uint8_t)j;
     }
   }
@@ -2106,8 +2125,10 @@ __device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, const int3
 #pragma unroll
   for (int k = 0; k < NQ; k++) {
     const int32_t cv = sh.rcl[rw[k]];
+    int32_t cb = 0;
+    if constexpr (B) cb = sh.rbase[rw[k]];
     ok[k] = NQ * lane + k < acnt && f.cus[k] != cv;
-    key[k] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)f.cus[k];
+    key[k] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)(f.cus[k] - cb);
   }
 #pragma unroll
   for (int k = 0; k < NQ; k++) cc[k] = ok[k] ? (uint32_t)at32(w + a0, (uint32_t)(NQ * lane + k)) : 0u;
@@ -2178,15 +2199,16 @@ __device__ __forceinline__ void emit_tile_run(const EmitFetch<NQ> &f, const int3
 // Tiles of at most 256 arcs, TP consecutive tiles per workgroup (one wave):
 // the loads and cluster gathers of all of them are issued before any is
 // processed. Tiles of more than 256 arcs are left to k_emit_tile_big.
-template <int TP>
+template <bool B, int TP>
 __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
                                                        const int4 *__restrict__ meta, int32_t ntiles,
                                                        const Status *st, unsigned long long *__restrict__ keys,
                                                        int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                                       int32_t *__restrict__ cnt) {
-  __shared__ EmitTileShared sh;
-  const int key_bits = bits_for(st->k);
+                                                       int32_t *__restrict__ cnt, const int32_t *__restrict__ gv,
+                                                       const GStat *gs) {
+  __shared__ EmitTileShared<B> sh;
+  const int key_bits = emit_lo_bits(st, gv);
   const int32_t groups = (ntiles + TP - 1) / TP;
   for (int32_t g = blockIdx.x; g < groups; g += gridDim.x) {
     int4 m[TP];
@@ -2198,20 +2220,21 @@ __global__ __launch_bounds__(kTB) void k_emit_tile(const int32_t *__restrict__ r
       use[u] = t < ntiles && m[u].w <= 4 * kTB;
       if (!use[u]) m[u] = make_int4(m[u].x, 0, 0, 0);
     }
-    EmitFetch<4> f[TP];
+    EmitFetch<B, 4> f[TP];
 #pragma unroll
-    for (int u = 0; u < TP; u++) emit_fetch_loads(f[u], m[u], rp, col, w, cl);
+    for (int u = 0; u < TP; u++) emit_fetch_loads(f[u], m[u], rp, col, w, cl, gv, gs);
 #pragma unroll
     for (int u = 0; u < TP; u++) emit_fetch_gather(f[u], cl);
 #pragma unroll
     for (int u = 0; u < TP; u++)
-      if (use[u]) emit_tile_run<4>(f[u], w, g * TP + u, key_bits, keys, vals, first, cnt, sh);
+      if (use[u]) emit_tile_run<B, 4>(f[u], w, g * TP + u, key_bits, keys, vals, first, cnt, sh);
   }
 }
 
 // The listed tiles of more than 256 arcs, 8 arcs per lane. Persistent (as
 // many workgroups as fit, striding over the list), with the next tile's
 // loads and gathers issued before this tile's LDS phases.
+template <bool B>
 __global__ __launch_bounds__(kTB) void k_emit_tile_big(const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ col,
                                                            const int32_t *__restrict__ w,
@@ -2220,25 +2243,26 @@ __global__ __launch_bounds__(kTB) void k_emit_tile_big(const int32_t *__restrict
                                                            const int32_t *__restrict__ big, const Status *st,
                                                            unsigned long long *__restrict__ keys,
                                                            int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                                           int32_t *__restrict__ cnt) {
-  __shared__ EmitTileShared sh;
-  const int key_bits = bits_for(st->k);
+                                                           int32_t *__restrict__ cnt, const int32_t *__restrict__ gv,
+                                                           const GStat *gs) {
+  __shared__ EmitTileShared<B> sh;
+  const int key_bits = emit_lo_bits(st, gv);
   const int32_t nb = st->big_tiles;
   int32_t i = (int32_t)blockIdx.x;
   if (i >= nb) return;
   int32_t t = big[i];
-  EmitFetch<kPerThread> cur;
-  emit_fetch_loads(cur, meta[t], rp, col, w, cl);
+  EmitFetch<B, kPerThread> cur;
+  emit_fetch_loads(cur, meta[t], rp, col, w, cl, gv, gs);
   emit_fetch_gather(cur, cl);
   while (true) {
     const int32_t in = i + (int32_t)gridDim.x;
     const int32_t tn = in < nb ? big[in] : 0;
-    EmitFetch<kPerThread> nxt;
+    EmitFetch<B, kPerThread> nxt;
     if (in < nb) {
-      emit_fetch_loads(nxt, meta[tn], rp, col, w, cl);
+      emit_fetch_loads(nxt, meta[tn], rp, col, w, cl, gv, gs);
       emit_fetch_gather(nxt, cl);
     }
-    emit_tile_run<kPerThread>(cur, w, t, key_bits, keys, vals, first, cnt, sh);
+    emit_tile_run<B, kPerThread>(cur, w, t, key_bits, keys, vals, first, cnt, sh);
     if (in >= nb) break;
     i = in;
     t = tn;
@@ -2267,15 +2291,17 @@ __global__ __launch_bounds__(kBlock) void k_emit_wave(const int32_t *__restrict_
                                                        const int32_t *list, const int32_t *cnt_p, const Status *st,
                                                        unsigned long long *__restrict__ keys,
                                                        int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                                       int32_t *__restrict__ seg_cnt) {
+                                                       int32_t *__restrict__ seg_cnt, const int32_t *__restrict__ gv,
+                                                       const GStat *gs) {
   constexpr int kPer = 8;
-  const int key_bits = bits_for(st->k);
+  const int key_bits = emit_lo_bits(st, gv);
   const int32_t cnt = *cnt_p;
   const int lane = threadIdx.x & 63;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; r < cnt; r += nwaves) {
     const int32_t v0 = list[r];
     const int32_t cv = cl[v0];
+    const int32_t cb = gv ? gs[gv[v0]].base : 0;
     const int32_t beg = rp[v0], end = rp[v0 + 1];
     int64_t out = beg;
     for (int32_t c0 = beg; c0 < end; c0 += 64 * kPer) {
@@ -2298,7 +2324,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_wave(const int32_t *__restrict_
 #pragma unroll
       for (int k = 0; k < kPer; k++)
         if (fl & (1u << k)) {
-          keys[out + off + o] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)cus[k];
+          keys[out + off + o] = ((unsigned long long)(uint32_t)cv << key_bits) | (uint32_t)(cus[k] - cb);
           vals[out + off + o] = cs[k];
           o++;
         }
@@ -2317,13 +2343,15 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
                                                        const int32_t *list, const int32_t *cnt_p, const Status *st,
                                                        unsigned long long *__restrict__ keys,
                                                        int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                                       int32_t *__restrict__ seg_cnt) {
+                                                       int32_t *__restrict__ seg_cnt, const int32_t *__restrict__ gv,
+                                                       const GStat *gs) {
   __shared__ int32_t sh[kBlock / 64];
-  const int key_bits = bits_for(st->k);
+  const int key_bits = emit_lo_bits(st, gv);
   const int32_t cnt = *cnt_p;
   for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
     const int32_t v0 = list[r];
     const int32_t cv = cl[v0];
+    const int32_t cb = gv ? gs[gv[v0]].base : 0;
     const int32_t beg = rp[v0], end = rp[v0 + 1];
     int64_t out = beg;
     for (int32_t c0 = beg; c0 < end; c0 += kBlock * kPerThread) {
@@ -2339,7 +2367,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_long(const int32_t *__restrict_
 #pragma unroll
       for (int k = 0; k < kPerThread; k++) cus[k] = cl[cus[k]];
       int32_t tot;
-      emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, key_bits, out, keys, vals, sh, tot);
+      emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, cb, key_bits, out, keys, vals, sh, tot);
       out += tot;
       __syncthreads();
     }
@@ -2358,15 +2386,17 @@ __global__ __launch_bounds__(kBlock) void k_emit_huge(const int32_t *__restrict_
                                                        const int32_t *list, const int32_t *cnt_p, const int32_t *meta,
                                                        const Status *st, unsigned long long *__restrict__ keys,
                                                        int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                                       int32_t *__restrict__ seg_cnt) {
+                                                       int32_t *__restrict__ seg_cnt, const int32_t *__restrict__ gv,
+                                                       const GStat *gs) {
   __shared__ int32_t sh[kBlock / 64];
-  const int key_bits = bits_for(st->k);
+  const int key_bits = emit_lo_bits(st, gv);
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
   for (int32_t p = blockIdx.x; p < items; p += gridDim.x) {
     const int32_t i = huge_find(meta, cnt, p, 0);
     const int32_t v0 = list[i];
     const int32_t cv = cl[v0];
+    const int32_t cb = gv ? gs[gv[v0]].base : 0;
     const int32_t beg = rp[v0] + (p - meta[3 * (int64_t)i]) * kHugeChunk;
     const int32_t end = min(rp[v0 + 1], beg + kHugeChunk);
     int64_t out = beg;
@@ -2383,7 +2413,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_huge(const int32_t *__restrict_
 #pragma unroll
       for (int k = 0; k < kPerThread; k++) cus[k] = cl[cus[k]];
       int32_t tot;
-      emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, key_bits, out, keys, vals, sh, tot);
+      emit_chunk(cus, cus, cs, kPerThread, i0, acnt, nullptr, 0, nullptr, cv, cb, key_bits, out, keys, vals, sh, tot);
       out += tot;
       __syncthreads();
     }
@@ -2661,7 +2691,7 @@ __global__ void k_seg_heads(const unsigned long long *keys, int64_t count, int32
 // are few and rarely on the same address.
 __global__ void k_seg_write(const unsigned long long *keys, const int32_t *vals, int64_t count, const int32_t *seg,
                             const int32_t *head, int key_bits, int32_t *colo, int32_t *wo, int32_t *rowcnt,
-                            unsigned long long *degu) {
+                            unsigned long long *degu, const int32_t *__restrict__ gv_new, const GStat *gs) {
   const int lane = threadIdx.x & 63;
   const unsigned long long mask_lo = (1ull << key_bits) - 1;
   for (int64_t base = blockIdx.x * (int64_t)kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
@@ -2680,7 +2710,10 @@ __global__ void k_seg_write(const unsigned long long *keys, const int32_t *vals,
     const int32_t s_next = __shfl_down(s, 1, 64);
     const bool last = (lane == 63) || (s_next != s);
     if (ok && last) atomicAdd((uint32_t *)&wo[s], (uint32_t)x);
-    if (ok && h) colo[s] = (int32_t)(k & mask_lo);
+    if (ok && h) {  // batched keys hold the neighbour relative to its graph's first vertex
+      const int32_t lo = (int32_t)(k & mask_lo);
+      colo[s] = gv_new ? lo + gs[gv_new[(int64_t)(k >> key_bits)]].base : lo;
+    }
     // per row piece: degree (sum of the segment pieces) and new columns (heads)
     const long long row = ok ? (long long)(k >> key_bits) : -1;
     unsigned long long dsum = (ok && last) ? x : 0;
@@ -3762,13 +3795,14 @@ __global__ void k_step_end(GStat *gs, int32_t slots, Status *st, GStat *ring, in
 // after the relabelling scan: each graph's vertex range at the new level
 // (mode 0: cluster contraction, every graph in the loop is contracted; mode
 // 1: marked-edge contraction, only graphs with a marked edge are)
-__global__ void k_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode) {
+__global__ void k_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, Status *st) {
   for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < slots; i += gridDim.x * kBlock) {
     GStat &g = gs[i];
     if (g.state != GS_ACTIVE) continue;
     const int32_t nb = ids[g.base];
     g.k = ids[g.base + g.k] - nb;
     g.base = nb;
+    atomicMax(&st->kloc, g.k);  // (the emission keys' low part holds a graph-local vertex)
     g.minkey = ~0ull;
     g.contracted = mode == 0 ? 1 : (g.nmarked != 0);
   }
@@ -4262,25 +4296,35 @@ hipError_t init_map(Work &w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s) {
+namespace {
+template <bool B>
+void launch_emit_tiles(const DGraph &g, Work &w, const int32_t *gv, const GStat *gs, hipStream_t s) {
+  const int tp = (int)tuning_for(g.nnz).emit_group;
+  const unsigned grid = grid_for((w.ntiles + tp - 1) / tp, 1, 1u << 20);
+  if (tp == 2)
+    k_emit_tile<B, 2><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles, w.st, w.keys[0],
+                                           w.vals[0], w.seg, w.seg_cnt, gv, gs);
+  else
+    k_emit_tile<B, 1><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles, w.st, w.keys[0],
+                                           w.vals[0], w.seg, w.seg_cnt, gv, gs);
+  k_emit_tile_big<B><<<resident_grid(k_emit_tile_big<B>, kTB, w.ntiles), kTB, 0, s>>>(
+      g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.big_tiles, w.st, w.keys[0], w.vals[0], w.seg, w.seg_cnt, gv, gs);
+}
+}  // namespace
+
+hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv) {
+  const int32_t *gv = bv ? bv->gv : nullptr;
+  const GStat *gs = bv ? bv->gs : nullptr;
   const int64_t long_max = g.nnz / kTile + 1;
   constexpr int kLong = kBins - 4;  // one region of long_max segments per long class
   const int64_t nseg = w.ntiles + kLong * long_max;
   // long-row segments beyond the device-side row counts stay empty
   hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, kLong * long_max, s);
   if (e != hipSuccess) return e;
-  {
-    const int tp = (int)tuning_for(g.nnz).emit_group;
-    const unsigned grid = grid_for((w.ntiles + tp - 1) / tp, 1, 1u << 20);
-    if (tp == 2)
-      k_emit_tile<2><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles, w.st, w.keys[0],
-                                          w.vals[0], w.seg, w.seg_cnt);
-    else
-      k_emit_tile<1><<<grid, kTB, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.ntiles, w.st, w.keys[0],
-                                          w.vals[0], w.seg, w.seg_cnt);
-    k_emit_tile_big<<<resident_grid(k_emit_tile_big, kTB, w.ntiles), kTB, 0, s>>>(
-        g.row_ptr, g.col, g.w, w.cl, w.tile_meta, w.big_tiles, w.st, w.keys[0], w.vals[0], w.seg, w.seg_cnt);
-  }
+  if (bv)
+    launch_emit_tiles<true>(g, w, gv, gs, s);
+  else
+    launch_emit_tiles<false>(g, w, nullptr, nullptr, s);
   for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;
@@ -4288,11 +4332,12 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
     if (b < 6 && tuning_for(g.nnz).emit_wave)  // rows of fewer than 1024 arcs: a wave per row
       k_emit_wave<<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(
           g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0],
-          w.seg + s0, w.seg_cnt + s0);
+          w.seg + s0, w.seg_cnt + s0, gv, gs);
     else
       k_emit_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl,
                                                               w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st,
-                                                              w.keys[0], w.vals[0], w.seg + s0, w.seg_cnt + s0);
+                                                              w.keys[0], w.vals[0], w.seg + s0, w.seg_cnt + s0, gv,
+                                                              gs);
   }
   if (bin_items(known, kBinHuge, 1) > 0) {
     // chunks of the huge rows (at most long_max of them: one segment each)
@@ -4302,7 +4347,7 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
     k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st, nullptr);
     k_emit_huge<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, list6, cnt6,
                                                                       w.huge_meta, w.st, w.keys[0], w.vals[0],
-                                                                      w.seg + s0, w.seg_cnt + s0);
+                                                                      w.seg + s0, w.seg_cnt + s0, gv, gs);
   }
   e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
   if (e != hipSuccess) return e;
@@ -4339,7 +4384,7 @@ hipError_t radix_sort(Work &w, int64_t count, int total_bits, int &which, hipStr
 }
 
 hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32_t k, int dst, int32_t level,
-                          hipStream_t s, bool single_bound) {
+                          hipStream_t s, bool single_bound, const int32_t *gv_new, const GStat *gs) {
   int32_t *rowcnt = w.rp[dst];
   unsigned long long *degu = (unsigned long long *)w.deg;
   // free scratch while the sorted triples sit in buffer `which`
@@ -4353,7 +4398,7 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
     e = scan_exclusive(w, head, seg, count, &w.st->nnz, s);
     if (e != hipSuccess) return e;
     k_seg_write<<<grid_for(count), kBlock, 0, s>>>(w.keys[which], w.vals[which], count, seg, head, key_bits,
-                                                   w.col[dst], w.w[dst], rowcnt, degu);
+                                                   w.col[dst], w.w[dst], rowcnt, degu, gv_new, gs);
   } else {
     e = fill_i32(&w.st->nnz, 0, 1, s);
     if (e != hipSuccess) return e;
@@ -4530,8 +4575,10 @@ hipError_t b_step_end(GStat *gs, int32_t slots, Status *st, GStat *ring, int32_t
   return hipGetLastError();
 }
 
-hipError_t b_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, hipStream_t s) {
-  k_gsizes<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, ids, mode);
+hipError_t b_gsizes(GStat *gs, int32_t slots, const int32_t *ids, int mode, Status *st, hipStream_t s) {
+  const hipError_t e = fill_i32(&st->kloc, 0, 1, s);
+  if (e != hipSuccess) return e;
+  k_gsizes<<<grid_for(slots), kBlock, 0, s>>>(gs, slots, ids, mode, st);
   return hipGetLastError();
 }
 

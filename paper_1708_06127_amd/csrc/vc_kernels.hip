@@ -523,12 +523,17 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
         hs[u] = (mul24_golden((uint32_t)xs[u] ^ ((uint32_t)xs[u] >> 16)) >> 8) & mask;
         old[u] = real[u] ? atomicCAS(&tkey[gi][hs[u]], -1, xs[u]) : -1;
       }
+      bool coll = false;
 #pragma unroll
-      for (int u = 0; u < kLoadBatch; u++) {
-        if (!real[u]) continue;
-        while (old[u] != -1 && old[u] != xs[u]) {  // taken by another label: probe on
-          hs[u] = (hs[u] + 1) & mask;
-          old[u] = atomicCAS(&tkey[gi][hs[u]], -1, xs[u]);
+      for (int u = 0; u < kLoadBatch; u++) coll |= real[u] && old[u] != -1 && old[u] != xs[u];
+      if (__ballot(coll)) {  // (rare: one wave-wide test skips the probing code)
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; u++) {
+          if (!real[u]) continue;
+          while (old[u] != -1 && old[u] != xs[u]) {  // taken by another label: probe on
+            hs[u] = (hs[u] + 1) & mask;
+            old[u] = atomicCAS(&tkey[gi][hs[u]], -1, xs[u]);
+          }
         }
       }
 #pragma unroll
@@ -798,12 +803,19 @@ __device__ __forceinline__ void lp_tile_run(const LpFetch<B, NQ> &f, int32_t *__
       else
         old[k] = ok[k] ? atomicCAS(&sh.slot[hb[k] + (int32_t)hh[k]].x, ~0u, (uint32_t)f.xs[k]) : ~0u;
     }
+    // collisions are rare (the table is at most half full): one wave-wide
+    // test skips the probing code when no lane has one
+    bool coll = false;
 #pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      if (!ok[k]) continue;
-      while (old[k] != ~0u && old[k] != (uint32_t)f.xs[k]) {  // taken by another label
-        hh[k] = (hh[k] + 1 == (uint32_t)hsz[k]) ? 0 : hh[k] + 1;
-        old[k] = atomicCAS(&sh.slot[hb[k] + (int32_t)hh[k]].x, ~0u, (uint32_t)f.xs[k]);
+    for (int k = 0; k < NQ; k++) coll |= ok[k] && old[k] != ~0u && old[k] != (uint32_t)f.xs[k];
+    if (__ballot(coll)) {
+#pragma unroll
+      for (int k = 0; k < NQ; k++) {
+        if (!ok[k]) continue;
+        while (old[k] != ~0u && old[k] != (uint32_t)f.xs[k]) {  // taken by another label
+          hh[k] = (hh[k] + 1 == (uint32_t)hsz[k]) ? 0 : hh[k] + 1;
+          old[k] = atomicCAS(&sh.slot[hb[k] + (int32_t)hh[k]].x, ~0u, (uint32_t)f.xs[k]);
+        }
       }
     }
     // add the run weights: the returned partial sum plus the run's weight is
@@ -2162,12 +2174,17 @@ __device__ __forceinline__ void emit_tile_run(const EmitFetch<B, NQ> &f, const i
       hh[k] = (mul24_golden(fold ^ (fold >> 16)) >> 8) & msk;
       old[k] = ok[k] ? atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]) : kNoPair;
     }
+    bool coll = false;
 #pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      if (!ok[k]) continue;
-      while (old[k] != kNoPair && old[k] != key[k]) {  // taken by another pair
-        hh[k] = (hh[k] + 1) & msk;
-        old[k] = atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]);
+    for (int k = 0; k < NQ; k++) coll |= ok[k] && old[k] != kNoPair && old[k] != key[k];
+    if (__ballot(coll)) {  // (rare: one wave-wide test skips the probing code)
+#pragma unroll
+      for (int k = 0; k < NQ; k++) {
+        if (!ok[k]) continue;
+        while (old[k] != kNoPair && old[k] != key[k]) {  // taken by another pair
+          hh[k] = (hh[k] + 1) & msk;
+          old[k] = atomicCAS(&sh.tkey[hh[k]], kNoPair, key[k]);
+        }
       }
     }
 #pragma unroll

@@ -43,7 +43,7 @@ struct ProfState {
   bool on = false;
   std::vector<ProfRec> pending;
   std::vector<hipEvent_t> pool;
-  int32_t *slots = nullptr;  // 4 int32 per record: tile_rows, pad, tile_arcs (u64)
+  int32_t *slots = nullptr;  // 4 int32 per record: tile rows, big tiles, tile arcs (u64)
   int32_t *dslots = nullptr;  // the same memory's device address
   int32_t cap = 0;
   int64_t launches[PROF_KINDS] = {0};
@@ -202,7 +202,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t map_n, int64_t extra) {
   L.add(12 * (size_t)huge_rows);               // 27 huge meta
   L.add((size_t)n + 1);                        // 28 flags8
   L.add(16 * (size_t)ntiles);                  // 29 tile_meta
-  L.add(24 * (2 * (size_t)ntiles + 1));        // 30 part
+  L.add(24 * (2 * (size_t)ntiles + 1 + kLongParts));  // 30 part
   L.add(8 * (size_t)nseg);                     // 31 seg
   L.add(4 * (size_t)nseg + 4);                 // 32 seg_cnt
   L.add(4 * (size_t)ntiles);                   // 33 big_tiles

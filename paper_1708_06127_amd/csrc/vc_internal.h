@@ -19,6 +19,12 @@ constexpr size_t kScratchBytes = VIECUT_NOALLOC_SCRATCH_BYTES;
 constexpr int kMaxScratchDevices = 64;
 constexpr int kBins = 8;      // degree classes for per-vertex work
 constexpr int kHugeChunk = 4096;  // arcs per work item of a huge row
+// Largest grids of the per-row launches of the long classes and of the huge
+// rows' chunk kernel; the level-0 statistics of their workgroups take that
+// many entries of Work::part beyond the tile kernels' (kLongParts).
+constexpr unsigned kRowsGridMax = 8192;
+constexpr unsigned kHugeChunksGrid = 4096;
+constexpr int64_t kLongParts = 3 * (int64_t)kRowsGridMax + kHugeChunksGrid;
 constexpr int kPartSlots = 16384;  // LDS table slots of one huge-row label partition (128 KB)
 constexpr int kPartDistinct = 4;   // pass 1 plans room for d / kPartDistinct distinct labels of a huge row
 constexpr int kPartProbe = 64;     // pass 1: a longer probe run sends the row to pass 2
@@ -69,9 +75,9 @@ struct Status {
   int32_t bin_cnt[8];          // vertices per degree class
   int32_t ring_cnt;            // (batched) finished graphs pushed to the ring so far
   int32_t active_cnt;          // (batched) graphs still in the round loop
-  int32_t tile_rows;           // rows covered by the arc tiles of the current level
   int32_t big_tiles;           // tiles of more than 256 arcs (listed in Work::big_tiles)
-  unsigned long long tile_arcs;  // arcs covered by the arc tiles of the current level
+  int32_t pad1;
+  unsigned long long tile_tot;  // (rows << 32) | arcs covered by the arc tiles of the current level
   int32_t pr_rows[2];          // rows marked with an LDS table of their row (short / long tables)
   unsigned long long fix_delta;  // correcting step: minimum weighted degree of the contracted graph
   long long sw_cut;            // device exact solve: the kernel graph's minimum cut
@@ -323,8 +329,8 @@ struct ProfScope {
   int slot = -1;
   hipStream_t s;
   const Status *st;
-  // device address of the record's 16-byte snapshot of (tile_rows, big_tiles,
-  // tile_arcs) in page-locked host memory, or nullptr: the first launch of
+  // device address of the record's 16-byte snapshot of (tile rows, big
+  // tiles, tile arcs) in page-locked host memory, or nullptr: the first launch of
   // the scope writes it from one thread (no copy is queued)
   int32_t *dev = nullptr;
   ProfScope(ProfKind kind, hipStream_t stream, const Status *st, int32_t ntiles);

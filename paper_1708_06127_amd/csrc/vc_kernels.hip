@@ -226,8 +226,7 @@ __global__ void k_status_reset(Status *st) {
     st->huge_slots = 0;
     st->ring_cnt = 0;
     st->active_cnt = 0;
-    st->tile_rows = 0;
-    st->tile_arcs = 0;
+    st->tile_tot = 0;
     st->big_tiles = 0;
   }
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
@@ -254,46 +253,77 @@ __global__ void k_check_rowptr(const int32_t *rp, int32_t n, int64_t nnz, Status
 // writes every tile's first row into meta[t].x, with no search.
 // Tiles of more than 4 * 64 arcs (a long row closes them) are also listed in
 // `big`, in any order, for the LP kernel that runs them with 8 arcs per thread.
-__global__ void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st, int32_t *big) {
+// Device-scope atomics on one cache line are serialized (about 11 ns each on
+// this GPU), so a workgroup takes kTilesPer tiles per thread (all their loads
+// in flight together) and makes one reservation for its big tiles and one
+// 64-bit addition of its (rows, arcs) totals.
+constexpr int kTilesPer = 8;
+__global__ __launch_bounds__(kBlock) void k_tiles(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, Status *st,
+                                                   int32_t *big) {
   __shared__ unsigned long long sh[kBlock / 64];
-  __shared__ int32_t s_cnt, s_base;
+  __shared__ int32_t s_off[kBlock / 64][kTilesPer];
+  __shared__ int32_t s_base;
   if (st->err) return;  // k_row_pass built no first rows
-  const int lane = threadIdx.x & 63;
-  unsigned long long rows = 0, arcs = 0;
-  for (int64_t t0 = blockIdx.x * (int64_t)kBlock; t0 < ntiles; t0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t t = t0 + threadIdx.x;
-    bool is_big = false;
-    if (t < ntiles) {
-      // first rows from k_row_pass (this pass rewrites meta[t].x unchanged)
-      const int32_t r0 = meta[t].x;
-      int32_t r1 = t + 1 == ntiles ? n : meta[t + 1].x;
-      if (r1 > r0 && rp[r1] - rp[r1 - 1] >= kTile) r1--;
-      const int32_t acnt = rp[r1] - rp[r0];
-      meta[t] = make_int4(r0, r1 - r0, rp[r0], acnt);
-      rows += (unsigned long long)(r1 - r0);
-      arcs += (unsigned long long)acnt;
-      is_big = acnt > 4 * kTB;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int64_t kSpan = (int64_t)kBlock * kTilesPer;
+  unsigned long long tot = 0;  // (rows << 32) + arcs: the arcs of all tiles stay below 2^31
+  for (int64_t b0 = blockIdx.x * kSpan; b0 < ntiles; b0 += (int64_t)gridDim.x * kSpan) {
+    // first rows from k_row_pass (this pass rewrites meta[t].x unchanged)
+    int32_t r0[kTilesPer], r1[kTilesPer];
+#pragma unroll
+    for (int k = 0; k < kTilesPer; k++) {
+      const int64_t t = b0 + (int64_t)k * kBlock + threadIdx.x;
+      r0[k] = t < ntiles ? meta[t].x : 0;
+      r1[k] = t < ntiles ? (t + 1 == ntiles ? n : meta[t + 1].x) : 0;
     }
-    // big tiles: a wave count in LDS, then one global reservation per block
-    if (threadIdx.x == 0) s_cnt = 0;
+    int32_t a0[kTilesPer], a1[kTilesPer], am[kTilesPer];
+#pragma unroll
+    for (int k = 0; k < kTilesPer; k++) {  // row ids lie in [0, n]
+      a0[k] = rp[r0[k]];
+      a1[k] = rp[r1[k]];
+      am[k] = rp[max(r1[k] - 1, 0)];
+    }
+    unsigned long long bal[kTilesPer];
+#pragma unroll
+    for (int k = 0; k < kTilesPer; k++) {
+      const int64_t t = b0 + (int64_t)k * kBlock + threadIdx.x;
+      bool is_big = false;
+      if (t < ntiles) {
+        int32_t e = r1[k], ae = a1[k];
+        if (e > r0[k] && ae - am[k] >= kTile) {  // a trailing long row is left to the long-row kernels
+          e--;
+          ae = am[k];
+        }
+        const int32_t acnt = ae - a0[k];
+        meta[t] = make_int4(r0[k], e - r0[k], a0[k], acnt);
+        tot += ((unsigned long long)(uint32_t)(e - r0[k]) << 32) + (uint32_t)acnt;
+        is_big = acnt > 4 * kTB;
+      }
+      bal[k] = __ballot(is_big);
+      if (lane == 0) s_off[wid][k] = __popcll(bal[k]);
+    }
     __syncthreads();
-    const unsigned long long bal = __ballot(is_big);
-    int32_t wbase = 0;
-    if (lane == 0 && bal) wbase = atomicAdd(&s_cnt, (int32_t)__popcll(bal));
-    wbase = __shfl(wbase, 0, 64);
+    if (threadIdx.x == 0) {  // offsets of the (wave, k) groups, one global reservation
+      int32_t sum = 0;
+      for (int q = 0; q < kBlock / 64; q++)
+        for (int k = 0; k < kTilesPer; k++) {
+          const int32_t c = s_off[q][k];
+          s_off[q][k] = sum;
+          sum += c;
+        }
+      s_base = sum ? atomicAdd(&st->big_tiles, sum) : 0;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) s_base = s_cnt ? atomicAdd(&st->big_tiles, s_cnt) : 0;
-    __syncthreads();
-    if (is_big) big[s_base + wbase + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)t;
+#pragma unroll
+    for (int k = 0; k < kTilesPer; k++)
+      if ((bal[k] >> lane) & 1)
+        big[s_base + s_off[wid][k] + __popcll(bal[k] & ((1ull << lane) - 1))] =
+            (int32_t)(b0 + (int64_t)k * kBlock + threadIdx.x);
     __syncthreads();
   }
   // totals over the tiles (the algorithmic size of a tile sweep)
-  rows = block_sum(rows, sh);
-  arcs = block_sum(arcs, sh);
-  if (threadIdx.x == 0) {
-    if (rows) atomicAdd(&st->tile_rows, (int32_t)rows);
-    if (arcs) atomicAdd(&st->tile_arcs, arcs);
-  }
+  tot = block_sum(tot, sh);
+  if (threadIdx.x == 0 && tot) atomicAdd(&st->tile_tot, tot);
 }
 
 // largest j in [0, rows) with s_rp[j] <= i (the row holding local arc i)
@@ -306,37 +336,66 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int
   return lo;
 }
 
-// Lists of long rows (classes 4-6 of degree_bin), appended per workgroup:
-// LDS counters, then one global reservation per class and workgroup.
 // One pass over the rows of a level: the first row of every arc tile (into
 // meta[t].x, see above) and the lists of long rows (classes 4-7 of
 // degree_bin), appended per workgroup: LDS counters, then one global
-// reservation per class and workgroup.
-__global__ void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta, int64_t stride, int32_t *bins,
-                           Status *st, int32_t long_split) {
+// reservation per pair of classes and workgroup (a 64-bit addition on two
+// adjacent 32-bit counts: a class never holds 2^31 rows, so no carry crosses
+// into the other count). A workgroup of kRowBlock threads takes kRowsPer rows
+// per thread, which keeps the serialized reservations few.
+constexpr int kRowBlock = 1024;
+constexpr int kRowsPer = 8;
+static_assert(offsetof(Status, bin_cnt) % 8 == 0, "bin_cnt pairs are added as 64-bit words");
+__global__ __launch_bounds__(kRowBlock) void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta,
+                                                        int64_t stride, int32_t *bins, Status *st,
+                                                        int32_t long_split) {
   constexpr int kLong = kBins - 4;  // long classes 4 .. kBins - 1
+  static_assert(kLong == 4, "two pairs of long classes");
   __shared__ int32_t cnt[kLong], base[kLong];
   // an invalid row_ptr (flagged by k_check_rowptr, earlier on the stream)
   // could name tiles outside [0, ntiles): nothing is built from it
   if (st->err) return;
-  for (int64_t b0 = blockIdx.x * (int64_t)kBlock; b0 <= n; b0 += (int64_t)gridDim.x * kBlock) {
+  constexpr int64_t kSpan = (int64_t)kRowBlock * kRowsPer;
+  for (int64_t b0 = blockIdx.x * kSpan; b0 <= n; b0 += (int64_t)gridDim.x * kSpan) {
     if (threadIdx.x < kLong) cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t v = b0 + threadIdx.x;
-    if (v <= n) {
-      const int64_t t_lo = v == 0 ? 0 : ((int64_t)rp[v - 1] + v - 1) / kTile + 1;
-      const int64_t t_hi = min(((int64_t)rp[v] + v) / kTile, (int64_t)ntiles - 1);
-      for (int64_t t = t_lo; t <= t_hi; t++) meta[t].x = (int32_t)v;
+    int32_t lo[kRowsPer], mid[kRowsPer], hi[kRowsPer];
+#pragma unroll
+    for (int k = 0; k < kRowsPer; k++) {  // rp[v - 1], rp[v], rp[v + 1] where they exist
+      const int64_t v = b0 + (int64_t)k * kRowBlock + threadIdx.x;
+      lo[k] = v >= 1 && v <= n ? rp[v - 1] : 0;
+      mid[k] = v <= n ? rp[v] : 0;
+      hi[k] = v < n ? rp[v + 1] : 0;
     }
-    const int32_t d = v < n ? rp[v + 1] - rp[v] : 0;
-    // classes 4 and 5 split at long_split (256..768) instead of degree_bin's 512
-    const int cls = d < kTile ? -1 : d < long_split ? 0 : d < 1024 ? 1 : degree_bin(d) - 4;
-    const int pos = cls >= 0 ? atomicAdd(&cnt[cls], 1) : 0;
     __syncthreads();
-    if (threadIdx.x < kLong)
-      base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&st->bin_cnt[4 + threadIdx.x], cnt[threadIdx.x]) : 0;
+    int cls[kRowsPer], pos[kRowsPer];
+#pragma unroll
+    for (int k = 0; k < kRowsPer; k++) {
+      const int64_t v = b0 + (int64_t)k * kRowBlock + threadIdx.x;
+      if (v <= n) {
+        const int64_t t_lo = v == 0 ? 0 : ((int64_t)lo[k] + v - 1) / kTile + 1;
+        const int64_t t_hi = min(((int64_t)mid[k] + v) / kTile, (int64_t)ntiles - 1);
+        for (int64_t t = t_lo; t <= t_hi; t++) meta[t].x = (int32_t)v;
+      }
+      const int32_t d = v < n ? hi[k] - mid[k] : 0;
+      // classes 4 and 5 split at long_split (256..768) instead of degree_bin's 512
+      cls[k] = d < kTile ? -1 : d < long_split ? 0 : d < 1024 ? 1 : degree_bin(d) - 4;
+      pos[k] = cls[k] >= 0 ? atomicAdd(&cnt[cls[k]], 1) : 0;
+    }
     __syncthreads();
-    if (cls >= 0) bins[(int64_t)(4 + cls) * stride + base[cls] + pos] = (int32_t)v;
+    if (threadIdx.x < kLong / 2) {
+      const int c = 2 * threadIdx.x;
+      const unsigned long long add = (uint32_t)cnt[c] | ((unsigned long long)(uint32_t)cnt[c + 1] << 32);
+      const unsigned long long old =
+          add ? atomicAdd(reinterpret_cast<unsigned long long *>(&st->bin_cnt[4 + c]), add) : 0ull;
+      base[c] = (int32_t)(uint32_t)old;
+      base[c + 1] = (int32_t)(old >> 32);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRowsPer; k++) {
+      const int64_t v = b0 + (int64_t)k * kRowBlock + threadIdx.x;
+      if (cls[k] >= 0) bins[(int64_t)(4 + cls[k]) * stride + base[cls[k]] + pos[k]] = (int32_t)v;
+    }
     __syncthreads();
   }
 }
@@ -378,15 +437,31 @@ constexpr int kLoadBatch = 8;
 // Identity labels: S(x) = w(v, x), so the new label is the row's argmax of
 // (w, -prio). At level 0 the same pass validates the row and computes the
 // weighted degree and the minimum-degree key.
+// Level-0 statistics of one workgroup, (minimum-degree key, weight sum, error
+// bits), into its own entry of `part` (combined by k_reduce_parts): device
+// atomics on the status words from every workgroup would be serialized.
+__device__ __forceinline__ void part_write(unsigned long long *part, unsigned long long key, unsigned long long sum,
+                                           int err) {
+  unsigned long long *p = part + 3 * (int64_t)blockIdx.x;
+  p[0] = key;
+  p[1] = sum;
+  p[2] = (unsigned long long)(uint32_t)err;
+}
+
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                       const int32_t *__restrict__ w, int32_t n,
                                                       const int32_t *__restrict__ list, const int32_t *cnt_p,
                                                       int32_t *__restrict__ L, long long *__restrict__ deg,
                                                       uint32_t salt, int level0, Status *st,
-                                                      const int32_t *__restrict__ gv, GStat *gs) {
+                                                      const int32_t *__restrict__ gv, GStat *gs,
+                                                      unsigned long long *part) {
   __shared__ unsigned long long sh[kBlock / 64];
-  if (!gv && st->err) return;
+  const bool stats = level0 && !gv;  // the workgroup's (min-degree key, weight sum, errors) go to part
+  if (!gv && st->err) {
+    if (stats && threadIdx.x == 0) part_write(part, ~0ull, 0, 0);
+    return;
+  }
   constexpr int NG = kBlock / G;
   const int gi = threadIdx.x / G, lane = threadIdx.x % G;
   const int32_t cnt = *cnt_p;
@@ -445,15 +520,11 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
       }
     }
   }
-  if (level0 && !gv) {
+  if (stats) {
     unsigned long long k = block_min(mykey, sh);
     unsigned long long s = block_sum(mysum, sh);
     int e = (int)block_max((unsigned long long)myerr, sh);
-    if (threadIdx.x == 0) {
-      if (k != ~0ull) atomicMin(&st->minkey, k);
-      if (s) atomicAdd(&st->wsum, s);
-      if (e) atomicOr(&st->err, e);
-    }
+    if (threadIdx.x == 0) part_write(part, k, s, e);
   }
 }
 
@@ -554,14 +625,14 @@ __global__ __launch_bounds__(kBlock) void k_lp_tab(const int32_t *__restrict__ r
   }
 }
 
-// Kernel timing: one thread copies the level's tile totals (16 bytes from
-// tile_rows) into the timing record, a page-locked host buffer.
+// Kernel timing: one thread copies the level's tile totals into the timing
+// record, a page-locked host buffer, as (rows, big tiles, arcs: 64 bits).
 __device__ __forceinline__ void prof_snapshot(int32_t *prof, const Status *st) {
   if (prof && blockIdx.x == 0 && threadIdx.x == 0) {
-    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(&st->tile_rows);
+    const unsigned long long t = st->tile_tot;
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(prof);
-    dst[0] = src[0];
-    dst[1] = src[1];
+    dst[0] = (t >> 32) | ((unsigned long long)(uint32_t)st->big_tiles << 32);
+    dst[1] = t & 0xFFFFFFFFull;
   }
 }
 
@@ -1329,14 +1400,20 @@ __global__ void k_huge_clear(int32_t *tk, uint32_t *tv, const Status *st) {
 __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                         const int32_t *__restrict__ w, int32_t n,
                                                         const int32_t *list, const int32_t *cnt_p,
-                                                        const int32_t *meta, const int32_t *__restrict__ Lin,
-                                                        int32_t *tk, uint32_t *tv, unsigned long long *best,
-                                                        long long *deg, uint32_t salt, int mode, Status *st,
-                                                        const int32_t *__restrict__ gv, GStat *gs) {
+                                                        const int32_t *meta, unsigned long long *part,
+                                                        unsigned long long *best, long long *deg, uint32_t salt,
+                                                        int mode, Status *st, const int32_t *__restrict__ gv,
+                                                        GStat *gs) {
   __shared__ unsigned long long sh[kBlock / 64];
-  if (!gv && st->err) return;
+  const bool stats = mode == 2 && !gv;  // the workgroup's weight sum and errors go to part
+  if (!gv && st->err) {
+    if (stats && threadIdx.x == 0) part_write(part, ~0ull, 0, 0);
+    return;
+  }
   const int32_t cnt = *cnt_p;
   const int32_t items = st->huge_items;
+  unsigned long long wsum = 0;
+  int werr = 0;
   for (int32_t p = blockIdx.x; p < items; p += gridDim.x) {
     int32_t i = huge_find(meta, cnt, p, 0);
     int32_t v = list[i];
@@ -1382,12 +1459,13 @@ __global__ __launch_bounds__(kBlock) void k_huge_chunks(const int32_t *__restric
         if (gv) {
           if (err) atomicOr(&gs[gv[v]].err, err);
         } else {
-          atomicAdd(&st->wsum, sum);
-          if (err) atomicOr(&st->err, err);
+          wsum += sum;
+          werr |= err;
         }
       }
     }
   }
+  if (stats && threadIdx.x == 0) part_write(part, ~0ull, wsum, werr);
 }
 
 // Table insertion for LP iterations t >= 2 on huge rows, one chunk of
@@ -2766,8 +2844,7 @@ __global__ void k_reset_bins(Status *st) {
   if (threadIdx.x < 8) st->bin_cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     st->dmax = 0;
-    st->tile_rows = 0;
-    st->tile_arcs = 0;
+    st->tile_tot = 0;
     st->big_tiles = 0;
   }
 }
@@ -3988,9 +4065,10 @@ hipError_t check_rowptr(const DGraph &g, Status *st, hipStream_t s) {
 
 hipError_t build_tiles(const DGraph &g, Work &w, hipStream_t s) {
   w.ntiles = (int32_t)((g.nnz + g.n + kTile - 1) / kTile);
-  k_row_pass<<<grid_for((int64_t)g.n + 1, kBlock, 2048), kBlock, 0, s>>>(
+  k_row_pass<<<grid_for((int64_t)g.n + 1, kRowBlock * kRowsPer, 2048), kRowBlock, 0, s>>>(
       g.row_ptr, g.n, w.ntiles, w.tile_meta, w.n_in, w.bins, w.st, (int32_t)tuning_for(g.nnz).long_split);
-  k_tiles<<<grid_for(w.ntiles), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta, w.st, w.big_tiles);
+  k_tiles<<<grid_for(w.ntiles, kBlock * kTilesPer, 1u << 16), kBlock, 0, s>>>(g.row_ptr, g.n, w.ntiles, w.tile_meta,
+                                                                             w.st, w.big_tiles);
   return hipGetLastError();
 }
 
@@ -4001,19 +4079,9 @@ inline int64_t long_rows_bound(const DGraph &g) { return g.nnz / kTile + 1; }
 // grid of a per-row launch: sized to the rows when the host knows them, else
 // about one resident wave per SIMD slot (the kernels stride over the list)
 inline unsigned rows_grid(int64_t items, int per_block, const int32_t *known) {
-  return grid_for(items, per_block, known ? 8192u : 2048u);
+  return grid_for(items, per_block, known ? kRowsGridMax : 2048u);
 }
 
-template <int G>
-void launch_first(const DGraph &g, Work &w, int b, const int32_t *known, int32_t *L, uint32_t salt, int level0,
-                  hipStream_t s) {
-  const int64_t items = bin_items(known, b, g.n);
-  if (items <= 0) return;
-  const int32_t *list = w.bins + (int64_t)b * w.n_in;
-  k_lp_first<G><<<rows_grid(items, kBlock / G, known), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
-                                                                    &w.st->bin_cnt[b], L, w.deg, salt, level0,
-                                                                    w.st);
-}
 template <int G, int TBL>
 void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int32_t *Lin, int32_t *Lout,
                 uint32_t salt, hipStream_t s, const int32_t *gv, const GStat *gs) {
@@ -4105,28 +4173,37 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
                                                         w.deg, salt, w.st, w.part, (int32_t)tg, nullptr, nullptr);
     }
   }
-  if (!bv && level0) k_reduce_parts<<<grid_for(tg + tb, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)(tg + tb), w.st);
+  // Level-0 statistics of a single solve: every workgroup of the tile, long-row
+  // and huge-chunk kernels leaves (key, sum, errors) in its own part entry,
+  // combined by one k_reduce_parts at the end.
+  static_assert(kLongParts >= (kBinHuge - 4) * (int64_t)kRowsGridMax + kHugeChunksGrid, "part entries");
+  const bool stats = !bv && level0;
+  int64_t np = (int64_t)tg + tb;
   // long rows: a wave per row up to 4096 arcs, chunked beyond
   for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
     if (items > 0) {
       const int32_t *list = w.bins + (int64_t)b * w.n_in;
-      k_lp_first<64><<<rows_grid(items, kBlock / 64, known), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list,
-                                                                          &w.st->bin_cnt[b], L, w.deg, salt, l0,
-                                                                          w.st, gv, gs);
+      const unsigned gb = rows_grid(items, kBlock / 64, known);
+      k_lp_first<64><<<gb, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list, &w.st->bin_cnt[b], L, w.deg, salt, l0,
+                                           w.st, gv, gs, w.part + 3 * np);
+      if (stats) np += gb;
     }
   }
-  if (bin_items(known, kBinHuge, 1) <= 0) return hipGetLastError();
-  // huge rows: chunked
-  const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
-  const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
-  k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st,
-                                   level0 ? w.deg : nullptr);
-  k_huge_chunks<<<grid_for(g.nnz, kHugeChunk, 4096), kBlock, 0, s>>>(
-      g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, nullptr, nullptr, nullptr, w.huge_best, w.deg, salt,
-      level0 ? 2 : 0, w.st, gv, gs);
-  k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, L, w.deg, salt,
-                                     level0 ? 2 : 0, w.st, gv, gs);
+  if (bin_items(known, kBinHuge, 1) > 0) {
+    // huge rows: chunked
+    const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
+    const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
+    k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st,
+                                     level0 ? w.deg : nullptr);
+    const unsigned gh = grid_for(g.nnz, kHugeChunk, kHugeChunksGrid);
+    k_huge_chunks<<<gh, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, w.part + 3 * np,
+                                        w.huge_best, w.deg, salt, level0 ? 2 : 0, w.st, gv, gs);
+    if (stats) np += gh;
+    k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, L, w.deg, salt,
+                                       level0 ? 2 : 0, w.st, gv, gs);
+  }
+  if (stats) k_reduce_parts<<<grid_for(np, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)np, w.st);
   return hipGetLastError();
 }
 

@@ -4017,6 +4017,61 @@ inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 8
 }  // namespace
 
 // ============================================================ launchers
+// ------------------------------------------------------------ side stream
+// Work on disjoint rows (the long-row kernels beside the arc tiles) is queued
+// on a second stream of the calling host thread, so that the two run side by
+// side on the device instead of one after the other. side_fork makes the side
+// stream wait for the work queued on s so far and returns it; side_join makes
+// s wait for the side stream. side_mark records the fork point on s without
+// waiting, for a later side_after_mark. Without a side stream (its creation
+// failed) every call returns s and the work stays in order on s. The streams
+// have the default priority and live until the process ends.
+namespace {
+struct SideStream {
+  int dev;
+  hipStream_t s2;
+  hipEvent_t fork, join;
+};
+SideStream *side_stream() {
+  thread_local std::vector<SideStream> made;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  for (auto &e : made)
+    if (e.dev == dev) return e.s2 ? &e : nullptr;
+  SideStream e{dev, nullptr, nullptr, nullptr};
+  if (hipStreamCreateWithFlags(&e.s2, hipStreamNonBlocking) != hipSuccess) {
+    e.s2 = nullptr;
+  } else if (hipEventCreateWithFlags(&e.fork, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&e.join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(e.s2);
+    e.s2 = nullptr;
+  }
+  made.push_back(e);
+  return made.back().s2 ? &made.back() : nullptr;
+}
+hipStream_t side_after_mark(hipStream_t s) {
+  SideStream *ss = side_stream();
+  if (!ss || hipStreamWaitEvent(ss->s2, ss->fork, 0) != hipSuccess) return s;
+  return ss->s2;
+}
+void side_mark(hipStream_t s) {
+  SideStream *ss = side_stream();
+  if (ss) (void)hipEventRecord(ss->fork, s);
+}
+hipStream_t side_fork(hipStream_t s) {
+  SideStream *ss = side_stream();
+  if (!ss || hipEventRecord(ss->fork, s) != hipSuccess) return s;
+  return side_after_mark(s);
+}
+hipError_t side_join(hipStream_t s, hipStream_t s2) {
+  if (s2 == s) return hipSuccess;
+  SideStream *ss = side_stream();
+  if (!ss) return hipErrorInvalidValue;
+  const hipError_t e = hipEventRecord(ss->join, s2);
+  return e != hipSuccess ? e : hipStreamWaitEvent(s, ss->join, 0);
+}
+}  // namespace
+
 hipError_t fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   k_fill_i32<<<grid_for(count), kBlock, 0, s>>>(p, v, count);
@@ -4081,6 +4136,17 @@ inline int64_t long_rows_bound(const DGraph &g) { return g.nnz / kTile + 1; }
 inline unsigned rows_grid(int64_t items, int per_block, const int32_t *known) {
   return grid_for(items, per_block, known ? kRowsGridMax : 2048u);
 }
+// The side stream costs a wait across hardware queues at the fork and at the
+// join (several microseconds each): it pays only when the long rows hold much
+// of a pass's work. With the class counts known their arcs are bounded from
+// below by the class minimums; without them (the first pass of a solve) the
+// average degree stands in.
+inline bool side_worth(const DGraph &g, const int32_t *known) {
+  if (!known) return g.nnz >= 64 * (int64_t)g.n;
+  const int64_t lb = 256ll * known[4] + (int64_t)tuning_for(g.nnz).long_split * known[5] + 1024ll * known[6] +
+                     4097ll * known[7];
+  return lb >= std::max<int64_t>(1 << 22, g.nnz / 8);
+}
 
 template <int G, int TBL>
 void launch_tab(const DGraph &g, Work &w, int b, const int32_t *known, const int32_t *Lin, int32_t *Lout,
@@ -4131,6 +4197,8 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   const bool each = tuning_for(g.nnz).first_group == 1;
   const unsigned tg = each ? grid_for(w.ntiles, 1, 1u << 20) : grid_for((w.ntiles + kTP - 1) / kTP, 1, 1u << 20);
   const unsigned tb = each ? 0u : resident_grid(k_first_tile_big<true, false>, kTB, w.ntiles);
+  // the long and huge rows on the side stream, beside the arc tiles
+  const hipStream_t s2 = side_worth(g, known) ? side_fork(s) : s;
   if (each) {
     ProfScope ps(level0 ? PROF_FIRST_TILE_L0 : PROF_FIRST_TILE, s, w.st, w.ntiles);
     if (bv) {
@@ -4185,8 +4253,8 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
     if (items > 0) {
       const int32_t *list = w.bins + (int64_t)b * w.n_in;
       const unsigned gb = rows_grid(items, kBlock / 64, known);
-      k_lp_first<64><<<gb, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list, &w.st->bin_cnt[b], L, w.deg, salt, l0,
-                                           w.st, gv, gs, w.part + 3 * np);
+      k_lp_first<64><<<gb, kBlock, 0, s2>>>(g.row_ptr, g.col, g.w, g.n, list, &w.st->bin_cnt[b], L, w.deg, salt, l0,
+                                            w.st, gv, gs, w.part + 3 * np);
       if (stats) np += gb;
     }
   }
@@ -4194,15 +4262,19 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
     // huge rows: chunked
     const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;
     const int32_t *cnt6 = &w.st->bin_cnt[kBinHuge];
-    k_huge_plan<<<1, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st,
-                                     level0 ? w.deg : nullptr);
+    k_huge_plan<<<1, kBlock, 0, s2>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, 0, w.huge_cap, w.st,
+                                      level0 ? w.deg : nullptr);
     const unsigned gh = grid_for(g.nnz, kHugeChunk, kHugeChunksGrid);
-    k_huge_chunks<<<gh, kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, w.part + 3 * np,
-                                        w.huge_best, w.deg, salt, level0 ? 2 : 0, w.st, gv, gs);
+    k_huge_chunks<<<gh, kBlock, 0, s2>>>(g.row_ptr, g.col, g.w, g.n, list6, cnt6, w.huge_meta, w.part + 3 * np,
+                                         w.huge_best, w.deg, salt, level0 ? 2 : 0, w.st, gv, gs);
     if (stats) np += gh;
-    k_huge_final<<<64, kBlock, 0, s>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, L, w.deg, salt,
-                                       level0 ? 2 : 0, w.st, gv, gs);
+    k_huge_final<<<64, kBlock, 0, s2>>>(g.row_ptr, list6, cnt6, w.huge_meta, w.huge_best, nullptr, L, w.deg, salt,
+                                        level0 ? 2 : 0, w.st, gv, gs);
   }
+  hipError_t e = hipGetLastError();
+  const hipError_t ej = side_join(s, s2);
+  if (e == hipSuccess) e = ej;
+  if (e != hipSuccess) return e;
   if (stats) k_reduce_parts<<<grid_for(np, kBlock, 64), kBlock, 0, s>>>(w.part, (int32_t)np, w.st);
   return hipGetLastError();
 }
@@ -4232,10 +4304,21 @@ void launch_lp_small(int tp, const DGraph &g, Work &w, const int32_t *Lin, int32
   }
 }
 
+namespace {
+hipError_t lp_long_rows(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout,
+                        uint32_t salt, hipStream_t s, const int32_t *gv, GStat *gs);
+}  // namespace
+
 hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout, uint32_t salt,
                    hipStream_t s, const BatchView *bv, int part) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   GStat *gs = bv ? bv->gs : nullptr;
+  // the long and huge rows on the side stream, beside the arc tiles (part 1
+  // marks the fork point before its tiles, part 2 starts from that mark)
+  hipStream_t s2 = s;
+  if (part == 0 && side_worth(g, known)) s2 = side_fork(s);
+  if (part == 1 && side_worth(g, nullptr)) side_mark(s);
+  if (part == 2 && side_worth(g, nullptr)) s2 = side_after_mark(s);
   if (part != 2) {
     ProfScope ps(PROF_LP_TILE, s, w.st, w.ntiles);
     const int tp = (int)tuning_for(g.nnz).lp_group;
@@ -4250,6 +4333,16 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
     }
   }
   if (part == 1) return hipGetLastError();
+  hipError_t e = lp_long_rows(g, w, known, Lin, Lout, salt, s2, gv, gs);
+  const hipError_t ej = side_join(s, s2);
+  return e != hipSuccess ? e : ej;
+}
+
+namespace {
+// LP iteration t >= 2 on the long and huge rows (the classes of at least
+// 256 arcs), queued on stream s
+hipError_t lp_long_rows(const DGraph &g, Work &w, const int32_t *known, const int32_t *Lin, int32_t *Lout,
+                        uint32_t salt, hipStream_t s, const int32_t *gv, GStat *gs) {
   launch_tab<64, 1024>(g, w, 4, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<64, 2048>(g, w, 5, known, Lin, Lout, salt, s, gv, gs);
   launch_tab<256, 8192>(g, w, 6, known, Lin, Lout, salt, s, gv, gs);
@@ -4287,6 +4380,7 @@ hipError_t lp_iter(const DGraph &g, Work &w, const int32_t *known, const int32_t
                                      w.st, gv, gs);
   return hipGetLastError();
 }
+}  // namespace
 
 hipError_t validate_sym(const DGraph &g, Status *st, hipStream_t s, const BatchView *bv) {
   k_validate_sym<<<grid_for(g.n), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, g.n, st, bv ? bv->gv : nullptr,
@@ -4406,19 +4500,47 @@ void launch_emit_tiles(const DGraph &g, Work &w, const int32_t *gv, const GStat 
 }
 }  // namespace
 
+namespace {
+hipError_t emit_long_rows(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const int32_t *gv,
+                          const GStat *gs, int64_t long_max);
+}  // namespace
+
 hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv) {
   const int32_t *gv = bv ? bv->gv : nullptr;
   const GStat *gs = bv ? bv->gs : nullptr;
   const int64_t long_max = g.nnz / kTile + 1;
   constexpr int kLong = kBins - 4;  // one region of long_max segments per long class
   const int64_t nseg = w.ntiles + kLong * long_max;
-  // long-row segments beyond the device-side row counts stay empty
-  hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, kLong * long_max, s);
-  if (e != hipSuccess) return e;
+  // the long and huge rows on the side stream, beside the arc tiles
+  const hipStream_t s2 = side_worth(g, known) ? side_fork(s) : s;
   if (bv)
     launch_emit_tiles<true>(g, w, gv, gs, s);
   else
     launch_emit_tiles<false>(g, w, nullptr, nullptr, s);
+  hipError_t e = emit_long_rows(g, w, known, s2, gv, gs, long_max);
+  const hipError_t ej = side_join(s, s2);
+  if (e == hipSuccess) e = ej;
+  if (e != hipSuccess) return e;
+  e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
+  if (e != hipSuccess) return e;
+  if (nseg <= tuning_for(g.nnz).compact_direct_max)
+    k_compact_direct<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st,
+                                                                       w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
+  else
+    k_compact<<<grid_for(g.nnz, kBlock * kCompactItems, 4096), kBlock, 0, s>>>(
+        w.seg, w.seg_cnt, (int32_t)nseg, w.st, w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
+  return hipGetLastError();
+}
+
+namespace {
+// Emission of the long and huge rows into their segment regions (beyond the
+// tiles' segments), queued on stream s
+hipError_t emit_long_rows(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const int32_t *gv,
+                          const GStat *gs, int64_t long_max) {
+  constexpr int kLong = kBins - 4;  // one region of long_max segments per long class
+  // long-row segments beyond the device-side row counts stay empty
+  hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, kLong * long_max, s);
+  if (e != hipSuccess) return e;
   for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;
@@ -4443,16 +4565,9 @@ hipError_t contract_emit(const DGraph &g, Work &w, const int32_t *known, hipStre
                                                                       w.huge_meta, w.st, w.keys[0], w.vals[0],
                                                                       w.seg + s0, w.seg_cnt + s0, gv, gs);
   }
-  e = scan_exclusive(w, w.seg_cnt, w.seg_cnt, nseg, &w.st->ax, s);
-  if (e != hipSuccess) return e;
-  if (nseg <= tuning_for(g.nnz).compact_direct_max)
-    k_compact_direct<<<grid_for(g.nnz, kBlock, 4096), kBlock, 0, s>>>(w.seg, w.seg_cnt, (int32_t)nseg, w.st,
-                                                                       w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
-  else
-    k_compact<<<grid_for(g.nnz, kBlock * kCompactItems, 4096), kBlock, 0, s>>>(
-        w.seg, w.seg_cnt, (int32_t)nseg, w.st, w.keys[0], w.vals[0], w.keys[1], w.vals[1]);
   return hipGetLastError();
 }
+}  // namespace
 
 namespace {
 template <int ITEMS>

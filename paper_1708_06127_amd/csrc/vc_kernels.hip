@@ -437,6 +437,23 @@ constexpr int kLoadBatch = 8;
 // Identity labels: S(x) = w(v, x), so the new label is the row's argmax of
 // (w, -prio). At level 0 the same pass validates the row and computes the
 // weighted degree and the minimum-degree key.
+// Up to three long-row classes in one launch: workgroups [first[c],
+// first[c + 1]) take class c (its list, count and, for emission, its segment
+// region), so classes with few or no rows cost no launch of their own.
+struct RowClasses {
+  const int32_t *list[3];
+  const int32_t *cnt[3];
+  int32_t *seg[3];
+  int32_t *seg_cnt[3];
+  int32_t first[4];
+};
+__device__ __forceinline__ int row_class(const RowClasses &rc) {
+  int c = 0;
+  if ((int32_t)blockIdx.x >= rc.first[1]) c = 1;
+  if ((int32_t)blockIdx.x >= rc.first[2]) c = 2;
+  return c;
+}
+
 // Level-0 statistics of one workgroup, (minimum-degree key, weight sum, error
 // bits), into its own entry of `part` (combined by k_reduce_parts): device
 // atomics on the status words from every workgroup would be serialized.
@@ -450,13 +467,15 @@ __device__ __forceinline__ void part_write(unsigned long long *part, unsigned lo
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                                      const int32_t *__restrict__ w, int32_t n,
-                                                      const int32_t *__restrict__ list, const int32_t *cnt_p,
+                                                      const int32_t *__restrict__ w, int32_t n, RowClasses rc,
                                                       int32_t *__restrict__ L, long long *__restrict__ deg,
                                                       uint32_t salt, int level0, Status *st,
                                                       const int32_t *__restrict__ gv, GStat *gs,
                                                       unsigned long long *part) {
   __shared__ unsigned long long sh[kBlock / 64];
+  const int cls = row_class(rc);
+  const int32_t *__restrict__ list = rc.list[cls];
+  const int32_t bid = (int32_t)blockIdx.x - rc.first[cls], nblk = rc.first[cls + 1] - rc.first[cls];
   const bool stats = level0 && !gv;  // the workgroup's (min-degree key, weight sum, errors) go to part
   if (!gv && st->err) {
     if (stats && threadIdx.x == 0) part_write(part, ~0ull, 0, 0);
@@ -464,10 +483,10 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
   }
   constexpr int NG = kBlock / G;
   const int gi = threadIdx.x / G, lane = threadIdx.x % G;
-  const int32_t cnt = *cnt_p;
+  const int32_t cnt = *rc.cnt[cls];
   unsigned long long mykey = ~0ull, mysum = 0;
   int myerr = 0;
-  for (int64_t base = blockIdx.x * (int64_t)NG; base < cnt; base += (int64_t)gridDim.x * NG) {
+  for (int64_t base = bid * (int64_t)NG; base < cnt; base += (int64_t)nblk * NG) {
     int64_t idx = base + gi;
     bool act = idx < cnt;
     int32_t v = act ? list[idx] : 0;
@@ -2383,17 +2402,21 @@ __device__ __forceinline__ int32_t wave_excl_scan(int32_t x, int32_t &total) {
 // appended in order with a wave prefix sum (no workgroup barriers)
 __global__ __launch_bounds__(kBlock) void k_emit_wave(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                                        const int32_t *__restrict__ w, const int32_t *__restrict__ cl,
-                                                       const int32_t *list, const int32_t *cnt_p, const Status *st,
+                                                       RowClasses rc, const Status *st,
                                                        unsigned long long *__restrict__ keys,
-                                                       int32_t *__restrict__ vals, int32_t *__restrict__ first,
-                                                       int32_t *__restrict__ seg_cnt, const int32_t *__restrict__ gv,
+                                                       int32_t *__restrict__ vals, const int32_t *__restrict__ gv,
                                                        const GStat *gs) {
   constexpr int kPer = 8;
+  const int cls = row_class(rc);
+  const int32_t *list = rc.list[cls];
+  int32_t *__restrict__ first = rc.seg[cls];
+  int32_t *__restrict__ seg_cnt = rc.seg_cnt[cls];
+  const int32_t bid = (int32_t)blockIdx.x - rc.first[cls], nblk = rc.first[cls + 1] - rc.first[cls];
   const int key_bits = emit_lo_bits(st, gv);
-  const int32_t cnt = *cnt_p;
+  const int32_t cnt = *rc.cnt[cls];
   const int lane = threadIdx.x & 63;
-  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
-  for (int64_t r = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6; r < cnt; r += nwaves) {
+  const int64_t nwaves = ((int64_t)nblk * kBlock) >> 6;
+  for (int64_t r = (bid * (int64_t)kBlock + threadIdx.x) >> 6; r < cnt; r += nwaves) {
     const int32_t v0 = list[r];
     const int32_t cv = cl[v0];
     const int32_t cb = gv ? gs[gv[v0]].base : 0;
@@ -4244,19 +4267,23 @@ hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, 
   // Level-0 statistics of a single solve: every workgroup of the tile, long-row
   // and huge-chunk kernels leaves (key, sum, errors) in its own part entry,
   // combined by one k_reduce_parts at the end.
-  static_assert(kLongParts >= (kBinHuge - 4) * (int64_t)kRowsGridMax + kHugeChunksGrid, "part entries");
+  static_assert(kBinHuge - 4 == 3 && kLongParts >= 3 * (int64_t)kRowsGridMax + kHugeChunksGrid, "part entries");
   const bool stats = !bv && level0;
   int64_t np = (int64_t)tg + tb;
-  // long rows: a wave per row up to 4096 arcs, chunked beyond
-  for (int b = 4; b < kBinHuge; b++) {
+  // long rows: a wave per row up to 4096 arcs (the three classes in one launch), chunked beyond
+  RowClasses rc = {};
+  rc.first[0] = 0;
+  for (int c = 0; c < 3; c++) {
+    const int b = 4 + c;
     const int64_t items = known ? known[b] : g.nnz / kTile + 1;
-    if (items > 0) {
-      const int32_t *list = w.bins + (int64_t)b * w.n_in;
-      const unsigned gb = rows_grid(items, kBlock / 64, known);
-      k_lp_first<64><<<gb, kBlock, 0, s2>>>(g.row_ptr, g.col, g.w, g.n, list, &w.st->bin_cnt[b], L, w.deg, salt, l0,
-                                            w.st, gv, gs, w.part + 3 * np);
-      if (stats) np += gb;
-    }
+    rc.list[c] = w.bins + (int64_t)b * w.n_in;
+    rc.cnt[c] = &w.st->bin_cnt[b];
+    rc.first[c + 1] = rc.first[c] + (items > 0 ? (int32_t)rows_grid(items, kBlock / 64, known) : 0);
+  }
+  if (rc.first[3] > 0) {
+    k_lp_first<64><<<rc.first[3], kBlock, 0, s2>>>(g.row_ptr, g.col, g.w, g.n, rc, L, w.deg, salt, l0, w.st, gv, gs,
+                                                   w.part + 3 * np);
+    if (stats) np += rc.first[3];
   }
   if (bin_items(known, kBinHuge, 1) > 0) {
     // huge rows: chunked
@@ -4541,20 +4568,31 @@ hipError_t emit_long_rows(const DGraph &g, Work &w, const int32_t *known, hipStr
   // long-row segments beyond the device-side row counts stay empty
   hipError_t e = fill_i32(w.seg_cnt + w.ntiles, 0, kLong * long_max, s);
   if (e != hipSuccess) return e;
+  // rows of fewer than 1024 arcs: a wave per row (both classes in one launch)
+  RowClasses rc = {};
+  const bool wave = tuning_for(g.nnz).emit_wave != 0;
+  for (int c = 0; c < 3; c++) rc.first[c + 1] = rc.first[c];
   for (int b = 4; b < kBinHuge; b++) {
     const int64_t items = known ? known[b] : long_max;
     if (items <= 0) continue;
     const int64_t s0 = w.ntiles + (b - 4) * long_max;
-    if (b < 6 && tuning_for(g.nnz).emit_wave)  // rows of fewer than 1024 arcs: a wave per row
-      k_emit_wave<<<grid_for(items, kBlock / 64, 8192), kBlock, 0, s>>>(
-          g.row_ptr, g.col, g.w, w.cl, w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st, w.keys[0], w.vals[0],
-          w.seg + s0, w.seg_cnt + s0, gv, gs);
-    else
+    if (b < 6 && wave) {
+      const int c = b - 4;
+      rc.list[c] = w.bins + (int64_t)b * w.n_in;
+      rc.cnt[c] = &w.st->bin_cnt[b];
+      rc.seg[c] = w.seg + s0;
+      rc.seg_cnt[c] = w.seg_cnt + s0;
+      const int32_t gb = (int32_t)grid_for(items, kBlock / 64, 8192);
+      for (int c2 = c + 1; c2 < 4; c2++) rc.first[c2] += gb;
+    } else {
       k_emit_long<<<grid_for(items, 1, 4096), kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl,
                                                               w.bins + (int64_t)b * w.n_in, &w.st->bin_cnt[b], w.st,
                                                               w.keys[0], w.vals[0], w.seg + s0, w.seg_cnt + s0, gv,
                                                               gs);
+    }
   }
+  if (rc.first[3] > 0)
+    k_emit_wave<<<rc.first[3], kBlock, 0, s>>>(g.row_ptr, g.col, g.w, w.cl, rc, w.st, w.keys[0], w.vals[0], gv, gs);
   if (bin_items(known, kBinHuge, 1) > 0) {
     // chunks of the huge rows (at most long_max of them: one segment each)
     const int32_t *list6 = w.bins + (int64_t)kBinHuge * w.n_in;

@@ -508,17 +508,24 @@ __global__ __launch_bounds__(kBlock) void k_lp_first(const int32_t *__restrict__
         xs[u] = col[i];
         cs[u] = w[i];
       }
+      bool bad = false;  // (level 0) an arc of this batch fails an input check
 #pragma unroll
       for (int u = 0; u < kLoadBatch; u++) {
         if (i0 + u * G >= end) break;
         const int32_t x = xs[u], c = cs[u];
-        if (level0) {
+        if (level0) bad |= ((uint32_t)x >= (uint32_t)n) | (x == v) | (c < 1);
+        sum += (unsigned long long)(uint32_t)c;
+        best = umax64(best, cand_key((uint32_t)c, x - b0, sl));
+      }
+      if (bad) {  // invalid input (rare): the error bits of the batch
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; u++) {
+          if (i0 + u * G >= end) break;
+          const int32_t x = xs[u], c = cs[u];
           if (x < 0 || x >= n) err |= ERR_COL;
           if (x == v) err |= ERR_SELF;
           if (c < 1) err |= ERR_WEIGHT;
         }
-        sum += (unsigned long long)(uint32_t)c;
-        best = umax64(best, cand_key((uint32_t)c, x - b0, sl));
       }
     }
     best = grp_max<G>(best);
@@ -1141,6 +1148,7 @@ __device__ __forceinline__ void first_tile_run(const FirstFetch<B, NQ> &f, int32
     unsigned long long best = 0, sum = 0;
     int32_t cur = rw[0], bj = 0;
     uint32_t sj = salt;
+    bool bad = false;  // (level 0) an arc of this lane fails an input check
     if constexpr (B) { bj = sh.base[cur]; sj = sh.salt[cur]; }
 #pragma unroll
     for (int k = 0; k < NQ; k++) {
@@ -1156,20 +1164,30 @@ __device__ __forceinline__ void first_tile_run(const FirstFetch<B, NQ> &f, int32
       best = umax64(best, cand_key((uint32_t)c, x - bj, sj));
       if constexpr (L0) {
         sum += (unsigned long long)(uint32_t)c;
-        int e = 0;
-        if (x < 0 || x >= n) e |= ERR_COL;
-        if (x == r0 + cur) e |= ERR_SELF;
-        if (c < 1) e |= ERR_WEIGHT;
-        if constexpr (B) {
-          if (e) atomicOr(&gs[gv[r0 + cur]].err, e);  // rare: straight to the graph's flags
-        } else {
-          acc.err |= e;
-        }
+        bad |= ((uint32_t)x >= (uint32_t)n) | (x == r0 + cur) | (c < 1);
       }
     }
     if (NQ * lane < acnt) {
       atomicMax(&sh.best[cur], best);
       if constexpr (L0) atomicAdd(&sh.sum[cur], sum);
+    }
+    if constexpr (L0) {
+      if (__ballot(bad)) {  // invalid input (rare): the error bits of this lane's arcs
+#pragma unroll
+        for (int k = 0; k < NQ; k++) {
+          if (NQ * lane + k >= acnt) break;
+          const int32_t x = f.xs[k], c = f.cs[k];
+          int e = 0;
+          if (x < 0 || x >= n) e |= ERR_COL;
+          if (x == r0 + rw[k]) e |= ERR_SELF;
+          if (c < 1) e |= ERR_WEIGHT;
+          if constexpr (B) {
+            if (e) atomicOr(&gs[gv[r0 + rw[k]]].err, e);  // straight to the graph's flags
+          } else {
+            acc.err |= e;
+          }
+        }
+      }
     }
   }
   __syncthreads();

@@ -163,6 +163,29 @@ def test_full_size_rmat22_core():
 
 
 # ------------------------------------------------------------ error paths
+@pytest.mark.parametrize("hub_deg", [700, 3000, 9000])
+def test_input_errors_in_long_rows(hub_deg):
+    """A bad arc inside the hub's row (a long row of the wave, workgroup or
+    chunked class) is reported like one in a tile: zero weight, a column out
+    of range and a self loop, each at an arc past the first load batch."""
+    g = hub_graph(11, hub_deg)
+    rp, col, w = to_dev(g)
+    a = int(g.row_ptr[0]) + hub_deg - 7  # an arc near the end of row 0
+    log("long-row errors: hub %d arc %d" % (hub_deg, a))
+    w0 = w.clone()
+    w0[a] = 0
+    with pytest.raises(vc.ViecutError) as e:
+        vc.mincut(rp, col, w0)
+    assert e.value.code == vc.EWEIGHT
+    for bad in (g.n + 5, -3, 0):
+        c2 = col.clone()
+        c2[a] = bad
+        with pytest.raises(vc.ViecutError) as e:
+            vc.mincut(rp, c2, w)
+        assert e.value.code == vc.EINVAL
+    compare(g, "hub-err%d" % hub_deg, trace=False, lp_iters=2, n0=16, seed=1)  # the untouched graph
+
+
 def test_error_codes_and_recovery():
     import torch
     ok = gg.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)])

@@ -3514,37 +3514,90 @@ __device__ __forceinline__ void uf_union(int32_t *parent, int32_t a, int32_t b) 
     if (atomicCAS(&parent[b], b, a) == b) return;
   }
 }
-// one wave per tile: wider workgroups ran more unions at once and lost more
-// time to failed root links than they gained
+// The same union-find on a tile's rows in LDS (local ids 0 .. rows - 1),
+// for the marked edges with both ends in the tile.
+__device__ __forceinline__ int32_t lds_root(int32_t *lp, int32_t x) {
+  while (true) {
+    const int32_t p = __hip_atomic_load(&lp[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (p == x) return x;
+    const int32_t gp = __hip_atomic_load(&lp[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (gp != p) __hip_atomic_store(&lp[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    x = gp;
+  }
+}
+__device__ __forceinline__ void lds_union(int32_t *lp, int32_t a, int32_t b) {
+  while (true) {
+    a = lds_root(lp, a);
+    b = lds_root(lp, b);
+    if (a == b) return;
+    if (a > b) { const int32_t t = a; a = b; b = t; }
+    if (atomicCAS(&lp[b], b, a) == b) return;
+  }
+}
+// One wave per tile (wider workgroups ran more unions at once and lost more
+// time to failed root links than they gained). Most marked edges join two
+// rows of the same tile (on the RHG graph's first coarse graph: 95 %, with
+// 99 % of its edges marked), so they are first united in LDS; then every
+// row that is not its local root is linked under it in the global forest
+// (one CAS, or a full union if another tile linked the row first), and only
+// the edges that leave the tile run full unions, from the local root. Links
+// always go to a smaller id, so each component's root stays its smallest
+// vertex, as with unions in any order.
 __global__ __launch_bounds__(kTB) void k_uf_tile(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                           const uint8_t *__restrict__ mark, const int4 *__restrict__ meta, int32_t ntiles,
                           int32_t *parent) {
   __shared__ int32_t s_rp[kTile + 1];
+  __shared__ int32_t lp[kTile];
   for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 m = meta[t];
     const int32_t r0 = m.x, rows = m.y, a0 = m.z, acnt = m.w;
     const int32_t q = (acnt + kTB - 1) / kTB;
     const int32_t i0 = threadIdx.x * q;
-    for (int j = threadIdx.x; j <= rows; j += kTB) s_rp[j] = rp[r0 + j] - a0;
+    for (int j = threadIdx.x; j <= rows; j += kTB) {
+      s_rp[j] = rp[r0 + j] - a0;
+      if (j < rows) lp[j] = j;
+    }
     __syncthreads();
+    uint8_t mk[kPerThread];
+    int32_t xs[kPerThread], js[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++) {  // the lane's marks first (clamped), then the marked columns
+      mk[k] = k < q && i0 + k < acnt ? mark[a0 + i0 + k] : 0;
+      js[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++) xs[k] = mk[k] ? col[a0 + i0 + k] : 0;
     if (i0 < acnt) {
-      const int32_t iend = min(i0 + q, acnt);
-      uint8_t mk[kPerThread];
-      int32_t xs[kPerThread];
-#pragma unroll
-      for (int k = 0; k < kPerThread; k++)  // the lane's marks first (clamped), then the marked columns
-        mk[k] = k < q && i0 + k < iend ? mark[a0 + i0 + k] : 0;
-#pragma unroll
-      for (int k = 0; k < kPerThread; k++) xs[k] = mk[k] ? col[a0 + i0 + k] : 0;
       int32_t j = row_of(s_rp, rows, i0);
 #pragma unroll
       for (int k = 0; k < kPerThread; k++) {
         const int32_t i = i0 + k;
-        if (i >= iend) break;
+        if (k >= q || i >= acnt) break;
         while (i >= s_rp[j + 1]) j++;
-        if (mk[k]) uf_union(parent, r0 + j, xs[k]);
+        js[k] = j;
       }
     }
+    // edges inside the tile, in LDS
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++) {
+      const uint32_t xl = (uint32_t)(xs[k] - r0);
+      if (mk[k] && xl < (uint32_t)rows) {
+        lds_union(lp, js[k], (int32_t)xl);
+        mk[k] = 0;
+      }
+    }
+    // rows under their local roots in the global forest
+    for (int j = threadIdx.x; j < rows; j += kTB) {
+      const int32_t rj = lds_root(lp, j);
+      if (rj != j) {
+        const int32_t v = r0 + j, a = r0 + rj;
+        if (atomicCAS(&parent[v], v, a) != v) uf_union(parent, v, a);
+      }
+    }
+    // edges that leave the tile
+#pragma unroll
+    for (int k = 0; k < kPerThread; k++)
+      if (mk[k]) uf_union(parent, r0 + lds_root(lp, js[k]), xs[k]);
     __syncthreads();
   }
 }

@@ -452,11 +452,16 @@ struct Solver {
     const int32_t k = st.k;
     const int64_t ax = st.ax;
     const int kb = bits_for_host(k);
-    int which = 1;  // the emission leaves the packed triples in buffer 1
-    VC_TRY(radix_sort(w, ax, 2 * kb, which, s));
     const int dst = cur == 0 ? 1 : 0;
-    level++;
-    VC_TRY(contract_build(w, which, ax, kb, k, dst, level, s));
+    if (k == 1) {  // one cluster: no inter-cluster arc (ax = 0), the graph collapses
+      level++;
+      VC_TRY(contract_collapse(w, dst, s));
+    } else {
+      int which = 1;  // the emission leaves the packed triples in buffer 1
+      VC_TRY(radix_sort(w, ax, 2 * kb, which, s));
+      level++;
+      VC_TRY(contract_build(w, which, ax, kb, k, dst, level, s));
+    }
     if (sweep >= 0) prof_span_end(sweep, s);
     rc = sync_status();
     if (rc) return rc;
@@ -480,8 +485,10 @@ struct Solver {
     const int32_t n_prev = G.n;
     G = H;
     cur = dst;
-    VC_TRY(reset_bins(w, s));
-    VC_TRY(build_tiles(G, w, s));
+    if (!(st.stop & ST_COLLAPSED)) {  // (a collapsed graph ends the rounds: no tiles needed)
+      VC_TRY(reset_bins(w, s));
+      VC_TRY(build_tiles(G, w, s));
+    }
     known = nullptr;
     trace_graph(level, G, n_prev);
     if (!(st.stop & ST_COLLAPSED)) trace_bound(level, G.n);

@@ -283,6 +283,10 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
                           hipStream_t s, bool single_bound = true, const int32_t *gv_new = nullptr,
                           const GStat *gs = nullptr);
 hipError_t bound_level0(Work &w, hipStream_t s);
+// The contracted graph of a partition into one cluster: one vertex, no arcs
+// (row pointers and degree zero, nnz = 0, the stop flag ST_COLLAPSED), in one
+// launch instead of the segment passes and the bound update.
+hipError_t contract_collapse(Work &w, int dst, hipStream_t s);
 // PR marks on the v < x arcs (st->nmarked != 0 iff some edge was marked)
 hipError_t pr_mark(const DGraph &g, Work &w, const int32_t *known, hipStream_t s, const BatchView *bv = nullptr);
 hipError_t union_find(const DGraph &g, Work &w, const int32_t *known, int32_t *rep, hipStream_t s);

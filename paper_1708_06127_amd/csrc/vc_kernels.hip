@@ -4730,6 +4730,21 @@ hipError_t contract_build(Work &w, int which, int64_t count, int key_bits, int32
   return hipGetLastError();
 }
 
+__global__ void k_collapse(int32_t *rp, long long *deg, Status *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  rp[0] = 0;
+  rp[1] = 0;
+  deg[0] = 0;
+  st->nnz = 0;
+  st->updated = 0;
+  st->stop |= ST_COLLAPSED;
+}
+
+hipError_t contract_collapse(Work &w, int dst, hipStream_t s) {
+  k_collapse<<<1, 64, 0, s>>>(w.rp[dst], w.deg, w.st);
+  return hipGetLastError();
+}
+
 hipError_t bound_level0(Work &w, hipStream_t s) {
   k_bound<<<1, 64, 0, s>>>(w.st, 0, w.n_in);
   k_witness<<<grid_for(w.n_in), kBlock, 0, s>>>(w.map, w.n_in, w.st, w.witness);

@@ -344,7 +344,7 @@ __device__ __forceinline__ int32_t row_of(const int32_t *s_rp, int32_t rows, int
 // into the other count). A workgroup of kRowBlock threads takes kRowsPer rows
 // per thread, which keeps the serialized reservations few.
 constexpr int kRowBlock = 1024;
-constexpr int kRowsPer = 8;
+constexpr int kRowsPer = 4;
 static_assert(offsetof(Status, bin_cnt) % 8 == 0, "bin_cnt pairs are added as 64-bit words");
 __global__ __launch_bounds__(kRowBlock) void k_row_pass(const int32_t *rp, int32_t n, int32_t ntiles, int4 *meta,
                                                         int64_t stride, int32_t *bins, Status *st,
@@ -4282,6 +4282,24 @@ unsigned resident_grid(K kernel, int block, int64_t items) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, full));
 }
 
+namespace {
+// Dynamic LDS above 64 KB must be allowed per kernel; the attribute is set
+// once per kernel and device, under a lock (several host threads may launch).
+hipError_t allow_lds(const void *fn, int bytes) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void *, int>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const auto &d : done)
+    if (d.first == fn && d.second == dev) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.push_back({fn, dev});
+  return e;
+}
+}  // namespace
+
 hipError_t lp_first(const DGraph &g, Work &w, const int32_t *known, int32_t *L, uint32_t salt, bool level0,
                     hipStream_t s, const BatchView *bv) {
   const int l0 = level0 ? 1 : 0;
@@ -4453,13 +4471,8 @@ hipError_t lp_long_rows(const DGraph &g, Work &w, const int32_t *known, const in
     const hipError_t e = fill_i32(&w.st->huge_fallback, 1, 1, s);
     if (e != hipSuccess) return e;
   } else {
-    static bool attr = false;
-    if (!attr) {
-      const hipError_t e = hipFuncSetAttribute((const void *)k_huge_part, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(8 * kPartSlots));
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
+    const hipError_t e = allow_lds((const void *)k_huge_part, (int)(8 * kPartSlots));
+    if (e != hipSuccess) return e;
     const unsigned pg = resident_grid(k_huge_part, kPartThreads, 1 << 20);
     k_huge_part<<<pg, kPartThreads, 8 * kPartSlots, s>>>(g.row_ptr, g.col, g.w, list6, cnt6, w.huge_meta, Lin,
                                                          w.huge_best, salt, w.st, gv, gs, w.huge_meta, 1);
@@ -4828,14 +4841,9 @@ hipError_t side_from_witness(Work &w, uint64_t *side, hipStream_t s) {
 namespace {
 // the largest matrix (128 x 129 words) needs more than 64 KB of LDS
 hipError_t allow_dense_lds() {
-  static bool done = false;
-  if (done) return hipSuccess;
   const int bytes = (int)(sizeof(uint32_t) * kDenseMax * (kDenseMax | 1));
-  hipError_t e = hipFuncSetAttribute((const void *)k_sw_dense, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_sw_dense_batch, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) done = true;
-  return e;
+  hipError_t e = allow_lds((const void *)k_sw_dense, bytes);
+  return e != hipSuccess ? e : allow_lds((const void *)k_sw_dense_batch, bytes);
 }
 }  // namespace
 

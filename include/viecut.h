@@ -28,6 +28,12 @@
  *
  * All graph pointers are DEVICE pointers unless stated otherwise. A stream
  * argument is a hipStream_t passed as void* (NULL = the default stream).
+ * Passes whose long rows carry much of the work also queue those rows'
+ * kernels on a second stream that the library keeps per host thread and
+ * device (default priority, created on first use, never destroyed); it is
+ * ordered after the work already on the caller's stream and the caller's
+ * stream waits for it (events) before the next pass, so every call's work,
+ * on both streams, is complete when the call returns.
  * No function throws; every function that can fail returns a status code
  * (VIECUT_OK = 0 or a negative VIECUT_E* value). On error no output is
  * written and the library stays usable.

@@ -31,9 +31,10 @@
  * Passes whose long rows carry much of the work also queue those rows'
  * kernels on a second stream that the library keeps per host thread and
  * device (default priority, created on first use, never destroyed); it is
- * ordered after the work already on the caller's stream and the caller's
- * stream waits for it (events) before the next pass, so every call's work,
- * on both streams, is complete when the call returns.
+ * ordered after the work already on the caller's stream, and the caller's
+ * stream waits for it (events) before the next pass: whatever is queued on
+ * the caller's stream after a call, or waits for that stream, also comes
+ * after the call's work on the second stream.
  * No function throws; every function that can fail returns a status code
  * (VIECUT_OK = 0 or a negative VIECUT_E* value). On error no output is
  * written and the library stays usable.

@@ -4119,29 +4119,53 @@ inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 8
 // s wait for the side stream. side_mark records the fork point on s without
 // waiting, for a later side_after_mark. Without a side stream (its creation
 // failed) every call returns s and the work stays in order on s. The streams
-// have the default priority and live until the process ends.
+// have the default priority and live until the process ends; a host thread
+// borrows one per device on first use and gives it back to a shared pool when
+// it exits, so the streams number at most the threads that use the library at
+// once (session workers come and go).
 namespace {
 struct SideStream {
   int dev;
   hipStream_t s2;
   hipEvent_t fork, join;
 };
+std::mutex side_mu;
+std::vector<SideStream> side_pool;
+struct SideLease {
+  std::vector<SideStream> held;
+  ~SideLease() {
+    std::lock_guard<std::mutex> lk(side_mu);
+    for (const auto &e : held)
+      if (e.s2) side_pool.push_back(e);
+  }
+};
 SideStream *side_stream() {
-  thread_local std::vector<SideStream> made;
+  thread_local SideLease lease;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  for (auto &e : made)
+  for (auto &e : lease.held)
     if (e.dev == dev) return e.s2 ? &e : nullptr;
   SideStream e{dev, nullptr, nullptr, nullptr};
-  if (hipStreamCreateWithFlags(&e.s2, hipStreamNonBlocking) != hipSuccess) {
-    e.s2 = nullptr;
-  } else if (hipEventCreateWithFlags(&e.fork, hipEventDisableTiming) != hipSuccess ||
-             hipEventCreateWithFlags(&e.join, hipEventDisableTiming) != hipSuccess) {
-    (void)hipStreamDestroy(e.s2);
-    e.s2 = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(side_mu);
+    for (size_t i = 0; i < side_pool.size(); i++)
+      if (side_pool[i].dev == dev) {
+        e = side_pool[i];
+        side_pool.erase(side_pool.begin() + (int64_t)i);
+        break;
+      }
   }
-  made.push_back(e);
-  return made.back().s2 ? &made.back() : nullptr;
+  if (!e.s2) {
+    if (hipStreamCreateWithFlags(&e.s2, hipStreamNonBlocking) != hipSuccess) {
+      e.s2 = nullptr;
+    } else if (hipEventCreateWithFlags(&e.fork, hipEventDisableTiming) != hipSuccess ||
+               hipEventCreateWithFlags(&e.join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(e.s2);
+      e.s2 = nullptr;
+    }
+  }
+  lease.held.push_back(e);
+  return lease.held.back().s2 ? &lease.held.back() : nullptr;
 }
 hipStream_t side_after_mark(hipStream_t s) {
   SideStream *ss = side_stream();

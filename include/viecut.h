@@ -29,8 +29,9 @@
  * All graph pointers are DEVICE pointers unless stated otherwise. A stream
  * argument is a hipStream_t passed as void* (NULL = the default stream).
  * Passes whose long rows carry much of the work also queue those rows'
- * kernels on a second stream that the library keeps per host thread and
- * device (default priority, created on first use, never destroyed); it is
+ * kernels on a second stream that the calling host thread borrows per device
+ * from a pool the library keeps for the life of the process (default
+ * priority; a thread gives its streams back when it exits); it is
  * ordered after the work already on the caller's stream, and the caller's
  * stream waits for it (events) before the next pass: whatever is queued on
  * the caller's stream after a call, or waits for that stream, also comes
